@@ -1,0 +1,795 @@
+/*
+ * Plain FP64 CPU oracle for local approximate GP prediction with greedy
+ * local designs (Gramacy & Haaland, "Speeding up neighborhood search in
+ * local Gaussian process prediction").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker for the HIP library:
+ * only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header or constant with the
+ * GPU path.  Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC.
+ *
+ * What it computes, per predictive location x (all FP64):
+ *   O1 kernel      K(a,b) = exp(-sum_k (a_k-b_k)^2 / d_k)           (Sec. 2.1)
+ *                  design covariance K_J = [K(x_i,x_l)] + g I         (Sec. 2.1,
+ *                  nugget; Eq. alc uses K_eta on the diagonal)
+ *   O2 candidates  the N' design rows nearest to x, ordered by
+ *                  (squared distance, row index)                      (Sec. 2.2)
+ *   O3 start       J = the n0 nearest; K_J^{-1} via Cholesky          (Sec. 2.2)
+ *   O4 greedy step for j = n0..n-1 add the candidate that maximises the
+ *                  integrand of Eq. alc (reduction in variance at x), found
+ *                  by exhaustive scoring of C \ J or by ray search     (Sec. 3.1,
+ *                  Sec. 4)
+ *   O5 update      partitioned inverse: K_{j+1}^{-1} from K_j^{-1} with
+ *                  G_j = g_j g_j^T, g_j = -K_j^{-1} k_j(x_{j+1}) / v_j  (Sec. 3.1,
+ *                  the quantities under Eq. alc, sign of g_j corrected)
+ *   O6 predict     Student-t mean and scale with n degrees of freedom (Eqs.
+ *                  predgp and preds2 with N -> n)                     (Sec. 2.1)
+ *
+ * Rounding is defined, not left to the compiler, so that another
+ * implementation can reproduce every value here bit for bit: squared
+ * distances and every inner product accumulate their terms in index order
+ * from 0.0 with one fused multiply-add per term; exp is the routine oexp
+ * below (Cody-Waite reduction, Taylor series of degree 13); division and
+ * square root are IEEE; nothing else is fused (-ffp-contract=off).
+ *
+ * Readings where the paper is silent or garbled (each listed in the design
+ * notes of the repository): ties in distance, ALC,
+ * ray value and snap distance go to the smaller candidate rank (or row index
+ * for the nearest-neighbour order); g_j carries a minus sign so that the
+ * integrand of Eq. alc equals (K(x_c,x) - k_c^T K^{-1} k_x)^2 / v_c, the
+ * squared posterior covariance over the posterior variance; the prior
+ * variance at a candidate, at a point on a ray and at x is 1 + g; v_c <= 0
+ * scores 0 and raises a status flag; Brent's tolerance defaults to
+ * 2^-13 = eps^(1/4) and its iteration budget to 100.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_NDIAG 8
+#define ORC_STATUS_VNONPOS 1   /* some v_c <= 0 was scored as 0 */
+#define ORC_STATUS_NONFINITE 2 /* non-finite prediction */
+#define ORC_STATUS_NOTPD 4     /* starting K_J not positive definite */
+#define ORC_STATUS_BADRAY 8    /* too few remaining candidates for the rays */
+
+/* ---------------------------------------------------------------- O1 ---- */
+
+/* Squared Euclidean distance, dimensions accumulated in order with one fused
+ * multiply-add each: s <- fma(t_k, t_k, s), t_k = a_k - b_k. */
+static double sqdist(const double *a, const double *b, int p)
+{
+    double s = 0.0;
+    for (int k = 0; k < p; k++) {
+        double t = a[k] - b[k];
+        s = fma(t, t, s);
+    }
+    return s;
+}
+
+/* exp(x): write x = k ln2 + r with k = nearest integer to x/ln2 and
+ * |r| <= ln2/2 (Cody & Waite's reduction, ln2 split into the nearest double
+ * and its remainder, each step one fused multiply-add), sum the Taylor series
+ * of exp(r) to degree 13 by Horner's rule with fused multiply-adds (the
+ * truncation error r^14/14! is below 1e-17), then scale by 2^k.  Results
+ * that would be subnormal (x < -708) are flushed to 0; every argument used
+ * here is <= 0. */
+static double oexp(double x)
+{
+    if (x != x) return x;
+    if (x < -708.0) return 0.0;
+    if (x > 709.0) return INFINITY;
+    const double ln2_hi = 0.6931471805599453;      /* 0x1.62e42fefa39efp-1 */
+    const double ln2_lo = 2.3190468138462996e-17;  /* ln2 - ln2_hi */
+    const double inv_ln2 = 1.4426950408889634;     /* 0x1.71547652b82fep+0 */
+    double k = nearbyint(x * inv_ln2);
+    double r = fma(-k, ln2_hi, x);
+    r = fma(-k, ln2_lo, r);
+    double q = 1.0 / 6227020800.0;                 /* 1/13! */
+    q = fma(q, r, 1.0 / 479001600.0);              /* 1/12! */
+    q = fma(q, r, 1.0 / 39916800.0);
+    q = fma(q, r, 1.0 / 3628800.0);
+    q = fma(q, r, 1.0 / 362880.0);
+    q = fma(q, r, 1.0 / 40320.0);
+    q = fma(q, r, 1.0 / 5040.0);
+    q = fma(q, r, 1.0 / 720.0);
+    q = fma(q, r, 1.0 / 120.0);
+    q = fma(q, r, 1.0 / 24.0);
+    q = fma(q, r, 1.0 / 6.0);
+    q = fma(q, r, 0.5);
+    q = fma(q, r, 1.0);
+    q = fma(q, r, 1.0);
+    return ldexp(q, (int)k);
+}
+
+/* Gaussian correlation, Sec. 2.1: isotropic exp(-r^2/d) when d_len == 1,
+ * separable exp(-sum_k (a_k-b_k)^2/d_k) otherwise.  No nugget here. */
+static double kern(const double *a, const double *b, int p, const double *d, int d_len)
+{
+    if (d_len == 1)
+        return oexp(-(sqdist(a, b, p) / d[0]));
+    double s = 0.0;
+    for (int k = 0; k < p; k++) {
+        double t = a[k] - b[k];
+        s = s + (t * t) / d[k];
+    }
+    return oexp(-s);
+}
+
+/* ---------------------------------------------------------------- O2 ---- */
+
+typedef struct {
+    double d2;
+    int64_t idx;
+} nbr;
+
+/* strict total order: (d2, idx) */
+static int nbr_less(nbr a, nbr b)
+{
+    return a.d2 < b.d2 || (a.d2 == b.d2 && a.idx < b.idx);
+}
+
+static void heap_sift_down(nbr *h, int n, int i)
+{
+    for (;;) {
+        int l = 2 * i + 1, r = l + 1, top = i;
+        if (l < n && nbr_less(h[top], h[l])) top = l;
+        if (r < n && nbr_less(h[top], h[r])) top = r;
+        if (top == i) return;
+        nbr t = h[i]; h[i] = h[top]; h[top] = t;
+        i = top;
+    }
+}
+
+static int nbr_cmp(const void *a, const void *b)
+{
+    nbr x = *(const nbr *)a, y = *(const nbr *)b;
+    return nbr_less(x, y) ? -1 : (nbr_less(y, x) ? 1 : 0);
+}
+
+/* The ncand design rows nearest to x, ascending in (d2, row).  A max-heap of
+ * size ncand keeps the best seen so far; the survivors are then sorted. */
+static void knn_one(const double *X, int64_t N, int p, const double *x, int ncand,
+                    int64_t *idx_out, double *d2_out, nbr *heap)
+{
+    int size = 0;
+    for (int64_t i = 0; i < N; i++) {
+        nbr c = {sqdist(X + i * p, x, p), i};
+        if (size < ncand) {
+            heap[size] = c;
+            for (int k = size++; k > 0;) {
+                int par = (k - 1) / 2;
+                if (!nbr_less(heap[par], heap[k])) break;
+                nbr t = heap[par]; heap[par] = heap[k]; heap[k] = t;
+                k = par;
+            }
+        } else if (nbr_less(c, heap[0])) {
+            heap[0] = c;
+            heap_sift_down(heap, size, 0);
+        }
+    }
+    qsort(heap, size, sizeof(nbr), nbr_cmp);
+    for (int r = 0; r < size; r++) {
+        idx_out[r] = heap[r].idx;
+        if (d2_out) d2_out[r] = heap[r].d2;
+    }
+}
+
+/* ------------------------------------------------------------- linalg --- */
+
+/* Inverse of a small symmetric positive definite matrix A (n x n, row-major)
+ * through its Cholesky factor: A = L L^T, A^{-1} = L^{-T} L^{-1}.
+ * Returns 0 on success, -1 if a pivot is not positive. */
+static int spd_inverse(const double *A, int n, double *Ainv, double *work)
+{
+    double *L = work;             /* n*n */
+    double *Li = work + n * n;    /* n*n, inverse of L (lower) */
+    memset(L, 0, sizeof(double) * n * n);
+    for (int i = 0; i < n; i++) {
+        for (int k = 0; k <= i; k++) {
+            double s = A[i * n + k];
+            for (int m = 0; m < k; m++) s = fma(-L[i * n + m], L[k * n + m], s);
+            if (i == k) {
+                if (!(s > 0.0)) return -1;
+                L[i * n + i] = sqrt(s);
+            } else {
+                L[i * n + k] = s / L[k * n + k];
+            }
+        }
+    }
+    memset(Li, 0, sizeof(double) * n * n);
+    for (int c = 0; c < n; c++) {            /* solve L Li[:,c] = e_c */
+        for (int i = c; i < n; i++) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int m = c; m < i; m++) s = fma(-L[i * n + m], Li[m * n + c], s);
+            Li[i * n + c] = s / L[i * n + i];
+        }
+    }
+    for (int i = 0; i < n; i++)              /* Ainv = Li^T Li */
+        for (int k = 0; k < n; k++) {
+            double s = 0.0;
+            for (int m = (i > k ? i : k); m < n; m++) s = fma(Li[m * n + i], Li[m * n + k], s);
+            Ainv[i * n + k] = s;
+        }
+    return 0;
+}
+
+/* y = A x, A is j x j with leading dimension ld */
+static void matvec(const double *A, int ld, int j, const double *x, double *y)
+{
+    for (int i = 0; i < j; i++) {
+        double s = 0.0;
+        for (int k = 0; k < j; k++) s = fma(A[i * ld + k], x[k], s);
+        y[i] = s;
+    }
+}
+
+static double dot(const double *a, const double *b, int j)
+{
+    double s = 0.0;
+    for (int i = 0; i < j; i++) s = fma(a[i], b[i], s);
+    return s;
+}
+
+/* ------------------------------------------------------ per location ---- */
+
+typedef struct {
+    const double *X, *y;
+    int64_t N;
+    int p;
+    int n0, n, ncand, search, numrays;
+    const double *d;
+    int d_len;
+    double g;
+    int brent_maxit;
+    double brent_tol;
+    const double *lo, *hi; /* bounding box of the whole design */
+} ctx_t;
+
+typedef struct {
+    /* per location scratch */
+    nbr *heap;
+    int64_t *cand;       /* ncand row ids, nearest first */
+    double *cand_d2;
+    double *Kc;          /* n x ncand: K(x_{J_i}, x_c) for every candidate c */
+    double *kxc;         /* ncand: K(x_c, x) */
+    double *Ki;          /* n x n, leading dimension n */
+    double *kx, *h, *w, *gv, *kz, *tmp;
+    int *J;              /* ranks of the selected candidates */
+    char *inJ;           /* ncand flags */
+    char *forbid;        /* ncand flags (ray starts) */
+} scratch_t;
+
+/* Continuous-point ALC for ray search (Eq. alc integrand at z, Sec. 4):
+ * (K(z,x) - k_J(z)^T K^{-1} k_J(x))^2 / ((1+g) - k_J(z)^T K^{-1} k_J(z)). */
+typedef struct {
+    const ctx_t *c;
+    scratch_t *s;
+    const double *x;
+    int j;
+    const double *a, *dir; /* segment p(s) = a + s * dir */
+    double *z;
+    int vflag;
+} rayfn_t;
+
+static double alc_at(const ctx_t *c, scratch_t *s, const double *x, int j, const double *z, int *vflag)
+{
+    for (int i = 0; i < j; i++)
+        s->kz[i] = kern(c->X + s->cand[s->J[i]] * c->p, z, c->p, c->d, c->d_len);
+    matvec(s->Ki, c->n, j, s->kz, s->w);
+    double v = (1.0 + c->g) - dot(s->kz, s->w, j);
+    double cov = kern(z, x, c->p, c->d, c->d_len) - dot(s->w, s->kx, j);
+    if (!(v > 0.0)) {
+        *vflag = 1;
+        return 0.0;
+    }
+    return cov * cov / v;
+}
+
+static double ray_negalc(double t, void *vp)
+{
+    rayfn_t *r = (rayfn_t *)vp;
+    for (int k = 0; k < r->c->p; k++) r->z[k] = fma(t, r->dir[k], r->a[k]);
+    return -alc_at(r->c, r->s, r->x, r->j, r->z, &r->vflag);
+}
+
+/* relative gap of a comparison: |a-b| / max(|a|,|b|).  Two exact zeros are
+ * not a near-tie (they come out of underflowed kernels on any machine). */
+static double relgap(double a, double b)
+{
+    double m = fmax(fabs(a), fabs(b));
+    if (m == 0.0) return INFINITY;
+    return fabs(a - b) / m;
+}
+
+/*
+ * Brent's (1973) derivative-free minimiser of a function on [lo, hi]: golden
+ * section search, replaced by a parabolic step through the three best points
+ * whenever that step falls inside the bracket and is shorter than half the
+ * step before last; no evaluation closer than tol1 = sqrt(eps)|x| + tol/3
+ * to the current best point; stop once the bracket half-width about the
+ * best point is within 2 tol1 (Sec. 4 names this routine, Brent_fmin).
+ * *mingap (if given) receives the smallest relative gap among the decisions
+ * the iteration took, so callers can tell near-tie steps apart.
+ */
+double orc_brent_min(double (*f)(double, void *), void *arg, double lo, double hi, double tol,
+                     int maxit, int *nevals, double *mingap, double *fbest)
+{
+    const double gold = 0.5 * (3.0 - sqrt(5.0));
+    const double sqeps = sqrt(DBL_EPSILON);
+    double a = lo, b = hi;
+    double x = a + gold * (b - a);
+    double w = x, v = x;
+    double fx = f(x, arg);
+    double fw = fx, fv = fx;
+    double step = 0.0, prev = 0.0; /* last step and the one before it */
+    double gap = INFINITY;
+    int evals = 1;
+
+    for (int it = 0; it < maxit; it++) {
+        double mid = 0.5 * (a + b);
+        double tol1 = sqeps * fabs(x) + tol / 3.0;
+        double tol2 = 2.0 * tol1;
+        double lhs = fabs(x - mid), rhs = tol2 - 0.5 * (b - a);
+        gap = fmin(gap, relgap(lhs, rhs));
+        if (lhs <= rhs) break;
+
+        int parabolic = 0;
+        if (fabs(prev) > tol1) {
+            /* parabola through (x,fx), (w,fw), (v,fv): step = num/den */
+            double r = (x - w) * (fx - fv);
+            double q = (x - v) * (fx - fw);
+            double num = (x - v) * q - (x - w) * r;
+            double den = 2.0 * (q - r);
+            if (den > 0.0) num = -num;
+            den = fabs(den);
+            double older = prev;
+            prev = step;
+            double half = fabs(0.5 * den * older);
+            gap = fmin(gap, relgap(fabs(num), half));
+            gap = fmin(gap, relgap(num, den * (a - x)));
+            gap = fmin(gap, relgap(num, den * (b - x)));
+            if (fabs(num) < half && num > den * (a - x) && num < den * (b - x)) {
+                step = num / den;
+                double u = x + step;
+                if (u - a < tol2 || b - u < tol2) step = (mid - x >= 0.0) ? tol1 : -tol1;
+                parabolic = 1;
+            }
+        }
+        if (!parabolic) {
+            prev = (x >= mid) ? a - x : b - x;
+            step = gold * prev;
+        }
+        double u = (fabs(step) >= tol1) ? x + step : x + ((step >= 0.0) ? tol1 : -tol1);
+        double fu = f(u, arg);
+        evals++;
+        gap = fmin(gap, relgap(fu, fx));
+        if (fu <= fx) {
+            if (u >= x) a = x; else b = x;
+            v = w; fv = fw;
+            w = x; fw = fx;
+            x = u; fx = fu;
+        } else {
+            if (u < x) a = u; else b = u;
+            gap = fmin(gap, relgap(fu, fw));
+            if (fu <= fw || w == x) {
+                v = w; fv = fw;
+                w = u; fw = fu;
+            } else {
+                gap = fmin(gap, relgap(fu, fv));
+                if (fu <= fv || v == x || v == w) {
+                    v = u; fv = fu;
+                }
+            }
+        }
+    }
+    if (nevals) *nevals = evals;
+    if (mingap) *mingap = gap;
+    if (fbest) *fbest = fx;
+    return x;
+}
+
+/* Round-robin start of the ray sequence, Sec. 4: k = t mod floor(sqrt(t)),
+ * t = j - n0 + 1 (0-based rank among the remaining candidates). */
+int orc_ray_k0(int t)
+{
+    int r = 0;
+    while ((r + 1) * (r + 1) <= t) r++;
+    return r > 0 ? t % r : 0;
+}
+
+/* Segment of a ray, Sec. 4: from start a, directed away from x, of length
+ * ten times |a - x|, cut at the bounding box [lo, hi] of the design.
+ * dir receives e - a for the clipped end e; returns the cut fraction tau. */
+double orc_ray_segment(const double *a, const double *x, const double *lo, const double *hi, int p,
+                       double *dir)
+{
+    double tau = 1.0;
+    for (int k = 0; k < p; k++) {
+        double dk = 10.0 * (a[k] - x[k]);
+        dir[k] = dk;
+        if (dk > 0.0) tau = fmin(tau, (hi[k] - a[k]) / dk);
+        else if (dk < 0.0) tau = fmin(tau, (lo[k] - a[k]) / dk);
+    }
+    if (tau < 0.0) tau = 0.0;
+    for (int k = 0; k < p; k++) dir[k] = tau * dir[k];
+    return tau;
+}
+
+/* One location: local design, then prediction.  forced (nullable) gives a
+ * selection sequence (design row ids, n entries) to follow instead of the
+ * oracle's own choices; the oracle's own choice is still recorded per step.
+ * diag (nullable): per greedy step ORC_NDIAG values
+ *   [0] oracle's choice (row id)      [1] best score (ALC_1)
+ *   [2] runner-up score (ALC_2)       [3] ALC of the candidate actually added
+ *   [4] smallest relative decision gap [5] Brent evaluations (ray)
+ *   [6] b_j = (1+g) - k_x^T K_j^{-1} k_x before the step
+ *   [7] ray search: s* of the winning ray (0 when its start was taken)
+ * trace_alc (nullable): (n-n0) x ncand ALC of every candidate (NaN if in J)
+ * trace_Ki (nullable): final n x n inverse.
+ */
+static int local_one(const ctx_t *c, scratch_t *s, const double *x, const int32_t *forced,
+                     double *mean, double *s2, double *df, int32_t *sel, double *diag,
+                     double *trace_alc, double *trace_Ki)
+{
+    const int p = c->p, n = c->n, nc = c->ncand;
+    const double *X = c->X;
+    int status = 0;
+    int n0 = (c->search == 2) ? n : c->n0; /* nearest-neighbour mode: J = n nearest */
+
+    knn_one(X, c->N, p, x, nc, s->cand, s->cand_d2, s->heap);
+    memset(s->inJ, 0, nc);
+    for (int q = 0; q < nc; q++) s->kxc[q] = kern(X + s->cand[q] * p, x, p, c->d, c->d_len);
+
+    /* O3: J = the n0 nearest */
+    for (int i = 0; i < n0; i++) {
+        s->J[i] = i;
+        s->inJ[i] = 1;
+        const double *xi = X + s->cand[i] * p;
+        for (int q = 0; q < nc; q++) s->Kc[(size_t)i * nc + q] = kern(xi, X + s->cand[q] * p, p, c->d, c->d_len);
+    }
+    {
+        double *A = s->tmp;                       /* n0 x n0 */
+        double *work = s->tmp + (size_t)n * n;    /* 2 n0 n0 */
+        double *Ai = s->tmp + (size_t)3 * n * n;
+        for (int i = 0; i < n0; i++)
+            for (int k = 0; k < n0; k++) A[i * n0 + k] = s->Kc[(size_t)i * nc + k] + (i == k ? c->g : 0.0);
+        if (spd_inverse(A, n0, Ai, work) != 0) status |= ORC_STATUS_NOTPD;
+        for (int i = 0; i < n0; i++)
+            for (int k = 0; k < n0; k++) s->Ki[i * n + k] = Ai[i * n0 + k];
+    }
+    for (int i = 0; i < n0; i++) s->kx[i] = s->kxc[i];
+
+    /* O4 / O5: greedy growth */
+    for (int j = n0; j < n; j++) {
+        double *dg = diag ? diag + (size_t)(j - n0) * ORC_NDIAG : NULL;
+        matvec(s->Ki, n, j, s->kx, s->h);                 /* h = K^{-1} k_x */
+        double bj = (1.0 + c->g) - dot(s->kx, s->h, j);
+        int best = -1;
+        double alc1 = -INFINITY, alc2 = -INFINITY, gap = INFINITY, swin = 0.0;
+        int evals = 0;
+
+        if (c->search == 0 || trace_alc) {
+            /* exhaustive scoring of every remaining candidate, rank order */
+            for (int q = 0; q < nc; q++) {
+                if (trace_alc) trace_alc[(size_t)(j - n0) * nc + q] = NAN;
+                if (s->inJ[q]) continue;
+                for (int i = 0; i < j; i++) s->kz[i] = s->Kc[(size_t)i * nc + q];
+                matvec(s->Ki, n, j, s->kz, s->w);                      /* w = K^{-1} k_c */
+                double v = (1.0 + c->g) - dot(s->kz, s->w, j);
+                double cov = s->kxc[q] - dot(s->w, s->kx, j);
+                double a;
+                if (v > 0.0) a = cov * cov / v;
+                else { a = 0.0; status |= ORC_STATUS_VNONPOS; }
+                if (trace_alc) trace_alc[(size_t)(j - n0) * nc + q] = a;
+                if (c->search != 0) continue;
+                if (a > alc1) { alc2 = alc1; alc1 = a; best = q; }
+                else if (a > alc2) alc2 = a;
+            }
+            if (c->search == 0) gap = (alc1 > 0.0) ? (alc1 - alc2) / alc1 : 0.0;
+        }
+        if (c->search == 1) {
+            /* ray search, Sec. 4 */
+            int R = c->numrays > 0 ? c->numrays : p;
+            int t = j - n0 + 1, k0 = orc_ray_k0(t);
+            int starts[64];
+            int got = 0, seen = 0;
+            memset(s->forbid, 0, nc);
+            for (int q = 0; q < nc && got < R; q++) {
+                if (s->inJ[q]) continue;
+                if (seen++ >= k0) { starts[got++] = q; s->forbid[q] = 1; }
+            }
+            if (got < R) { status |= ORC_STATUS_BADRAY; R = got; }
+            double bestval = -INFINITY, secondval = -INFINITY, bests = 0.0;
+            int bestr = -1;
+            double dirs[64 * 16], zs[16], bestz[16];
+            for (int r = 0; r < R; r++) {
+                const double *a = X + s->cand[starts[r]] * p;
+                double *dir = dirs + r * p;
+                double tau = orc_ray_segment(a, x, c->lo, c->hi, p, dir);
+                rayfn_t fn = {c, s, x, j, a, dir, zs, 0};
+                double sstar = 0.0, val;
+                int vflag = 0;
+                double a0 = alc_at(c, s, x, j, a, &vflag);
+                if (tau > 0.0) {
+                    int ne = 0;
+                    double bg = INFINITY, fb = 0.0;
+                    sstar = orc_brent_min(ray_negalc, &fn, 0.0, 1.0, c->brent_tol, c->brent_maxit, &ne, &bg, &fb);
+                    evals += ne;
+                    gap = fmin(gap, bg);
+                    val = -fb;
+                    gap = fmin(gap, relgap(a0, val));
+                    if (a0 >= val) { sstar = 0.0; val = a0; } /* s = 0 post-check */
+                } else {
+                    val = a0;
+                }
+                if (fn.vflag || vflag) status |= ORC_STATUS_VNONPOS;
+                if (val > bestval) {
+                    secondval = bestval; bestval = val; bestr = r; bests = sstar;
+                } else if (val > secondval) secondval = val;
+            }
+            if (R > 1) gap = fmin(gap, relgap(bestval, secondval));
+            alc1 = bestval;
+            alc2 = secondval;
+            swin = bests;
+            if (bests == 0.0) {
+                best = starts[bestr];
+            } else {
+                /* snap the continuous optimum to the nearest allowed candidate */
+                const double *a = X + s->cand[starts[bestr]] * p;
+                const double *dir = dirs + bestr * p;
+                for (int k = 0; k < p; k++) bestz[k] = fma(bests, dir[k], a[k]);
+                double dbest = INFINITY, dsec = INFINITY;
+                for (int q = 0; q < nc; q++) {
+                    if (s->inJ[q] || s->forbid[q]) continue;
+                    double dq = sqdist(X + s->cand[q] * p, bestz, p);
+                    if (dq < dbest) { dsec = dbest; dbest = dq; best = q; }
+                    else if (dq < dsec) dsec = dq;
+                }
+                gap = fmin(gap, relgap(dbest, dsec));
+            }
+        }
+        if (c->search == 2) best = -1; /* unreachable: n0 == n */
+
+        /* the candidate actually added */
+        int take = best;
+        if (forced) {
+            take = -1;
+            for (int q = 0; q < nc; q++)
+                if (s->cand[q] == (int64_t)forced[j]) { take = q; break; }
+            if (take < 0 || s->inJ[take]) return -2; /* forced choice not a free candidate */
+        }
+        if (take < 0) return -3;
+
+        /* O5: partitioned-inverse update with the chosen candidate */
+        for (int i = 0; i < j; i++) s->kz[i] = s->Kc[(size_t)i * nc + take];
+        matvec(s->Ki, n, j, s->kz, s->w);
+        double v = (1.0 + c->g) - dot(s->kz, s->w, j);
+        double cov = s->kxc[take] - dot(s->w, s->kx, j);
+        double alc_take = (v > 0.0) ? cov * cov / v : 0.0;
+        if (!(v > 0.0)) status |= ORC_STATUS_VNONPOS;
+        for (int i = 0; i < j; i++) s->gv[i] = -s->w[i] / v;       /* g_j */
+        for (int i = 0; i < j; i++)
+            for (int k = 0; k < j; k++) s->Ki[i * n + k] = fma(s->gv[i] * s->gv[k], v, s->Ki[i * n + k]); /* + G_j v_j */
+        for (int i = 0; i < j; i++) {
+            s->Ki[i * n + j] = s->gv[i];
+            s->Ki[j * n + i] = s->gv[i];
+        }
+        s->Ki[j * n + j] = 1.0 / v;
+
+        if (dg) {
+            dg[0] = (best >= 0) ? (double)s->cand[best] : -1.0;
+            dg[1] = alc1;
+            dg[2] = alc2;
+            dg[3] = alc_take;
+            dg[4] = gap;
+            dg[5] = (double)evals;
+            dg[6] = bj;
+            dg[7] = swin;
+        }
+        s->J[j] = take;
+        s->inJ[take] = 1;
+        s->kx[j] = s->kxc[take];
+        const double *xt = X + s->cand[take] * p;
+        for (int q = 0; q < nc; q++) s->Kc[(size_t)j * nc + q] = kern(xt, X + s->cand[q] * p, p, c->d, c->d_len);
+    }
+
+    /* O6: prediction with the local design of size n */
+    {
+        double *yJ = s->tmp;
+        for (int i = 0; i < n; i++) yJ[i] = c->y[s->cand[s->J[i]]];
+        matvec(s->Ki, n, n, s->kx, s->h);
+        double mu = dot(s->h, yJ, n);
+        matvec(s->Ki, n, n, yJ, s->w);
+        double psi = dot(yJ, s->w, n);
+        double sc = psi * ((1.0 + c->g) - dot(s->kx, s->h, n)) / (double)n;
+        *mean = mu;
+        *s2 = sc;
+        *df = (double)n;
+        if (!isfinite(mu) || !isfinite(sc)) status |= ORC_STATUS_NONFINITE;
+    }
+    if (sel)
+        for (int i = 0; i < n; i++) sel[i] = (int32_t)s->cand[s->J[i]];
+    if (trace_Ki) memcpy(trace_Ki, s->Ki, sizeof(double) * n * n);
+    return status;
+}
+
+static int scratch_alloc(scratch_t *s, int n, int ncand)
+{
+    memset(s, 0, sizeof(*s));
+    s->heap = malloc(sizeof(nbr) * ncand);
+    s->cand = malloc(sizeof(int64_t) * ncand);
+    s->cand_d2 = malloc(sizeof(double) * ncand);
+    s->Kc = malloc(sizeof(double) * (size_t)n * ncand);
+    s->kxc = malloc(sizeof(double) * ncand);
+    s->Ki = calloc((size_t)n * n, sizeof(double));
+    s->kx = malloc(sizeof(double) * n);
+    s->h = malloc(sizeof(double) * n);
+    s->w = malloc(sizeof(double) * n);
+    s->gv = malloc(sizeof(double) * n);
+    s->kz = malloc(sizeof(double) * n);
+    s->tmp = malloc(sizeof(double) * (size_t)4 * n * n + 16);
+    s->J = malloc(sizeof(int) * n);
+    s->inJ = malloc(ncand);
+    s->forbid = malloc(ncand);
+    return (s->heap && s->cand && s->cand_d2 && s->Kc && s->kxc && s->Ki && s->kx && s->h && s->w &&
+            s->gv && s->kz && s->tmp && s->J && s->inJ && s->forbid) ? 0 : -1;
+}
+
+static void scratch_free(scratch_t *s)
+{
+    free(s->heap); free(s->cand); free(s->cand_d2); free(s->Kc); free(s->kxc); free(s->Ki);
+    free(s->kx); free(s->h); free(s->w); free(s->gv); free(s->kz); free(s->tmp); free(s->J);
+    free(s->inJ); free(s->forbid);
+}
+
+static int check_args(int64_t N, int p, int n0, int n, int ncand, int search, int numrays, const double *d,
+                      int d_len, double g)
+{
+    if (N < 1 || p < 1 || p > 16) return -1;
+    if (n0 < 1 || n < n0 || ncand < n || (int64_t)ncand > N) return -1;
+    if (search < 0 || search > 2) return -1;
+    if (search == 1 && (numrays > 64)) return -1;
+    if (!(d_len == 1 || d_len == p)) return -1;
+    for (int k = 0; k < d_len; k++)
+        if (!(d[k] > 0.0)) return -1;
+    if (!(g >= 0.0)) return -1;
+    return 0;
+}
+
+/* bounding box of the whole design */
+static void bbox(const double *X, int64_t N, int p, double *lo, double *hi)
+{
+    for (int k = 0; k < p; k++) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+    for (int64_t i = 0; i < N; i++)
+        for (int k = 0; k < p; k++) {
+            double v = X[i * p + k];
+            if (v < lo[k]) lo[k] = v;
+            if (v > hi[k]) hi[k] = v;
+        }
+}
+
+/* ------------------------------------------------------------ exports --- */
+
+/* Nearest candidates for M locations: idx (M x ncand row ids), d2 (M x ncand). */
+int orc_knn(const double *X, int64_t N, int p, const double *XX, int64_t M, int ncand, int64_t *idx,
+            double *d2, int nthreads)
+{
+    if (N < 1 || p < 1 || ncand < 1 || (int64_t)ncand > N || M < 0) return -1;
+    int err = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        nbr *heap = malloc(sizeof(nbr) * ncand);
+        if (!heap) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(dynamic)
+        for (int64_t m = 0; m < M; m++)
+            if (heap) knn_one(X, N, p, XX + m * p, ncand, idx + m * ncand, d2 ? d2 + m * ncand : NULL, heap);
+        free(heap);
+    }
+    return err;
+}
+
+/* Local GP prediction for M locations (OpenMP over locations, Sec. 5).
+ * forced (nullable, M x n): follow these selections (replay).
+ * Outputs mean/s2/df (M), sel (nullable, M x n), diag (nullable,
+ * M x (n-n0) x ORC_NDIAG), status (M).  Returns 0, or -1 on bad arguments,
+ * -2 on allocation failure. */
+int orc_predict(const double *X, const double *y, int64_t N, int p, const double *XX, int64_t M, int n0,
+                int n, int ncand, int search, int numrays, const double *d, int d_len, double g,
+                int brent_maxit, double brent_tol, const int32_t *forced, int nthreads, double *mean,
+                double *s2, double *df, int32_t *sel, double *diag, int32_t *status)
+{
+    if (check_args(N, p, n0, n, ncand, search, numrays, d, d_len, g) != 0 || M < 0) return -1;
+    double lo[16], hi[16];
+    bbox(X, N, p, lo, hi);
+    ctx_t c = {X, y, N, p, n0, n, ncand, search, numrays, d, d_len, g,
+               brent_maxit > 0 ? brent_maxit : 100, brent_tol > 0.0 ? brent_tol : ldexp(1.0, -13), lo, hi};
+    int nd = (search == 2) ? 0 : n - n0;
+    int err = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        scratch_t s;
+        int ok = scratch_alloc(&s, n, ncand) == 0;
+        if (!ok) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(dynamic)
+        for (int64_t m = 0; m < M; m++) {
+            if (!ok) continue;
+            int st = local_one(&c, &s, XX + m * p, forced ? forced + m * n : NULL, mean + m, s2 + m, df + m,
+                               sel ? sel + m * n : NULL, diag ? diag + (size_t)m * nd * ORC_NDIAG : NULL,
+                               NULL, NULL);
+            if (st < 0) {
+#pragma omp atomic write
+                err = st;
+                st = 0x100;
+            }
+            if (status) status[m] = st;
+        }
+        scratch_free(&s);
+    }
+    return err;
+}
+
+/* One location with full traces for the brute-force checks: ALC of every
+ * candidate at every step (exhaustive scoring is run in every search mode),
+ * the final inverse, the candidate list and the per-step diagnostics. */
+int orc_trace(const double *X, const double *y, int64_t N, int p, const double *x, int n0, int n, int ncand,
+              int search, int numrays, const double *d, int d_len, double g, int brent_maxit,
+              double brent_tol, const int32_t *forced, double *mean, double *s2, double *df, int32_t *sel,
+              double *diag, double *trace_alc, double *trace_Ki, int64_t *cand)
+{
+    if (check_args(N, p, n0, n, ncand, search, numrays, d, d_len, g) != 0) return -1;
+    double lo[16], hi[16];
+    bbox(X, N, p, lo, hi);
+    ctx_t c = {X, y, N, p, n0, n, ncand, search, numrays, d, d_len, g,
+               brent_maxit > 0 ? brent_maxit : 100, brent_tol > 0.0 ? brent_tol : ldexp(1.0, -13), lo, hi};
+    scratch_t s;
+    if (scratch_alloc(&s, n, ncand) != 0) return -2;
+    int st = local_one(&c, &s, x, forced, mean, s2, df, sel, diag, trace_alc, trace_Ki);
+    if (cand) memcpy(cand, s.cand, sizeof(int64_t) * ncand);
+    scratch_free(&s);
+    return st;
+}
+
+/* Exported for direct checks of the pieces. */
+double orc_exp(double x)
+{
+    return oexp(x);
+}
+
+double orc_kern(const double *a, const double *b, int p, const double *d, int d_len)
+{
+    return kern(a, b, p, d, d_len);
+}
+
+double orc_sqdist(const double *a, const double *b, int p)
+{
+    return sqdist(a, b, p);
+}
+
+int orc_spd_inverse(const double *A, int n, double *Ainv)
+{
+    double *work = malloc(sizeof(double) * 2 * n * n);
+    if (!work) return -2;
+    int r = spd_inverse(A, n, Ainv, work);
+    free(work);
+    return r;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,197 @@
+"""Seeded synthetic workloads for local approximate GP prediction.
+
+This module only draws inputs: design X (N x p), responses y (N), predictive
+set XX (M x p) and the fixed method parameters of each workload.  It holds
+none of the method's arithmetic, so both the CPU oracle and the HIP path read
+the very same arrays from here.
+
+The paper's own data (borehole, LGBB, Zhou, piston) are not reproduced; the
+workloads below are synthetic stand-ins with the shapes the paper uses in its
+experiments (Sec. 5: p = 2 and p = 8, N up to 1e6, n = 50, N' = 1000 nearest
+candidates, a predictive set of 1e4 locations).
+
+Seeds: numpy ``default_rng(14090074 + 100 * cfg + stream)`` with stream 0 for
+the design, 1 for the predictive set and 2 for request arrivals.  The ray
+workload reuses the design and predictive set of the exhaustive 8-d one.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+SEED_BASE = 14090074
+
+SEARCH_EXHAUSTIVE = 0
+SEARCH_RAY = 1
+SEARCH_NN = 2
+
+PREC_FP64 = 0
+PREC_MIXED = 1
+
+
+@dataclasses.dataclass
+class Params:
+    """Method knobs, laGP-style (Sec. 2.2 and Sec. 5 of the paper).
+
+    n0: size of the nearest-neighbour starting design; n: final local design
+    size; ncand: N', the number of nearest candidates searched; search: one of
+    SEARCH_*; numrays: rays per greedy step (ray search); d: lengthscale(s),
+    one value (isotropic) or p values (separable); g: nugget; precision:
+    PREC_FP64 or PREC_MIXED; rescore_k: FP64 re-scored shortlist in the mixed
+    form; brent_maxit / brent_tol: the line-search budget and tolerance.
+    """
+
+    n0: int = 6
+    n: int = 50
+    ncand: int = 1000
+    search: int = SEARCH_EXHAUSTIVE
+    numrays: int = 0
+    d: tuple = (0.1,)
+    g: float = 1e-6
+    precision: int = PREC_FP64
+    rescore_k: int = 16
+    brent_maxit: int = 100
+    brent_tol: float = 2.0 ** -13
+
+    def replace(self, **kw) -> "Params":
+        return dataclasses.replace(self, **kw)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    X: np.ndarray
+    y: np.ndarray
+    XX: np.ndarray
+    params: Params
+    truth: np.ndarray | None = None  # noise-free response at XX, for RMSE
+
+
+def _rng(cfg: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(SEED_BASE + 100 * cfg + stream)
+
+
+def f_bump2(X: np.ndarray) -> np.ndarray:
+    """2-d response: exp(-((x1-.5)^2+(x2-.5)^2)/0.08) sin(6 x1) + 0.3 cos(5 x2)."""
+    x1, x2 = X[:, 0], X[:, 1]
+    return np.exp(-((x1 - 0.5) ** 2 + (x2 - 0.5) ** 2) / 0.08) * np.sin(6.0 * x1) + 0.3 * np.cos(5.0 * x2)
+
+
+def f_sines8(X: np.ndarray) -> np.ndarray:
+    """8-d response: sum_j sin(2 pi w_j x_j) + x1 x2 x3, w_j = 0.5 + 0.25 j."""
+    w = 0.5 + 0.25 * np.arange(1, X.shape[1] + 1)
+    return np.sin(2.0 * math.pi * w[None, :] * X).sum(axis=1) + X[:, 0] * X[:, 1] * X[:, 2]
+
+
+def f_mix4(X: np.ndarray) -> np.ndarray:
+    """4-d response: sin(3 x1) cos(2 x2) + x3^2 - 0.5 x4."""
+    return np.sin(3.0 * X[:, 0]) * np.cos(2.0 * X[:, 1]) + X[:, 2] ** 2 - 0.5 * X[:, 3]
+
+
+def grid2(side: int) -> np.ndarray:
+    """Regular side x side grid on [0,1]^2, x = i/(side-1); first axis slowest."""
+    g = np.arange(side, dtype=np.float64) / (side - 1)
+    a, b = np.meshgrid(g, g, indexing="ij")
+    return np.ascontiguousarray(np.stack([a.ravel(), b.ravel()], axis=1))
+
+
+def tiny_2d(M: int | None = None) -> Workload:
+    """N = 4000 iid uniform design on [0,1]^2, 100 uniform predictive locations,
+    d = 0.1, g = 1e-6, n0 = 6, n = 50, exhaustive over the 500 nearest."""
+    X = _rng(0, 0).random((4000, 2))
+    XX = _rng(0, 1).random((100, 2))
+    if M is not None:
+        XX = XX[:M]
+    p = Params(n0=6, n=50, ncand=500, search=SEARCH_EXHAUSTIVE, d=(0.1,), g=1e-6)
+    return Workload("uniform2d_N4000_M100_n50_cand500_exhaustive", X, f_bump2(X), XX, p, f_bump2(XX))
+
+
+def uniform8d(M: int | None = None, N: int = 1_000_000, search: int = SEARCH_EXHAUSTIVE) -> Workload:
+    """N = 1e6 iid uniform design on [0,1]^8, 1e4 uniform predictive locations,
+    separable kernel with d_k = 0.5 in every dimension, g = 1e-6, n0 = 6,
+    n = 50, 1000 nearest candidates; exhaustive, or 10 rays per step."""
+    X = _rng(1, 0).random((N, 8))
+    XX = _rng(1, 1).random((10_000, 8))
+    if M is not None:
+        XX = XX[:M]
+    p = Params(n0=6, n=50, ncand=1000, search=search, numrays=10 if search == SEARCH_RAY else 0,
+               d=(0.5,) * 8, g=1e-6)
+    mode = {SEARCH_EXHAUSTIVE: "exhaustive", SEARCH_RAY: "ray10", SEARCH_NN: "nn"}[search]
+    return Workload(f"uniform8d_N{N}_M{XX.shape[0]}_n50_cand1000_{mode}", X, f_sines8(X), XX, p, f_sines8(XX))
+
+
+def grid2d(M: int | None = None, side: int = 1000, precision: int = PREC_FP64) -> Workload:
+    """1000 x 1000 grid design on [0,1]^2 with the 2-d bump response, 1e5
+    uniform predictive locations, 4000 nearest candidates, n = 100,
+    d = 0.05, g = 1e-6, n0 = 6, exhaustive; FP64 or mixed precision."""
+    X = grid2(side)
+    XX = _rng(3, 1).random((100_000, 2))
+    if M is not None:
+        XX = XX[:M]
+    p = Params(n0=6, n=100, ncand=4000, search=SEARCH_EXHAUSTIVE, d=(0.05,), g=1e-6, precision=precision)
+    tag = "mixed" if precision == PREC_MIXED else "fp64"
+    return Workload(f"grid2d_N{side * side}_M{XX.shape[0]}_n100_cand4000_{tag}", X, f_bump2(X), XX, p, f_bump2(XX))
+
+
+def serving4d(N: int = 2_000_000) -> Workload:
+    """Resident serving design: N = 2e6 iid uniform on [0,1]^4 with the 4-d
+    response; d = 0.1, g = 1e-6, n0 = 6, 4 rays, 1000 nearest candidates.
+    Requests are drawn by ``serving_requests``; XX here is empty."""
+    X = _rng(4, 0).random((N, 4))
+    p = Params(n0=6, n=50, ncand=1000, search=SEARCH_EXHAUSTIVE, numrays=4, d=(0.1,), g=1e-6)
+    return Workload(f"uniform4d_N{N}_serving", X, f_mix4(X), np.zeros((0, 4)), p, None)
+
+
+@dataclasses.dataclass
+class Request:
+    arrival_s: float
+    XX: np.ndarray
+    n: int
+    search: int
+    precision: int
+
+
+def serving_requests(count: int, qps: float, precision_mix: float = 0.0, p: int = 4) -> list[Request]:
+    """Open-loop Poisson arrivals at rate ``qps``; each request carries
+    floor(10**U(0,3)) locations (1..1000, log-uniform), n from {30, 50, 100},
+    exhaustive or ray search at 50/50, and the mixed form with probability
+    ``precision_mix``."""
+    rng = _rng(4, 2)
+    t = 0.0
+    out = []
+    for _ in range(count):
+        t += rng.exponential(1.0 / qps)
+        m = int(np.floor(10.0 ** rng.uniform(0.0, 3.0)))
+        m = max(1, min(1000, m))
+        XX = rng.random((m, p))
+        n = int(rng.choice([30, 50, 100]))
+        search = SEARCH_RAY if rng.random() < 0.5 else SEARCH_EXHAUSTIVE
+        prec = PREC_MIXED if rng.random() < precision_mix else PREC_FP64
+        out.append(Request(t, XX, n, search, prec))
+    return out
+
+
+def small_case(seed: int, N: int, p: int, M: int, **kw) -> Workload:
+    """Small uniform workloads for parity sweeps: design and locations iid
+    uniform on [0,1]^p, the 2-d bump response (p = 2) or the 8-d sines
+    response restricted to p dims otherwise."""
+    rng = np.random.default_rng(SEED_BASE + 7919 * seed)
+    X = rng.random((N, p))
+    XX = rng.random((M, p))
+    if p == 2:
+        y = f_bump2(X)
+    else:
+        y = f_sines8(np.pad(X, ((0, 0), (0, max(0, 3 - p))))) if p < 3 else f_sines8(X)
+    params = Params(**kw)
+    return Workload(f"small_s{seed}_N{N}_p{p}_M{M}", X, y, XX, params, None)
+
+
+WORKLOADS = {
+    "uniform2d_tiny": tiny_2d,
+    "uniform8d_exhaustive": lambda M=None: uniform8d(M, search=SEARCH_EXHAUSTIVE),
+    "uniform8d_ray": lambda M=None: uniform8d(M, search=SEARCH_RAY),
+    "grid2d_fp64": lambda M=None: grid2d(M, precision=PREC_FP64),
+    "grid2d_mixed": lambda M=None: grid2d(M, precision=PREC_MIXED),
+}
