@@ -1,0 +1,203 @@
+/*
+ * lagp.h - C ABI of the MI355X local approximate Gaussian-process library.
+ *
+ * The library predicts, at every location x of a predictive set, with a GP
+ * fitted to a small local design grown greedily from the design X_N
+ * (Gramacy & Haaland, "Speeding up neighborhood search in local Gaussian
+ * process prediction"):
+ *   - candidates: the N' design rows nearest to x (Sec. 2.2, the restriction
+ *     of the search to N' nearest neighbours);
+ *   - start: the n0 nearest rows (Sec. 2.2);
+ *   - greedy steps j = n0 .. n-1 add the candidate maximising the reduction
+ *     in predictive variance at x, the integrand of Eq. (alc) (Sec. 3.1),
+ *     found by exhaustive scoring of the remaining candidates or by the ray
+ *     search of Sec. 4 (rays from x, Brent line search, snap to the nearest
+ *     candidate); the local inverse grows by the partitioned-inverse update
+ *     whose pieces G_j, g_j, v_j appear under Eq. (alc);
+ *   - prediction: the Student-t mean and scale of Eqs. (predgp), (preds2)
+ *     with the n local points in place of N, and n degrees of freedom.
+ * Correlation K(a,b) = exp(-sum_k (a_k-b_k)^2 / d_k) (Sec. 2.1), one d
+ * (isotropic) or one per dimension (separable); nugget g on the design
+ * diagonal and in the prior variance 1 + g at candidates and at x.
+ *
+ * Conventions for every entry point:
+ *   - arrays are row-major; X is N x p, XX is M x p, all FP64;
+ *   - "device" pointers are HIP device memory (hipMalloc, or a torch CUDA
+ *     tensor's data_ptr on ROCm); the caller owns every input and output;
+ *   - stream is a hipStream_t passed as void* (NULL: the default stream);
+ *     work is enqueued on it and outputs are valid once it is synchronised;
+ *   - return codes: LAGP_OK (0) success, LAGP_EINVAL bad argument (checked
+ *     on the host before anything is enqueued), LAGP_ENOMEM allocation
+ *     failure, LAGP_EDEVICE a HIP error, LAGP_EAGAIN a full server queue,
+ *     LAGP_WARN_NUMERIC success but some locations hit a numerical problem
+ *     (their status word is non-zero).  lagp_last_error() gives the text of
+ *     the last failure on the calling thread.  No C++ exception crosses the
+ *     ABI.
+ */
+#ifndef LAGP_H
+#define LAGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LAGP_OK 0
+#define LAGP_EINVAL (-1)
+#define LAGP_ENOMEM (-2)
+#define LAGP_EDEVICE (-3)
+#define LAGP_EAGAIN (-4)
+#define LAGP_WARN_NUMERIC 1
+
+#define LAGP_MAX_DIM 16    /* largest input dimension p */
+#define LAGP_MAX_N 128     /* largest local design size n */
+#define LAGP_MAX_NCAND 4096 /* largest candidate count N' */
+#define LAGP_MAX_RAYS 32   /* largest number of rays per greedy step */
+
+/* search modes */
+#define LAGP_SEARCH_EXHAUSTIVE 0 /* score every remaining candidate (Sec. 3.1) */
+#define LAGP_SEARCH_RAY 1        /* rays + Brent + snap (Sec. 4) */
+#define LAGP_SEARCH_NN 2         /* the n nearest neighbours, no search (Sec. 2.2) */
+
+/* precision forms */
+#define LAGP_PREC_FP64 0      /* everything in FP64, every sum in its defined order (bit-reproducible) */
+#define LAGP_PREC_MIXED 1     /* candidate screening in FP32 on MFMA, shortlist re-scored in FP64 */
+#define LAGP_PREC_FP64_MFMA 2 /* candidate screening in FP64 on MFMA, shortlist re-scored in FP64 */
+
+/* per-location status bits */
+#define LAGP_STATUS_VNONPOS 1   /* a Schur complement v <= 0 was met; scored as 0 */
+#define LAGP_STATUS_NONFINITE 2 /* non-finite mean or scale */
+#define LAGP_STATUS_NOTPD 4     /* the starting n0 x n0 covariance is not positive definite */
+
+typedef struct lagp_design lagp_design;
+typedef struct lagp_server lagp_server;
+
+/* Method parameters (laGP's start, end, close, numrays, d, g, method).
+ *   n0: nearest neighbours in the starting design, 1 <= n0 <= n;
+ *   n: final local design size, n <= LAGP_MAX_N;
+ *   ncand: N', nearest candidates searched, n <= ncand <= min(N, LAGP_MAX_NCAND);
+ *   numrays: rays per greedy step in ray search (<= 0 means p, Sec. 5's
+ *     default); the candidate list must hold n - 1 + numrays + the largest
+ *     round-robin offset (Sec. 4) entries;
+ *   search: LAGP_SEARCH_*; precision: LAGP_PREC_*;
+ *   d_len: 1 (isotropic) or p (separable); d[0..d_len-1] > 0;
+ *   g: nugget >= 0;
+ *   rescore_k: size of the FP64 re-scored shortlist in the mixed form (1..64);
+ *   brent_maxit, brent_tol: Brent line-search budget (<= 0: 100) and
+ *     tolerance (<= 0: 2^-13). */
+typedef struct {
+  int32_t n0;
+  int32_t n;
+  int32_t ncand;
+  int32_t numrays;
+  int32_t search;
+  int32_t precision;
+  int32_t d_len;
+  int32_t rescore_k;
+  double d[LAGP_MAX_DIM];
+  double g;
+  int32_t brent_maxit;
+  int32_t reserved;
+  double brent_tol;
+} lagp_params;
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t lagp_version(void);
+
+/* Text of the last error on the calling thread ("" if none).  The pointer
+ * stays valid until the next failing call on this thread. */
+const char* lagp_last_error(void);
+
+/* Upload a design (Sec. 2.1: the N x p inputs X_N and responses Y_N).
+ * X (N x p) and y (N) are device pointers; the handle keeps its own device
+ * copies and the bounding box of X (used to cut rays, Sec. 4), so the inputs
+ * may be freed once the stream is synchronised.  1 <= p <= LAGP_MAX_DIM,
+ * N >= 1.  *out receives the handle.  The handle is immutable: concurrent
+ * lagp_predict calls on different streams may share it. */
+int32_t lagp_design_create(const double* X, const double* y, int64_t N, int32_t p, void* stream,
+                           lagp_design** out);
+
+/* Release a design handle (NULL is ignored).  Synchronises the device. */
+void lagp_design_destroy(lagp_design* design);
+
+/* Dimensions of a design handle. */
+int32_t lagp_design_info(const lagp_design* design, int64_t* N, int32_t* p);
+
+/* The ncand design rows nearest to each location (Sec. 2.2): for location m,
+ * cand_idx[m*ncand + r] is the row of rank r, ordered by squared distance
+ * then row index, and cand_d2 (nullable) its squared distance (dimensions
+ * summed in order with one fused multiply-add each).  XX (M x p),
+ * cand_idx (M x ncand, int32) and cand_d2 (M x ncand) are device pointers.
+ * 1 <= ncand <= min(N, LAGP_MAX_NCAND); M >= 0 (M == 0 is a no-op). */
+int32_t lagp_candidates(const lagp_design* design, const double* XX, int64_t M, int32_t ncand,
+                        int32_t* cand_idx, double* cand_d2, void* stream);
+
+/* Local approximate GP prediction at the M rows of XX (device, M x p).
+ * Outputs (device): mean, s2 (Student-t scale sigma^2 of Eq. preds2 with n
+ * local points) and df (= n), each of length M; sel_idx (nullable, M x n
+ * int32) the design rows of the local design in selection order; diag
+ * (nullable, M x (n - n0) x 2) per greedy step the best and runner-up
+ * criterion values the search saw (exhaustive: the two largest ALC; ray: the
+ * two best ray optima); status (nullable, M int32) LAGP_STATUS_* bits.
+ * Locations are independent; their results do not depend on M or on which
+ * other locations share the call.  Workspace is allocated on the stream
+ * (stream-ordered) and released on it.  The call is asynchronous: it
+ * returns LAGP_OK once the work is enqueued, and numerical trouble at a
+ * location shows only in its status word. */
+int32_t lagp_predict(const lagp_design* design, const double* XX, int64_t M, const lagp_params* params,
+                     double* mean, double* s2, double* df, int32_t* sel_idx, double* diag, int32_t* status,
+                     void* stream);
+
+/* Local GP prediction from candidate lists already on the device, as
+ * lagp_candidates writes them: cand_idx (M x params->ncand int32, nearest
+ * first).  Everything else as lagp_predict.  Lets a caller keep candidate
+ * lists resident and re-run the design search (another n, search mode or
+ * precision) without repeating the neighbour search. */
+int32_t lagp_predict_candidates(const lagp_design* design, const double* XX, int64_t M, const int32_t* cand_idx,
+                                const lagp_params* params, double* mean, double* s2, double* df, int32_t* sel_idx,
+                                double* diag, int32_t* status, void* stream);
+
+/* ---- serving: continuous batching over a resident design ---------------
+ *
+ * A server owns a worker thread and a device stream.  Requests (host
+ * location arrays plus parameters) are admitted as long as the device
+ * memory they need fits the budget; admitted requests run concurrently on
+ * the device, results stay in server memory until fetched. */
+
+/* Create a server on a design.  hbm_budget_bytes bounds the device memory
+ * the admitted requests may hold at once; max_inflight bounds how many run
+ * together (>= 1). */
+int32_t lagp_server_create(const lagp_design* design, size_t hbm_budget_bytes, int32_t max_inflight,
+                           lagp_server** out);
+
+/* Submit a request: XX_host (M x p, host memory, copied before return),
+ * params as for lagp_predict.  *ticket receives its id.  LAGP_EAGAIN when the
+ * queue of waiting requests is full; LAGP_ENOMEM when the request alone can
+ * never fit the budget. */
+int32_t lagp_server_submit(lagp_server* server, const double* XX_host, int64_t M, const lagp_params* params,
+                           uint64_t* ticket);
+
+/* *done = 1 once the ticket's results are ready on the host, else 0. */
+int32_t lagp_server_poll(lagp_server* server, uint64_t ticket, int32_t* done);
+
+/* Block until the ticket is done, then copy its results into host arrays
+ * (each nullable; mean/s2/df length M, sel_idx M x n, status M) and release
+ * the ticket.  *latency_ms (nullable) receives submit-to-ready time. */
+int32_t lagp_server_fetch(lagp_server* server, uint64_t ticket, double* mean, double* s2, double* df,
+                          int32_t* sel_idx, int32_t* status, double* latency_ms);
+
+/* Latency percentiles over fetched requests and prediction throughput
+ * since creation or the last reset. */
+int32_t lagp_server_stats(lagp_server* server, double* p50_ms, double* p99_ms, double* pred_per_s,
+                          int32_t reset);
+
+/* Drain outstanding work and release the server (NULL is ignored). */
+void lagp_server_destroy(lagp_server* server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAGP_H */

@@ -458,7 +458,15 @@ static int local_one(const ctx_t *c, scratch_t *s, const double *x, const int32_
         double *Ai = s->tmp + (size_t)3 * n * n;
         for (int i = 0; i < n0; i++)
             for (int k = 0; k < n0; k++) A[i * n0 + k] = s->Kc[(size_t)i * nc + k] + (i == k ? c->g : 0.0);
-        if (spd_inverse(A, n0, Ai, work) != 0) status |= ORC_STATUS_NOTPD;
+        if (spd_inverse(A, n0, Ai, work) != 0) {
+            /* the paper is silent here; reading: no prediction for this x */
+            *mean = NAN;
+            *s2 = NAN;
+            *df = (double)n;
+            if (sel)
+                for (int i = 0; i < n; i++) sel[i] = (i < n0) ? (int32_t)s->cand[i] : -1;
+            return ORC_STATUS_NOTPD | ORC_STATUS_NONFINITE;
+        }
         for (int i = 0; i < n0; i++)
             for (int k = 0; k < n0; k++) s->Ki[i * n + k] = Ai[i * n0 + k];
     }

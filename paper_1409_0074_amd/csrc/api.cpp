@@ -1,0 +1,340 @@
+// Host side of the C ABI: argument checks, device workspace, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lagp_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define LAGP_HIP(call)                                                                             \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess) return fail(LAGP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t workspace_budget() {
+  const char* s = std::getenv("LAGP_WORKSPACE_MB");
+  if (s) {
+    const long mb = std::atol(s);
+    if (mb > 0) return (size_t)mb << 20;
+  }
+  return (size_t)4 << 30;
+}
+
+int max_lds_per_block() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+  return v;
+}
+
+// Largest round-robin offset k = t mod floor(sqrt t) over t = 1..steps (Sec. 4).
+int max_ray_offset(int steps) {
+  int best = 0;
+  for (int t = 1; t <= steps; ++t) {
+    int r = 0;
+    while ((r + 1) * (r + 1) <= t) ++r;
+    best = std::max(best, r > 0 ? t % r : 0);
+  }
+  return best;
+}
+
+int32_t check_params(const lagp_design* d, const lagp_params* P, int* rays) {
+  if (!P) return fail(LAGP_EINVAL, "params is NULL");
+  const int p = d->p;
+  if (P->search < LAGP_SEARCH_EXHAUSTIVE || P->search > LAGP_SEARCH_NN)
+    return fail(LAGP_EINVAL, "search must be LAGP_SEARCH_EXHAUSTIVE, _RAY or _NN");
+  if (P->precision != LAGP_PREC_FP64 && P->precision != LAGP_PREC_MIXED && P->precision != LAGP_PREC_FP64_MFMA)
+    return fail(LAGP_EINVAL, "precision must be LAGP_PREC_FP64, LAGP_PREC_MIXED or LAGP_PREC_FP64_MFMA");
+  if (P->precision != LAGP_PREC_FP64 && P->search != LAGP_SEARCH_EXHAUSTIVE)
+    return fail(LAGP_EINVAL, "the screened precision forms apply to exhaustive search only");
+  if (P->precision == LAGP_PREC_MIXED) return fail(LAGP_EINVAL, "the mixed precision form is not built in this library");
+  if (P->n < 1 || P->n > LAGP_MAX_N) return fail(LAGP_EINVAL, "n must be in [1, LAGP_MAX_N]");
+  if (P->search != LAGP_SEARCH_NN && (P->n0 < 1 || P->n0 > P->n)) return fail(LAGP_EINVAL, "n0 must be in [1, n]");
+  if (P->ncand < P->n) return fail(LAGP_EINVAL, "ncand must be >= n");
+  if ((int64_t)P->ncand > d->N) return fail(LAGP_EINVAL, "ncand must be <= N");
+  if (P->ncand > LAGP_MAX_NCAND) return fail(LAGP_EINVAL, "ncand must be <= LAGP_MAX_NCAND");
+  if (!(P->d_len == 1 || P->d_len == p)) return fail(LAGP_EINVAL, "d_len must be 1 or p");
+  for (int k = 0; k < P->d_len; ++k)
+    if (!(P->d[k] > 0.0) || !std::isfinite(P->d[k])) return fail(LAGP_EINVAL, "lengthscales must be finite and > 0");
+  if (!(P->g >= 0.0) || !std::isfinite(P->g)) return fail(LAGP_EINVAL, "nugget g must be finite and >= 0");
+  *rays = 0;
+  if (P->search == LAGP_SEARCH_RAY) {
+    const int R = P->numrays > 0 ? P->numrays : p;
+    if (R > LAGP_MAX_RAYS) return fail(LAGP_EINVAL, "numrays must be <= LAGP_MAX_RAYS");
+    // at step j the starts are remaining ranks k0 .. k0+R-1 with j taken
+    const int need = (P->n - 1) + R + max_ray_offset(P->n - P->n0);
+    if (P->ncand < need)
+      return fail(LAGP_EINVAL, "ncand too small for the ray starts: need n - 1 + numrays + max round-robin offset = " +
+                                   std::to_string(need));
+    if (P->brent_tol < 0.0 || !std::isfinite(P->brent_tol)) return fail(LAGP_EINVAL, "brent_tol must be finite");
+    *rays = R;
+  }
+  return LAGP_OK;
+}
+
+struct Workspace {
+  void* ptr = nullptr;
+  hipStream_t s = nullptr;
+  ~Workspace() {
+    if (ptr) (void)hipFreeAsync(ptr, s);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t lagp_version(void) { return 10000; }
+
+const char* lagp_last_error(void) { return g_err.c_str(); }
+
+int32_t lagp_design_create(const double* X, const double* y, int64_t N, int32_t p, void* stream,
+                           lagp_design** out) {
+  if (!out) return fail(LAGP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!X || !y) return fail(LAGP_EINVAL, "X and y must not be NULL");
+  if (N < 1 || N > INT32_MAX) return fail(LAGP_EINVAL, "N must be in [1, 2^31-1]");
+  if (p < 1 || p > LAGP_MAX_DIM) return fail(LAGP_EINVAL, "p must be in [1, LAGP_MAX_DIM]");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  lagp_design* d = new (std::nothrow) lagp_design();
+  if (!d) return fail(LAGP_ENOMEM, "host allocation failed");
+  d->N = N;
+  d->p = p;
+  if (hipGetDevice(&d->device) != hipSuccess) {
+    delete d;
+    return fail(LAGP_EDEVICE, "hipGetDevice failed");
+  }
+  const size_t xb = sizeof(double) * (size_t)N * p, yb = sizeof(double) * (size_t)N;
+  if (hipMalloc(&d->X, xb) != hipSuccess || hipMalloc(&d->y, yb) != hipSuccess ||
+      hipMalloc(&d->lo, sizeof(double) * p) != hipSuccess || hipMalloc(&d->hi, sizeof(double) * p) != hipSuccess) {
+    lagp_design_destroy(d);
+    return fail(LAGP_ENOMEM, "device allocation of the design failed");
+  }
+  hipError_t e = hipMemcpyAsync(d->X, X, xb, hipMemcpyDefault, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d->y, y, yb, hipMemcpyDefault, s);
+  if (e == hipSuccess) e = lagp::launch_bbox(d->X, N, p, d->lo, d->hi, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    lagp_design_destroy(d);
+    return fail(LAGP_EDEVICE, std::string("design upload: ") + hipGetErrorString(e));
+  }
+  *out = d;
+  return LAGP_OK;
+}
+
+void lagp_design_destroy(lagp_design* d) {
+  if (!d) return;
+  (void)hipDeviceSynchronize();
+  if (d->X) (void)hipFree(d->X);
+  if (d->y) (void)hipFree(d->y);
+  if (d->lo) (void)hipFree(d->lo);
+  if (d->hi) (void)hipFree(d->hi);
+  delete d;
+}
+
+int32_t lagp_design_info(const lagp_design* d, int64_t* N, int32_t* p) {
+  if (!d) return fail(LAGP_EINVAL, "design is NULL");
+  if (N) *N = d->N;
+  if (p) *p = d->p;
+  return LAGP_OK;
+}
+
+int32_t lagp_candidates(const lagp_design* d, const double* XX, int64_t M, int32_t ncand, int32_t* cand_idx,
+                        double* cand_d2, void* stream) {
+  if (!d) return fail(LAGP_EINVAL, "design is NULL");
+  if (M < 0) return fail(LAGP_EINVAL, "M must be >= 0");
+  if (M == 0) return LAGP_OK;
+  if (!XX || !cand_idx) return fail(LAGP_EINVAL, "XX and cand_idx must not be NULL");
+  if (ncand < 1 || (int64_t)ncand > d->N || ncand > LAGP_MAX_NCAND)
+    return fail(LAGP_EINVAL, "ncand must be in [1, min(N, LAGP_MAX_NCAND)]");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int S = lagp::knn_sort_size(ncand);
+  if (lagp::knn_lds_bytes(S, d->p) > (size_t)max_lds_per_block()) return fail(LAGP_EINVAL, "ncand too large for LDS");
+  const size_t per = (size_t)S * (sizeof(double) + sizeof(int32_t));
+  int64_t chunk = std::max<int64_t>(lagp::KNN_QB, (int64_t)(workspace_budget() / per));
+  chunk = std::min<int64_t>(chunk, M);
+  Workspace ws;
+  ws.s = s;
+  LAGP_HIP(hipMallocAsync(&ws.ptr, per * chunk, s));
+  for (int64_t m0 = 0; m0 < M; m0 += chunk) {
+    lagp::KnnArgs a{};
+    a.X = d->X;
+    a.XX = XX + m0 * d->p;
+    a.buf_d2 = reinterpret_cast<double*>(ws.ptr);
+    a.buf_idx = reinterpret_cast<int32_t*>(a.buf_d2 + (size_t)S * chunk);
+    a.out_idx = cand_idx + m0 * ncand;
+    a.out_d2 = cand_d2 ? cand_d2 + m0 * ncand : nullptr;
+    a.N = d->N;
+    a.M = (int32_t)std::min<int64_t>(chunk, M - m0);
+    a.p = d->p;
+    a.ncand = ncand;
+    a.S = S;
+    LAGP_HIP(lagp::launch_knn(a, s));
+  }
+  return LAGP_OK;
+}
+
+}  // extern "C"
+
+namespace lagp {
+
+// Bytes run_predict allocates for M locations under a workspace cap, and the
+// per-location figure (kNN buffers when candidates are not given, the kernel
+// rows, k(x_c, x), the starting-inverse scratch and a status word).
+size_t predict_per_location_bytes(const lagp_design* d, const lagp_params* P, bool have_cand) {
+  const int n = P->n, nc = P->ncand;
+  const int n0 = P->search == LAGP_SEARCH_NN ? n : P->n0;
+  const int ncs = (nc + 15) & ~15;
+  const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? n : n0;
+  const size_t b_knn = have_cand ? 0 : (size_t)knn_sort_size(nc) * (sizeof(double) + sizeof(int32_t));
+  const size_t b_cand = have_cand ? 0 : sizeof(int32_t) * (size_t)nc;
+  (void)d;
+  return b_knn + b_cand + sizeof(double) * (size_t)kc_rows * ncs + sizeof(double) * (size_t)ncs +
+         sizeof(double) * 2 * (size_t)n0 * n0 + sizeof(int32_t);
+}
+
+int64_t predict_chunk(const lagp_design* d, const lagp_params* P, bool have_cand, int64_t M, size_t ws_budget) {
+  const size_t per = predict_per_location_bytes(d, P, have_cand);
+  int64_t chunk = std::max<int64_t>(KNN_QB, (int64_t)(ws_budget / per));
+  return std::min<int64_t>(chunk, M);
+}
+
+size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool have_cand, int64_t M,
+                               size_t ws_budget) {
+  if (M <= 0) return 0;
+  return predict_per_location_bytes(d, P, have_cand) * (size_t)predict_chunk(d, P, have_cand, M, ws_budget) + 6 * 256;
+}
+
+int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
+                    const lagp_params* P, double* mean, double* s2, double* df, int32_t* sel_idx, double* diag,
+                    int32_t* status, void* stream, size_t ws_budget) {
+  if (!d) return fail(LAGP_EINVAL, "design is NULL");
+  if (M < 0) return fail(LAGP_EINVAL, "M must be >= 0");
+  int rays = 0;
+  int32_t rc = check_params(d, P, &rays);
+  if (rc != LAGP_OK) return rc;
+  if (M == 0) return LAGP_OK;
+  if (!XX || !mean || !s2 || !df) return fail(LAGP_EINVAL, "XX, mean, s2 and df must not be NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int p = d->p, n = P->n, nc = P->ncand;
+  const int n0 = P->search == LAGP_SEARCH_NN ? n : P->n0;
+  const int ncs = (nc + 15) & ~15;
+  const int S = lagp::knn_sort_size(nc);
+  const int lds_max = max_lds_per_block();
+  if (!cand_in && lagp::knn_lds_bytes(S, p) > (size_t)lds_max) return fail(LAGP_EINVAL, "ncand too large for LDS");
+  if (lagp::local_lds_bytes(n, ncs, p, std::max(rays, 1)) > (size_t)lds_max)
+    return fail(LAGP_EINVAL, "local design too large for LDS (n, p, numrays)");
+  const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? n : n0;
+  // per-location workspace: kNN buffers and candidate list (unless given),
+  // kernel rows, k(x_c, x), starting-inverse scratch, status
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t b_knn = cand_in ? 0 : (size_t)S * (sizeof(double) + sizeof(int32_t));
+  const size_t b_cand = cand_in ? 0 : sizeof(int32_t) * (size_t)nc;
+  const size_t b_kc = sizeof(double) * (size_t)kc_rows * ncs;
+  const size_t b_kxc = sizeof(double) * (size_t)ncs;
+  const size_t b_chol = sizeof(double) * 2 * (size_t)n0 * n0;
+  const int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget);
+  Workspace ws;
+  ws.s = s;
+  const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_kc = o_cand + al(b_cand * chunk),
+               o_kxc = o_kc + al(b_kc * chunk), o_chol = o_kxc + al(b_kxc * chunk),
+               o_st = o_chol + al(b_chol * chunk), total = o_st + al(sizeof(int32_t) * chunk);
+  LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
+  char* base = reinterpret_cast<char*>(ws.ptr);
+  for (int64_t m0 = 0; m0 < M; m0 += chunk) {
+    const int32_t mc = (int32_t)std::min<int64_t>(chunk, M - m0);
+    const int32_t* cand = cand_in ? cand_in + m0 * nc : reinterpret_cast<const int32_t*>(base + o_cand);
+    if (!cand_in) {
+      lagp::KnnArgs k{};
+      k.X = d->X;
+      k.XX = XX + m0 * p;
+      k.buf_d2 = reinterpret_cast<double*>(base + o_knn);
+      k.buf_idx = reinterpret_cast<int32_t*>(k.buf_d2 + (size_t)S * chunk);
+      k.out_idx = reinterpret_cast<int32_t*>(base + o_cand);
+      k.out_d2 = nullptr;
+      k.N = d->N;
+      k.M = mc;
+      k.p = p;
+      k.ncand = nc;
+      k.S = S;
+      LAGP_HIP(lagp::launch_knn(k, s));
+    }
+    lagp::LocalArgs a{};
+    a.X = d->X;
+    a.y = d->y;
+    a.lo = d->lo;
+    a.hi = d->hi;
+    a.XX = XX + m0 * p;
+    a.cand = cand;
+    a.Kc = reinterpret_cast<double*>(base + o_kc);
+    a.kxc = reinterpret_cast<double*>(base + o_kxc);
+    a.chol = reinterpret_cast<double*>(base + o_chol);
+    a.mean = mean + m0;
+    a.s2 = s2 + m0;
+    a.df = df + m0;
+    a.sel = sel_idx ? sel_idx + m0 * n : nullptr;
+    a.diag = diag ? diag + m0 * (int64_t)(n - n0) * 2 : nullptr;
+    a.status = status ? status + m0 : reinterpret_cast<int32_t*>(base + o_st);
+    a.N = d->N;
+    a.M = mc;
+    a.p = p;
+    a.n0 = n0;
+    a.n = n;
+    a.ncand = nc;
+    a.ncs = ncs;
+    a.kc_rows = kc_rows;
+    a.numrays = rays;
+    a.search = P->search;
+    a.precision = P->precision;
+    a.rescore_k = P->rescore_k;
+    a.dlen = P->d_len;
+    a.brent_maxit = P->brent_maxit > 0 ? P->brent_maxit : 100;
+    a.brent_tol = P->brent_tol > 0.0 ? P->brent_tol : std::ldexp(1.0, -13);
+    a.g = P->g;
+    for (int q = 0; q < P->d_len; ++q) a.d[q] = P->d[q];
+    LAGP_HIP(lagp::launch_local(a, s));
+  }
+  return LAGP_OK;
+}
+
+int32_t check_predict_params(const lagp_design* d, const lagp_params* P) {
+  int rays = 0;
+  return check_params(d, P, &rays);
+}
+
+const char* set_error(const char* msg) {
+  g_err = msg;
+  return g_err.c_str();
+}
+
+}  // namespace lagp
+
+extern "C" {
+
+int32_t lagp_predict(const lagp_design* d, const double* XX, int64_t M, const lagp_params* P, double* mean,
+                     double* s2, double* df, int32_t* sel_idx, double* diag, int32_t* status, void* stream) {
+  return lagp::run_predict(d, XX, M, nullptr, P, mean, s2, df, sel_idx, diag, status, stream, workspace_budget());
+}
+
+int32_t lagp_predict_candidates(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_idx,
+                                const lagp_params* P, double* mean, double* s2, double* df, int32_t* sel_idx,
+                                double* diag, int32_t* status, void* stream) {
+  if (M > 0 && !cand_idx) return fail(LAGP_EINVAL, "cand_idx must not be NULL");
+  return lagp::run_predict(d, XX, M, cand_idx, P, mean, s2, df, sel_idx, diag, status, stream, workspace_budget());
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Device arithmetic shared by the kernels of the local GP library.
+//
+// Rounding is pinned down operation by operation (the library is compiled
+// with -ffp-contract=off, so nothing is fused unless written as fma):
+//  * squared distance: terms accumulated in dimension order from 0.0, one
+//    fused multiply-add per dimension;
+//  * every inner product that feeds the local inverse, the ray objective or
+//    the prediction: terms accumulated in index order from 0.0 with one fused
+//    multiply-add each;
+//  * exp: Cody-Waite reduction by ln2 and a degree-13 Taylor polynomial
+//    (below), results under 2^-1022 flushed to zero;
+//  * division and square root: IEEE (gfx950 f64 div/sqrt are correctly
+//    rounded).
+// With these definitions the kernel values, the partitioned-inverse updates,
+// the ray line searches and the final mean and scale are reproducible bit
+// for bit by any IEEE implementation of the same steps.  Only the candidate
+// scoring contraction (MFMA) sums in a different order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lagp {
+
+// exp(x) = 2^k exp(r), k = rint(x / ln2), r = x - k ln2 computed with ln2 as
+// the double nearest to it plus the remainder (two fused multiply-adds);
+// exp(r), |r| <= ln2/2, by its Taylor polynomial to degree 13 in Horner form
+// (truncation below 1e-17 relative).  Faithful (< 1 ulp) on [-708, 709].
+__device__ __forceinline__ double gexp(double x) {
+  if (x != x) return x;
+  if (x < -708.0) return 0.0;
+  if (x > 709.0) return __builtin_huge_val();
+  const double L2H = 0x1.62e42fefa39efp-1;   // double nearest ln 2
+  const double L2L = 0x1.abc9e3b39803fp-56;  // ln 2 - L2H
+  const double IL2 = 0x1.71547652b82fep+0;   // double nearest 1/ln 2
+  const double k = __builtin_rint(x * IL2);
+  double r = __builtin_fma(-k, L2H, x);
+  r = __builtin_fma(-k, L2L, r);
+  // 1/m! for m = 13 .. 2, each the correctly rounded quotient of exact ints
+  double t = 1.0 / 6227020800.0;
+  t = __builtin_fma(t, r, 1.0 / 479001600.0);
+  t = __builtin_fma(t, r, 1.0 / 39916800.0);
+  t = __builtin_fma(t, r, 1.0 / 3628800.0);
+  t = __builtin_fma(t, r, 1.0 / 362880.0);
+  t = __builtin_fma(t, r, 1.0 / 40320.0);
+  t = __builtin_fma(t, r, 1.0 / 5040.0);
+  t = __builtin_fma(t, r, 1.0 / 720.0);
+  t = __builtin_fma(t, r, 1.0 / 120.0);
+  t = __builtin_fma(t, r, 1.0 / 24.0);
+  t = __builtin_fma(t, r, 1.0 / 6.0);
+  t = __builtin_fma(t, r, 0.5);
+  t = __builtin_fma(t, r, 1.0);
+  t = __builtin_fma(t, r, 1.0);
+  return __builtin_ldexp(t, (int)k);
+}
+
+// Squared Euclidean distance with one fma per dimension, in order.
+__device__ __forceinline__ double sqdist(const double* a, const double* b, int p) {
+  double s = 0.0;
+  for (int k = 0; k < p; ++k) {
+    const double t = a[k] - b[k];
+    s = __builtin_fma(t, t, s);
+  }
+  return s;
+}
+
+// Gaussian correlation exp(-sum_k (a_k-b_k)^2/d_k): one lengthscale
+// (isotropic, dlen == 1) or one per dimension (separable).  No nugget.
+__device__ __forceinline__ double corr(const double* a, const double* b, int p, const double* d, int dlen) {
+  if (dlen == 1) return gexp(-(sqdist(a, b, p) / d[0]));
+  double s = 0.0;
+  for (int k = 0; k < p; ++k) {
+    const double t = a[k] - b[k];
+    s = s + (t * t) / d[k];
+  }
+  return gexp(-s);
+}
+
+// (d2, row) strict order used for the nearest-candidate lists.
+__device__ __forceinline__ bool key_less(double da, int ia, double db, int ib) {
+  return da < db || (da == db && ia < ib);
+}
+
+}  // namespace lagp

@@ -1,0 +1,86 @@
+// Internal declarations of the local GP library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lagp.h"
+
+struct lagp_design {
+  int64_t N;
+  int32_t p;
+  double* X;   // device, N x p row-major
+  double* y;   // device, N
+  double* lo;  // device, p: per-dimension minimum of X
+  double* hi;  // device, p: per-dimension maximum of X
+  int device;
+};
+
+namespace lagp {
+
+// Everything a local-design kernel needs for one chunk of locations.
+struct LocalArgs {
+  const double* X;
+  const double* y;
+  const double* lo;
+  const double* hi;
+  const double* XX;    // chunk locations, M x p
+  const int32_t* cand; // M x ncand nearest rows, nearest first
+  double* Kc;          // workspace, M x n x ncs: K(x_{J_i}, x_c) rows
+  double* kxc;         // workspace, M x ncs: K(x_c, x)
+  double* chol;        // workspace, M x n0 x n0 (starting inverse scratch)
+  double* mean;
+  double* s2;
+  double* df;
+  int32_t* sel;        // nullable, M x n
+  double* diag;        // nullable, M x (n - n0) x 2
+  int32_t* status;     // M
+  int64_t N;
+  int32_t M;
+  int32_t p;
+  int32_t n0, n, ncand, ncs, numrays;
+  int32_t kc_rows;     // rows of Kc kept per location (n exhaustive, n0 otherwise)
+  int32_t search, precision, rescore_k;
+  int32_t dlen;
+  int32_t brent_maxit;
+  double brent_tol;
+  double g;
+  double d[LAGP_MAX_DIM];
+};
+
+struct KnnArgs {
+  const double* X;
+  const double* XX;   // M x p
+  double* buf_d2;     // workspace, ceil(M/QB)*QB x S
+  int32_t* buf_idx;   // workspace
+  int32_t* out_idx;   // M x ncand
+  double* out_d2;     // nullable, M x ncand
+  int64_t N;
+  int32_t M;
+  int32_t p;
+  int32_t ncand;
+  int32_t S;          // sort size (power of two) == buffer capacity
+};
+
+constexpr int KNN_QB = 8;        // locations per kNN workgroup
+constexpr int KNN_THREADS = 256;
+constexpr int LOCAL_THREADS = 256;
+
+int knn_sort_size(int ncand);
+size_t knn_lds_bytes(int S, int p);
+hipError_t launch_knn(const KnnArgs& a, hipStream_t s);
+
+size_t local_lds_bytes(int n, int ncs, int p, int numrays);
+hipError_t launch_local(const LocalArgs& a, hipStream_t s);
+
+hipError_t launch_bbox(const double* X, int64_t N, int p, double* lo, double* hi, hipStream_t s);
+
+// Shared by the C ABI and the server (api.cpp).
+int32_t check_predict_params(const lagp_design* d, const lagp_params* P);
+size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool have_cand, int64_t M,
+                               size_t ws_budget);
+int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in, const lagp_params* P,
+                    double* mean, double* s2, double* df, int32_t* sel_idx, double* diag, int32_t* status,
+                    void* stream, size_t ws_budget);
+const char* set_error(const char* msg);
+
+}  // namespace lagp

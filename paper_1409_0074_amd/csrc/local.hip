@@ -1,0 +1,813 @@
+// Greedy local designs and local GP prediction, one workgroup per location.
+//
+// Per location x with candidate list C (nearest first):
+//   start   J = the n0 nearest; K_J^{-1} by a Cholesky factorisation
+//           (Sec. 2.2), or J = the n nearest in nearest-neighbour mode;
+//   step j  choose the candidate maximising the reduction in variance at x,
+//           the integrand of Eq. (alc):
+//             ALC_c = (K(x_c,x) - k_c^T K^{-1} k_x)^2 / ((1+g) - k_c^T K^{-1} k_c)
+//           - exhaustive (Sec. 3.1): every remaining candidate is scored; the
+//             contraction W = K_J^{-1} [k_c]_c runs on f64 MFMA tiles of 16
+//             candidates, its epilogue folds W into the quadratic form;
+//           - ray (Sec. 4): p rays (or numrays) from round-robin starts among
+//             the nearest remaining candidates, each a Brent line search on a
+//             segment cut at the design's bounding box, an s = 0 check, the
+//             best optimum snapped to the nearest allowed candidate;
+//           then grow K_J^{-1} by the partitioned inverse (G_j, g_j, v_j under
+//           Eq. (alc), with g_j = -K^{-1}k/v);
+//   predict mean k^T K^{-1} y, scale psi ((1+g) - k^T K^{-1} k)/n, df n
+//           (Eqs. predgp, preds2 with n local points).
+// The kernel rows K(x_{J_i}, x_c) live in a per-location workspace (one row
+// appended per step).  Everything except the MFMA scoring contraction uses
+// index-order fma sums, so those values are reproducible bit for bit.
+#include "dev_math.h"
+#include "lagp_internal.h"
+
+namespace lagp {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int NW = LOCAL_THREADS / 64;  // waves per workgroup
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ int shfl_xor_i(int v, int m) { return __shfl_xor(v, m, 64); }
+
+// LDS carve-up (all sizes decided on the host, see local_lds_bytes).
+struct Lds {
+  double* Ki;    // NR x LD, K_J^{-1}, zero outside the leading j x j block
+  double* kx;    // NP: k_J(x)
+  double* h;     // NP: K^{-1} k_x (scoring only)
+  double* col;   // NP: kernel column of the chosen candidate
+  double* wv;    // NP
+  double* gv;    // NP: g_j
+  double* yJ;    // NP
+  double* x;     // LAGP_MAX_DIM: the location
+  double* xj;    // n x p: coordinates of the local design
+  double* kzb;   // NW x 128: ray objective scratch, per wave
+  double* wvb;   // NW x 128
+  double* ra;    // R x p: ray starts
+  double* rdir;  // R x p: clipped segment directions
+  double* rval;  // R: best ALC along each ray
+  double* rs;    // R: its s*
+  double* redv;  // 2 NW
+  double* scal;  // 8 scalars
+  int* redi;     // NW
+  int* J;        // NP: ranks of the local design, selection order
+  int* starts;   // R
+  int* ints;     // 8 scalars
+  unsigned char* selm;  // ncs: 1 = not available (selected or padding)
+};
+
+__host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+
+struct LdsPlan {
+  int NP, NR, LD, R;
+  size_t off[24];
+  size_t bytes;
+};
+
+__host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R) {
+  LdsPlan P;
+  P.NP = n <= 64 ? 64 : 128;
+  P.NR = (n + 15) & ~15;
+  P.LD = P.NP + 4;
+  P.R = R < 1 ? 1 : R;
+  size_t o = 0;
+  int k = 0;
+  auto take = [&](size_t b) { P.off[k++] = o; o = align16(o + b); };
+  take(sizeof(double) * P.NR * P.LD);       // Ki
+  for (int i = 0; i < 6; ++i) take(sizeof(double) * P.NP);  // kx h col wv gv yJ
+  take(sizeof(double) * LAGP_MAX_DIM);     // x
+  take(sizeof(double) * n * p);            // xj
+  take(sizeof(double) * NW * 128);         // kzb
+  take(sizeof(double) * NW * 128);         // wvb
+  take(sizeof(double) * P.R * p);          // ra
+  take(sizeof(double) * P.R * p);          // rdir
+  take(sizeof(double) * P.R);              // rval
+  take(sizeof(double) * P.R);              // rs
+  take(sizeof(double) * 2 * NW);           // redv
+  take(sizeof(double) * 8);                // scal
+  take(sizeof(int) * NW);                  // redi
+  take(sizeof(int) * P.NP);                // J
+  take(sizeof(int) * P.R);                 // starts
+  take(sizeof(int) * 8);                   // ints
+  take(ncs);                               // selm
+  P.bytes = o;
+  return P;
+}
+
+__device__ inline Lds carve(unsigned char* s, const LdsPlan& P) {
+  Lds L;
+  int k = 0;
+  auto D = [&]() { return reinterpret_cast<double*>(s + P.off[k++]); };
+  L.Ki = D();
+  L.kx = D(); L.h = D(); L.col = D(); L.wv = D(); L.gv = D(); L.yJ = D();
+  L.x = D(); L.xj = D(); L.kzb = D(); L.wvb = D(); L.ra = D(); L.rdir = D();
+  L.rval = D(); L.rs = D(); L.redv = D(); L.scal = D();
+  L.redi = reinterpret_cast<int*>(s + P.off[k++]);
+  L.J = reinterpret_cast<int*>(s + P.off[k++]);
+  L.starts = reinterpret_cast<int*>(s + P.off[k++]);
+  L.ints = reinterpret_cast<int*>(s + P.off[k++]);
+  L.selm = s + P.off[k++];
+  return L;
+}
+
+// ------------------------------------------------------------ start ------
+
+// K_J^{-1} of the starting design (J = ranks 0..n0-1), bit-compatible with a
+// row-by-row Cholesky: L = chol(K_J + g I) computed column by column in LDS
+// (each entry's sum runs over the same index order), L^{-1} by forward
+// substitution (one thread per column, scratch in global memory), then
+// K^{-1} = L^{-T} L^{-1}.  Returns false if a pivot is not positive.
+__device__ bool start_inverse(const LocalArgs& a, const Lds& L, int LD, const double* Kc, double* Li, int n0) {
+  const int tid = threadIdx.x;
+  const int ncs = a.ncs;
+  for (int t = tid; t < n0 * n0; t += blockDim.x) {
+    const int i = t / n0, k = t % n0;
+    L.Ki[i * LD + k] = Kc[(int64_t)i * ncs + k] + (i == k ? a.g : 0.0);
+  }
+  if (tid == 0) L.ints[1] = 1;
+  __syncthreads();
+  for (int k = 0; k < n0; ++k) {
+    if (tid == 0) {
+      double s = L.Ki[k * LD + k];
+      for (int m = 0; m < k; ++m) s = __builtin_fma(-L.Ki[k * LD + m], L.Ki[k * LD + m], s);
+      if (!(s > 0.0)) L.ints[1] = 0;
+      L.Ki[k * LD + k] = __builtin_sqrt(s);
+    }
+    __syncthreads();
+    const double piv = L.Ki[k * LD + k];
+    for (int i = k + 1 + tid; i < n0; i += blockDim.x) {
+      double s = L.Ki[i * LD + k];
+      for (int m = 0; m < k; ++m) s = __builtin_fma(-L.Ki[i * LD + m], L.Ki[k * LD + m], s);
+      L.Ki[i * LD + k] = s / piv;
+    }
+    __syncthreads();
+  }
+  const bool ok = L.ints[1] != 0;
+  // forward substitution: column c of L^{-1}
+  for (int c = tid; c < n0; c += blockDim.x) {
+    for (int i = c; i < n0; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int m = c; m < i; ++m) s = __builtin_fma(-L.Ki[i * LD + m], Li[m * n0 + c], s);
+      Li[i * n0 + c] = s / L.Ki[i * LD + i];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < n0 * n0; t += blockDim.x) {
+    const int i = t / n0, k = t % n0;
+    double s = 0.0;
+    for (int m = (i > k ? i : k); m < n0; ++m) s = __builtin_fma(Li[m * n0 + i], Li[m * n0 + k], s);
+    Li[n0 * n0 + t] = s;
+  }
+  __syncthreads();
+  for (int t = tid; t < n0 * n0; t += blockDim.x) {
+    const int i = t / n0, k = t % n0;
+    L.Ki[i * LD + k] = Li[n0 * n0 + t];
+  }
+  __syncthreads();
+  return ok;
+}
+
+// ------------------------------------------------------- exhaustive ------
+
+struct Best {
+  double v1, v2;
+  int i1;
+};
+
+__device__ __forceinline__ void best_push(Best& b, double v, int i) {
+  if (v > b.v1 || (v == b.v1 && i < b.i1)) {
+    b.v2 = b.v1;
+    b.v1 = v;
+    b.i1 = i;
+  } else if (v > b.v2) {
+    b.v2 = v;
+  }
+}
+
+__device__ __forceinline__ Best best_merge(Best a, Best b) {
+  Best r;
+  if (b.v1 > a.v1 || (b.v1 == a.v1 && b.i1 < a.i1)) {
+    r.v1 = b.v1; r.i1 = b.i1; r.v2 = fmax(a.v1, b.v2);
+  } else {
+    r.v1 = a.v1; r.i1 = a.i1; r.v2 = fmax(a.v2, b.v1);
+  }
+  return r;
+}
+
+// Block-wide argmax of the per-thread bests; result in L.ints[0], L.scal[1..2].
+__device__ void block_best(const Lds& L, Best b) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int m = 32; m >= 1; m >>= 1) {
+    Best o;
+    o.v1 = shfl_xor_d(b.v1, m);
+    o.v2 = shfl_xor_d(b.v2, m);
+    o.i1 = shfl_xor_i(b.i1, m);
+    b = best_merge(b, o);
+  }
+  if (lane == 0) {
+    L.redv[2 * wave] = b.v1;
+    L.redv[2 * wave + 1] = b.v2;
+    L.redi[wave] = b.i1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Best r = {L.redv[0], L.redv[1], L.redi[0]};
+    for (int w = 1; w < NW; ++w) {
+      Best o = {L.redv[2 * w], L.redv[2 * w + 1], L.redi[w]};
+      r = best_merge(r, o);
+    }
+    L.ints[0] = r.i1;
+    L.scal[1] = r.v1;
+    L.scal[2] = r.v2;
+  }
+  __syncthreads();
+}
+
+// Score every available candidate at design size j on the vector ALUs, each
+// candidate's terms summed in index order exactly as the definitions fix it:
+//   w_i = sum_k fma(Kinv[i][k], k_c[k]),  v_c = (1+g) - sum_i fma(k_c[i], w_i),
+//   cov_c = K(x_c, x) - sum_i fma(w_i, k_x[i]),  ALC_c = cov_c^2 / v_c,
+// so the scores, and hence every selection, are reproducible bit for bit.
+// One candidate per lane: its kernel column sits in registers (zero past j,
+// and Kinv is zero past j, so the padded terms fma(0, 0, w) leave w
+// unchanged); Kinv rows are read from LDS with wave-uniform addresses.
+template <int NP>
+__device__ Best score_exact(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc, int j,
+                            int* vflag) {
+  constexpr int KB = 8;
+  const int nkb = (j + KB - 1) / KB;
+  const int ncs = a.ncs;
+  const double one_g = 1.0 + a.g;
+  Best best = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
+  for (int c0 = 0; c0 < a.ncand; c0 += blockDim.x) {
+    const int c = c0 + threadIdx.x;
+    const bool live = c < a.ncand && !L.selm[c];
+    double kc[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) kc[k] = (live && k < j) ? Kc[(int64_t)k * ncs + c] : 0.0;
+    double v = 0.0, cv = 0.0;
+    // four rows at a time: four independent fma chains, each summed in
+    // ascending k; rows j.. of Kinv, k_x and k_c are zero, so the padded
+    // rows add fma(0, ., v) = v and fma(0, 0, cv) = cv exactly
+    for (int i = 0; i < j; i += 4) {
+      const double* k0 = L.Ki + i * LD;
+      const double* k1 = k0 + LD;
+      const double* k2 = k1 + LD;
+      const double* k3 = k2 + LD;
+      double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+      for (int b = 0; b < NP / KB; ++b) {
+        if (b < nkb) {
+#pragma unroll
+          for (int u = 0; u < KB; ++u) {
+            const double x = kc[b * KB + u];
+            w0 = __builtin_fma(k0[b * KB + u], x, w0);
+            w1 = __builtin_fma(k1[b * KB + u], x, w1);
+            w2 = __builtin_fma(k2[b * KB + u], x, w2);
+            w3 = __builtin_fma(k3[b * KB + u], x, w3);
+          }
+        }
+      }
+      const double* col = Kc + c;
+      const double c0v = (live && i < j) ? col[(int64_t)i * ncs] : 0.0;
+      const double c1v = (live && i + 1 < j) ? col[(int64_t)(i + 1) * ncs] : 0.0;
+      const double c2v = (live && i + 2 < j) ? col[(int64_t)(i + 2) * ncs] : 0.0;
+      const double c3v = (live && i + 3 < j) ? col[(int64_t)(i + 3) * ncs] : 0.0;
+      v = __builtin_fma(c0v, w0, v);
+      cv = __builtin_fma(w0, L.kx[i], cv);
+      v = __builtin_fma(c1v, w1, v);
+      cv = __builtin_fma(w1, L.kx[i + 1], cv);
+      v = __builtin_fma(c2v, w2, v);
+      cv = __builtin_fma(w2, L.kx[i + 2], cv);
+      v = __builtin_fma(c3v, w3, v);
+      cv = __builtin_fma(w3, L.kx[i + 3], cv);
+    }
+    if (live) {
+      const double vv = one_g - v;
+      const double cov = kxc[c] - cv;
+      double alc = 0.0;
+      if (vv > 0.0) alc = cov * cov / vv;
+      else *vflag = 1;
+      best_push(best, alc, c);
+    }
+  }
+  return best;
+}
+
+// Score every available candidate at design size j with f64 MFMA.
+// Lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950): A[i][k] from
+// lane 16k + i, B[k][n] from lane 16k + n, D[i][n] in register i/4 of lane
+// 16(i%4) + n.  With K-chunk q holding design rows 4q..4q+3 (lane quarter g
+// holds row 4q+g), the B register of chunk q is exactly the factor that D
+// register q%4 of row block q/4 needs in the epilogue sum_i k_c[i] W[i][c].
+template <int NP>
+__device__ Best score_exhaustive(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc,
+                                 int j, int* vflag) {
+  constexpr int QMAX = NP / 4;
+  constexpr int RBMAX = NP / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g4 = lane >> 4, cl = lane & 15;
+  const int nq = (j + 3) >> 2;
+  const int nrb = (j + 15) >> 4;
+  const int ncs = a.ncs;
+  const int ntiles = ncs >> 4;
+  const double one_g = 1.0 + a.g;
+  Best best = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
+  for (int t = wave; t < ntiles; t += NW) {
+    const int c = (t << 4) + cl;
+    double b[QMAX];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      b[q] = 0.0;
+      if (q < nq) {
+        const int row = 4 * q + g4;
+        if (row < j) b[q] = Kc[(int64_t)row * ncs + c];
+      }
+    }
+    double cv = 0.0;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q)
+      if (q < nq) cv = __builtin_fma(L.h[4 * q + g4], b[q], cv);
+    double qf = 0.0;
+#pragma unroll
+    for (int I = 0; I < RBMAX; ++I) {
+      if (I < nrb) {
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        const double* arow = L.Ki + (16 * I + cl) * LD + g4;
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q)
+          if (q < nq) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[4 * q], b[q], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * I + r < nq) qf = __builtin_fma(b[4 * I + r], acc[r], qf);
+      }
+    }
+    qf += shfl_xor_d(qf, 16);
+    qf += shfl_xor_d(qf, 32);
+    cv += shfl_xor_d(cv, 16);
+    cv += shfl_xor_d(cv, 32);
+    if (g4 == 0 && !L.selm[c]) {
+      const double v = one_g - qf;
+      const double cov = kxc[c] - cv;
+      double alc = 0.0;
+      if (v > 0.0) alc = cov * cov / v;
+      else *vflag = 1;
+      best_push(best, alc, c);
+    }
+  }
+  return best;
+}
+
+// ------------------------------------------------------------ update -----
+
+// Grow K^{-1} from j x j to (j+1) x (j+1) with candidate rank cs (the
+// partitioned inverse of Sec. 3.1), append cs to the design, and compute its
+// kernel row against every candidate.  Returns v_j of the added point.
+__device__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc, const double* kxc,
+                            const int32_t* C, int j, int cs) {
+  const int tid = threadIdx.x;
+  const int ncs = a.ncs, p = a.p;
+  const double* xs = a.X + (int64_t)C[cs] * p;
+  if (a.search == LAGP_SEARCH_EXHAUSTIVE) {
+    for (int i = tid; i < j; i += blockDim.x) L.col[i] = Kc[(int64_t)i * ncs + cs];
+  } else {
+    // same arguments as the stored rows K(x_{J_i}, x_c), hence the same bits
+    for (int i = tid; i < j; i += blockDim.x) L.col[i] = corr(L.xj + i * p, xs, p, a.d, a.dlen);
+  }
+  __syncthreads();
+  for (int i = tid; i < j; i += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < j; ++k) s = __builtin_fma(L.Ki[i * LD + k], L.col[k], s);
+    L.wv[i] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int i = 0; i < j; ++i) s = __builtin_fma(L.col[i], L.wv[i], s);
+    L.scal[0] = (1.0 + a.g) - s;
+  }
+  __syncthreads();
+  const double v = L.scal[0];
+  for (int i = tid; i < j; i += blockDim.x) L.gv[i] = -L.wv[i] / v;
+  __syncthreads();
+  for (int t = tid; t < j * j; t += blockDim.x) {
+    const int i = t / j, k = t - i * j;
+    L.Ki[i * LD + k] = __builtin_fma(L.gv[i] * L.gv[k], v, L.Ki[i * LD + k]);
+  }
+  for (int i = tid; i < j; i += blockDim.x) {
+    L.Ki[i * LD + j] = L.gv[i];
+    L.Ki[j * LD + i] = L.gv[i];
+  }
+  if (tid == 0) {
+    L.Ki[j * LD + j] = 1.0 / v;
+    L.J[j] = cs;
+    L.selm[cs] = 1;
+    L.kx[j] = kxc[cs];
+  }
+  for (int k = tid; k < p; k += blockDim.x) L.xj[j * p + k] = xs[k];
+  if (j + 1 < a.n && a.search == LAGP_SEARCH_EXHAUSTIVE) {
+    double* row = Kc + (int64_t)j * ncs;
+    for (int c = tid; c < ncs; c += blockDim.x)
+      row[c] = (c < a.ncand) ? corr(xs, a.X + (int64_t)C[c] * p, p, a.d, a.dlen) : 0.0;
+  }
+  __syncthreads();
+  return v;
+}
+
+// ---------------------------------------------------------- ray search ---
+
+// Ray objective ALC at z = a_r + s dir_r (z = a_r exactly when at_start),
+// computed by one wave: kernel vector on the lanes, K^{-1} k_z one row per
+// lane, the two inner products serially on lanes 0 and 1 (index order).
+__device__ double ray_alc(const LocalArgs& a, const Lds& L, int LD, int j, int r, double s, bool at_start,
+                          int* vflag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = a.p;
+  double* kz = L.kzb + wave * 128;
+  double* wz = L.wvb + wave * 128;
+  const double* ar = L.ra + r * p;
+  const double* dr = L.rdir + r * p;
+  for (int i = lane; i < j; i += 64) {
+    const double* xi = L.xj + i * p;
+    double acc = 0.0;
+    if (a.dlen == 1) {
+      for (int k = 0; k < p; ++k) {
+        const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
+        const double t = xi[k] - zk;
+        acc = __builtin_fma(t, t, acc);
+      }
+      kz[i] = gexp(-(acc / a.d[0]));
+    } else {
+      for (int k = 0; k < p; ++k) {
+        const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
+        const double t = xi[k] - zk;
+        acc = acc + (t * t) / a.d[k];
+      }
+      kz[i] = gexp(-acc);
+    }
+  }
+  wave_sync();
+  for (int i = lane; i < j; i += 64) {
+    double t = 0.0;
+    for (int k = 0; k < j; ++k) t = __builtin_fma(L.Ki[i * LD + k], kz[k], t);
+    wz[i] = t;
+  }
+  wave_sync();
+  double val = 0.0;
+  if (lane == 0) {
+    double t = 0.0;
+    for (int i = 0; i < j; ++i) t = __builtin_fma(kz[i], wz[i], t);
+    val = (1.0 + a.g) - t;
+  } else if (lane == 1) {
+    double t = 0.0;
+    for (int i = 0; i < j; ++i) t = __builtin_fma(wz[i], L.kx[i], t);
+    double acc = 0.0;
+    if (a.dlen == 1) {
+      for (int k = 0; k < p; ++k) {
+        const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
+        const double u = zk - L.x[k];
+        acc = __builtin_fma(u, u, acc);
+      }
+      val = gexp(-(acc / a.d[0])) - t;
+    } else {
+      for (int k = 0; k < p; ++k) {
+        const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
+        const double u = zk - L.x[k];
+        acc = acc + (u * u) / a.d[k];
+      }
+      val = gexp(-acc) - t;
+    }
+  }
+  const double v = __shfl(val, 0, 64);
+  const double cov = __shfl(val, 1, 64);
+  wave_sync();
+  if (v > 0.0) return cov * cov / v;
+  *vflag = 1;
+  return 0.0;
+}
+
+// Brent's (1973) minimiser of f(s) = -ALC on [0, 1]: golden-section steps,
+// replaced by the parabola through the three best points when that step lands
+// inside the bracket and is shorter than half the step before last; never
+// closer than tol1 = 2^-26 |x| + tol/3 to the best point; stop when the
+// bracket half-width about the best point is within 2 tol1.  Every lane of
+// the wave runs the same scalar recurrence.
+__device__ double brent_ray(const LocalArgs& a, const Lds& L, int LD, int j, int r, double* fbest, int* vflag) {
+  const double gold = 0x1.8722191a02d60p-2;  // (3 - sqrt 5)/2
+  const double sqeps = 0x1p-26;              // sqrt(2^-52)
+  const double tol = a.brent_tol;
+  double lo = 0.0, hi = 1.0;
+  double x = lo + gold * (hi - lo);
+  double w = x, v = x;
+  double fx = -ray_alc(a, L, LD, j, r, x, false, vflag);
+  double fw = fx, fv = fx;
+  double step = 0.0, prev = 0.0;
+  for (int it = 0; it < a.brent_maxit; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double tol1 = sqeps * fabs(x) + tol / 3.0;
+    const double tol2 = 2.0 * tol1;
+    if (fabs(x - mid) <= tol2 - 0.5 * (hi - lo)) break;
+    bool para = false;
+    if (fabs(prev) > tol1) {
+      const double rr = (x - w) * (fx - fv);
+      double q = (x - v) * (fx - fw);
+      double num = (x - v) * q - (x - w) * rr;
+      double den = 2.0 * (q - rr);
+      if (den > 0.0) num = -num;
+      den = fabs(den);
+      const double older = prev;
+      prev = step;
+      if (fabs(num) < fabs(0.5 * den * older) && num > den * (lo - x) && num < den * (hi - x)) {
+        step = num / den;
+        const double u = x + step;
+        if (u - lo < tol2 || hi - u < tol2) step = (mid - x >= 0.0) ? tol1 : -tol1;
+        para = true;
+      }
+    }
+    if (!para) {
+      prev = (x >= mid) ? lo - x : hi - x;
+      step = gold * prev;
+    }
+    const double u = (fabs(step) >= tol1) ? x + step : x + ((step >= 0.0) ? tol1 : -tol1);
+    const double fu = -ray_alc(a, L, LD, j, r, u, false, vflag);
+    if (fu <= fx) {
+      if (u >= x) lo = x; else hi = x;
+      v = w; fv = fw;
+      w = x; fw = fx;
+      x = u; fx = fu;
+    } else {
+      if (u < x) lo = u; else hi = u;
+      if (fu <= fw || w == x) {
+        v = w; fv = fw;
+        w = u; fw = fu;
+      } else if (fu <= fv || v == x || v == w) {
+        v = u; fv = fu;
+      }
+    }
+  }
+  *fbest = fx;
+  return x;
+}
+
+// One ray-search step at design size j: returns the chosen candidate rank,
+// the best and runner-up ray values in *b1, *b2.
+__device__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, int j, int n0, double* b1,
+                        double* b2, int* vflag) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = a.p;
+  const int R = a.numrays;
+  if (tid == 0) {
+    const int t = j - n0 + 1;
+    int rt = 0;
+    while ((rt + 1) * (rt + 1) <= t) ++rt;
+    const int k0 = rt > 0 ? t % rt : 0;
+    int seen = 0, got = 0;
+    for (int c = 0; c < a.ncand && got < R; ++c) {
+      if (L.selm[c]) continue;
+      if (seen++ >= k0) L.starts[got++] = c;
+    }
+    L.ints[2] = got;
+  }
+  __syncthreads();
+  const int ns = L.ints[2];
+  for (int r = wave; r < ns; r += NW) {
+    const double* src = a.X + (int64_t)C[L.starts[r]] * p;
+    for (int k = lane; k < p; k += 64) L.ra[r * p + k] = src[k];
+    wave_sync();
+    if (lane == 0) {
+      double tau = 1.0;
+      for (int k = 0; k < p; ++k) {
+        const double dk = 10.0 * (L.ra[r * p + k] - L.x[k]);
+        L.rdir[r * p + k] = dk;
+        if (dk > 0.0) tau = fmin(tau, (a.hi[k] - L.ra[r * p + k]) / dk);
+        else if (dk < 0.0) tau = fmin(tau, (a.lo[k] - L.ra[r * p + k]) / dk);
+      }
+      if (tau < 0.0) tau = 0.0;
+      for (int k = 0; k < p; ++k) L.rdir[r * p + k] = tau * L.rdir[r * p + k];
+      L.rs[r] = tau;
+    }
+    wave_sync();
+    const double tau = L.rs[r];
+    const double a0 = ray_alc(a, L, LD, j, r, 0.0, true, vflag);
+    double sst = 0.0, val = a0;
+    if (tau > 0.0) {
+      double fb;
+      sst = brent_ray(a, L, LD, j, r, &fb, vflag);
+      val = -fb;
+      if (a0 >= val) {
+        sst = 0.0;
+        val = a0;
+      }
+    }
+    if (lane == 0) {
+      L.rval[r] = val;
+      L.rs[r] = sst;
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double bv = -__builtin_huge_val(), sv = -__builtin_huge_val();
+    int br = 0;
+    for (int r = 0; r < ns; ++r) {
+      const double vr = L.rval[r];
+      if (vr > bv) {
+        sv = bv; bv = vr; br = r;
+      } else if (vr > sv) {
+        sv = vr;
+      }
+    }
+    L.ints[3] = br;
+    L.scal[1] = bv;
+    L.scal[2] = sv;
+    L.scal[3] = L.rs[br];
+  }
+  __syncthreads();
+  const int br = L.ints[3];
+  const double sw = L.scal[3];
+  *b1 = L.scal[1];
+  *b2 = L.scal[2];
+  if (sw == 0.0) return L.starts[br];
+  // snap z* = a + s* dir to the nearest candidate outside J and the starts
+  const double* ar = L.ra + br * p;
+  const double* dr = L.rdir + br * p;
+  Best nb = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};  // maximise -d2
+  for (int c = tid; c < a.ncand; c += blockDim.x) {
+    if (L.selm[c]) continue;
+    bool start = false;
+    for (int r = 0; r < ns; ++r) start |= (L.starts[r] == c);
+    if (start) continue;
+    const double* xc = a.X + (int64_t)C[c] * p;
+    double acc = 0.0;
+    for (int k = 0; k < p; ++k) {
+      const double zk = __builtin_fma(sw, dr[k], ar[k]);
+      const double t = xc[k] - zk;
+      acc = __builtin_fma(t, t, acc);
+    }
+    best_push(nb, -acc, c);
+  }
+  block_best(L, nb);
+  return L.ints[0];
+}
+
+// ------------------------------------------------------------ kernel -----
+
+// Kernel variants: one instantiation per search / scoring form so each
+// carries only its own register footprint.
+enum Mode { MODE_EXACT = 0, MODE_MFMA64 = 1, MODE_RAY = 3, MODE_NN = 4 };
+
+template <int NP, int MODE>
+__global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 1;
+  const LdsPlan P = plan_lds(a.n, a.ncs, a.p, R);
+  const Lds L = carve(smem, P);
+  const int LD = P.LD;
+  const int tid = threadIdx.x;
+  const int m = blockIdx.x;
+  const int p = a.p, n = a.n, nc = a.ncand, ncs = a.ncs;
+  const int n0 = (a.search == LAGP_SEARCH_NN) ? n : a.n0;
+  const int32_t* C = a.cand + (int64_t)m * nc;
+  double* Kc = a.Kc + (int64_t)m * a.kc_rows * ncs;
+  double* kxc = a.kxc + (int64_t)m * ncs;
+  double* Li = a.chol + (int64_t)m * 2 * n0 * n0;
+
+  for (int k = tid; k < p; k += blockDim.x) L.x[k] = a.XX[(int64_t)m * p + k];
+  for (int t = tid; t < P.NR * LD; t += blockDim.x) L.Ki[t] = 0.0;
+  for (int t = tid; t < P.NP; t += blockDim.x) {
+    L.kx[t] = 0.0; L.h[t] = 0.0; L.col[t] = 0.0; L.wv[t] = 0.0; L.gv[t] = 0.0; L.yJ[t] = 0.0;
+  }
+  for (int c = tid; c < ncs; c += blockDim.x) L.selm[c] = (c < nc) ? 0 : 1;
+  __syncthreads();
+
+  // kernel vector to x, and the starting rows of the kernel matrix
+  // exhaustive search keeps whole kernel rows; otherwise only K_J is needed
+  const int kcols = (a.search == LAGP_SEARCH_EXHAUSTIVE) ? ncs : n0;
+  for (int c = tid; c < ncs; c += blockDim.x) kxc[c] = (c < nc) ? corr(a.X + (int64_t)C[c] * p, L.x, p, a.d, a.dlen) : 0.0;
+  for (int t = tid; t < n0 * kcols; t += blockDim.x) {
+    const int i = t / kcols, c = t - i * kcols;
+    Kc[(int64_t)i * ncs + c] =
+        (c < nc) ? corr(a.X + (int64_t)C[i] * p, a.X + (int64_t)C[c] * p, p, a.d, a.dlen) : 0.0;
+  }
+  for (int i = tid; i < n0; i += blockDim.x) {
+    L.J[i] = i;
+    L.selm[i] = 1;
+  }
+  for (int t = tid; t < n0 * p; t += blockDim.x) L.xj[t] = a.X[(int64_t)C[t / p] * p + (t % p)];
+  if (tid == 0) L.ints[4] = 0;
+  __syncthreads();
+  for (int i = tid; i < n0; i += blockDim.x) L.kx[i] = kxc[i];
+  const bool pd = start_inverse(a, L, LD, Kc, Li, n0);
+
+  int vflag = 0;
+  int done = n0;  // design size reached
+  if (pd) {
+    for (int j = n0; j < n; ++j) {
+      int cs;
+      double b1, b2;
+      if constexpr (MODE == MODE_RAY) {
+        cs = ray_step(a, L, LD, C, j, n0, &b1, &b2, &vflag);
+      } else {
+        Best b;
+        if constexpr (MODE == MODE_EXACT || MODE == MODE_NN) {
+          b = score_exact<NP>(a, L, LD, Kc, kxc, j, &vflag);  // (NN never runs a step)
+        } else {
+          for (int i = tid; i < j; i += blockDim.x) {
+            double s = 0.0;
+            for (int k = 0; k < j; ++k) s = __builtin_fma(L.Ki[i * LD + k], L.kx[k], s);
+            L.h[i] = s;
+          }
+          __syncthreads();
+          b = score_exhaustive<NP>(a, L, LD, Kc, kxc, j, &vflag);
+        }
+        block_best(L, b);
+        cs = L.ints[0];
+        b1 = L.scal[1];
+        b2 = L.scal[2];
+      }
+      if (cs < 0 || cs >= nc) break;  // no finite score anywhere: give up on x
+      const double v = add_point(a, L, LD, Kc, kxc, C, j, cs);
+      done = j + 1;
+      if (!(v > 0.0)) vflag = 1;
+      if (tid == 0 && a.diag) {
+        double* dg = a.diag + ((int64_t)m * (n - a.n0) + (j - n0)) * 2;
+        dg[0] = b1;
+        dg[1] = b2;
+      }
+    }
+  }
+
+  // prediction with the n local points
+  const bool ok = pd && done == n;
+  if (ok) {
+    for (int i = tid; i < n; i += blockDim.x) L.yJ[i] = a.y[C[L.J[i]]];
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) {
+      double s = 0.0, t = 0.0;
+      for (int k = 0; k < n; ++k) {
+        s = __builtin_fma(L.Ki[i * LD + k], L.kx[k], s);
+        t = __builtin_fma(L.Ki[i * LD + k], L.yJ[k], t);
+      }
+      L.h[i] = s;
+      L.wv[i] = t;
+    }
+  }
+  if (vflag) L.ints[4] = 1;
+  __syncthreads();
+  if (tid == 0) {
+    double mu = __builtin_nan(""), sc = __builtin_nan("");
+    if (ok) {
+      mu = 0.0;
+      double psi = 0.0, q = 0.0;
+      for (int i = 0; i < n; ++i) mu = __builtin_fma(L.h[i], L.yJ[i], mu);
+      for (int i = 0; i < n; ++i) psi = __builtin_fma(L.yJ[i], L.wv[i], psi);
+      for (int i = 0; i < n; ++i) q = __builtin_fma(L.kx[i], L.h[i], q);
+      sc = psi * ((1.0 + a.g) - q) / (double)n;
+    }
+    int st = 0;
+    if (!pd) st |= LAGP_STATUS_NOTPD;
+    if (L.ints[4] == 1) st |= LAGP_STATUS_VNONPOS;
+    if (!(fabs(mu) <= 1.7976931348623157e308 && fabs(sc) <= 1.7976931348623157e308)) st |= LAGP_STATUS_NONFINITE;
+    a.mean[m] = mu;
+    a.s2[m] = sc;
+    a.df[m] = (double)n;
+    a.status[m] = st;
+  }
+  if (a.sel)
+    for (int i = tid; i < n; i += blockDim.x) a.sel[(int64_t)m * n + i] = (i < done) ? C[L.J[i]] : -1;
+}
+
+size_t local_lds_bytes(int n, int ncs, int p, int numrays) { return plan_lds(n, ncs, p, numrays).bytes; }
+
+template <int NP, int MODE>
+static hipError_t launch_mode(const LocalArgs& a, size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_local<NP, MODE>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_local<NP, MODE>), dim3(a.M), dim3(LOCAL_THREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int NP>
+static hipError_t launch_np(const LocalArgs& a, size_t lds, hipStream_t s) {
+  if (a.search == LAGP_SEARCH_RAY) return launch_mode<NP, MODE_RAY>(a, lds, s);
+  if (a.search == LAGP_SEARCH_NN) return launch_mode<NP, MODE_NN>(a, lds, s);
+  if (a.precision == LAGP_PREC_FP64_MFMA) return launch_mode<NP, MODE_MFMA64>(a, lds, s);
+  return launch_mode<NP, MODE_EXACT>(a, lds, s);
+}
+
+hipError_t launch_local(const LocalArgs& a, hipStream_t s) {
+  if (a.M <= 0) return hipSuccess;
+  const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 1;
+  const size_t lds = local_lds_bytes(a.n, a.ncs, a.p, R);
+  return a.n <= 64 ? launch_np<64>(a, lds, s) : launch_np<128>(a, lds, s);
+}
+
+}  // namespace lagp

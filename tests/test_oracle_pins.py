@@ -514,3 +514,14 @@ def test_golden_fixture_is_reproduced(orc):
         assert r["sel"].tolist() == gold[tag]["sel"]
         assert [float(v).hex() for v in r["mean"]] == gold[tag]["mean"]
         assert [float(v).hex() for v in r["s2"]] == gold[tag]["s2"]
+
+
+def test_singular_start_reports_nan(orc):
+    """Duplicate design rows with no nugget make the starting covariance
+    singular: the location reports NaN and the NOTPD status bit."""
+    X = np.repeat(np.random.default_rng(19).random((50, 2)), 2, axis=0)
+    y = W.f_bump2(X)
+    prm = W.Params(n0=4, n=8, ncand=20, d=(0.1,), g=0.0)
+    out = orc.predict(X, y, X[:3] + 0.0, prm, nthreads=1)
+    assert np.all(np.isnan(out["mean"])) and np.all(out["status"] & orc.STATUS_NOTPD)
+    assert np.all(out["sel"][:, 4:] == -1)
