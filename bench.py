@@ -67,6 +67,73 @@ def cpu_baseline(w, params, target_s: float = 15.0):
                 sample=f"first {m} of the {w.XX.shape[0]} locations, {dt:.1f} s, OpenMP over locations")
 
 
+def serving(nreq: int):
+    """Serving workload: resident 4-d design (N = 2e6), requests of 1..1000
+    locations (log-uniform), n from {30, 50, 100}, exhaustive or ray search;
+    saturation throughput from a burst, then open-loop Poisson arrivals at
+    half of it."""
+    import torch
+
+    import paper_1409_0074_amd as lg
+    from paper_1409_0074_amd import loadgen
+    from paper_1409_0074_amd import workloads as W
+
+    w = W.serving4d()
+    d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
+    base = w.params
+    budget, slots = 16 << 30, 8
+    reqs = W.serving_requests(nreq, qps=1.0)
+    mean_m = float(np.mean([r.XX.shape[0] for r in reqs]))
+    loadgen.run(d.handle, reqs[:20], base, budget, slots, burst=True)  # warm-up
+    sat = loadgen.run(d.handle, reqs, base, budget, slots, burst=True)
+    qps = 0.5 * sat["pred_per_s"] / mean_m
+    op = loadgen.run(d.handle, reqs, base, budget, slots, time_scale=1.0 / qps)
+    d.close()
+    return {"workload": w.name, "requests": nreq, "mean_locations": round(mean_m, 1),
+            "saturation_pred_per_s": round(sat["pred_per_s"], 1), "qps": round(qps, 2),
+            "p50_ms": round(op["p50_ms"], 3), "p99_ms": round(op["p99_ms"], 3),
+            "pred_per_s": round(op["pred_per_s"], 1), "errors": len(op["errors"]) + len(sat["errors"]),
+            "arrivals": "open-loop Poisson at half the burst throughput", "budget_bytes": budget, "slots": slots}
+
+
+def grid(M: int):
+    """2-d grid workload (N = 1e6 grid, n = 100, 4000 candidates, d = 0.05) on
+    the first M locations: FP64 and mixed rates, and the mixed form's
+    agreement with FP64."""
+    import torch
+
+    import paper_1409_0074_amd as lg
+    from paper_1409_0074_amd import workloads as W
+
+    w = W.grid2d(M=M)
+    d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
+    XX = torch.from_numpy(w.XX).cuda()
+    out = {"workload": w.name, "M": M}
+    res = {}
+    for tag, prec in (("fp64", W.PREC_FP64), ("mixed", W.PREC_MIXED)):
+        P = lg.make_params(w.params, precision=prec)
+        d.predict(XX[:64], P)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = d.predict(XX, P, diag=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[tag] = {k: v.cpu().numpy() for k, v in o.items() if v is not None}
+        out[tag] = {"pred_per_s": round(M / dt, 2), "seconds": round(dt, 3)}
+    d.close()
+    f, m = res["fp64"], res["mixed"]
+    floor = 1e-6 * np.sqrt(np.mean(w.y ** 2))
+    e_mu = np.abs(m["mean"] - f["mean"]) / np.maximum(np.abs(f["mean"]), floor)
+    e_s2 = np.abs(m["s2"] - f["s2"]) / np.abs(f["s2"])
+    out["mixed_vs_fp64"] = {"identical_designs": float(np.mean(np.all(m["sel"] == f["sel"], axis=1))),
+                            "mean_relerr_max": float(e_mu.max()), "s2_relerr_max": float(e_s2.max()),
+                            "mean_within_1e-5": float(np.mean(e_mu <= 1e-5)),
+                            "s2_within_1e-5": float(np.mean(e_s2 <= 1e-5))}
+    scoring = scoring_flops(w.params.n0, w.params.n, w.params.ncand) * M
+    out["fp64"]["scoring_tflops"] = round(scoring / out["fp64"]["seconds"] / 1e12, 3)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +143,10 @@ def main() -> int:
     ap.add_argument("--ray-steps", type=int, default=2)
     ap.add_argument("--no-ray", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--grid", action="store_true", help="also run the 2-d grid workload, FP64 and mixed")
+    ap.add_argument("--grid-M", type=int, default=2000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -167,6 +238,10 @@ def main() -> int:
                          "rmse_ray_vs_exhaustive": float(np.sqrt(np.mean((ry_mean - ex_mean) ** 2)))}
 
     lg.lagp_design_destroy(design)
+    if not args.no_serving:
+        result["serving"] = serving(args.serving_requests)
+    if args.grid:
+        result["grid"] = grid(args.grid_M)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w, prm)
     print(json.dumps(result), flush=True)

@@ -62,9 +62,8 @@ extern "C" {
 #define LAGP_SEARCH_NN 2         /* the n nearest neighbours, no search (Sec. 2.2) */
 
 /* precision forms */
-#define LAGP_PREC_FP64 0      /* everything in FP64, every sum in its defined order (bit-reproducible) */
-#define LAGP_PREC_MIXED 1     /* candidate screening in FP32 on MFMA, shortlist re-scored in FP64 */
-#define LAGP_PREC_FP64_MFMA 2 /* candidate screening in FP64 on MFMA, shortlist re-scored in FP64 */
+#define LAGP_PREC_FP64 0  /* everything in FP64, every sum in its defined order (bit-reproducible) */
+#define LAGP_PREC_MIXED 1 /* candidate screening in FP32 on MFMA, shortlist re-scored in FP64 */
 
 /* per-location status bits */
 #define LAGP_STATUS_VNONPOS 1   /* a Schur complement v <= 0 was met; scored as 0 */

@@ -9,7 +9,8 @@
  * GPU path.  Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC.
  *
  * What it computes, per predictive location x (all FP64):
- *   O1 kernel      K(a,b) = exp(-sum_k (a_k-b_k)^2 / d_k)           (Sec. 2.1)
+ *   O1 kernel      K(a,b) = exp(-sum_k (a_k-b_k)^2 / d_k)           (Sec. 2.1),
+ *                  evaluated with the reciprocals 1/d_k
  *                  design covariance K_J = [K(x_i,x_l)] + g I         (Sec. 2.1,
  *                  nugget; Eq. alc uses K_eta on the diagonal)
  *   O2 candidates  the N' design rows nearest to x, ordered by
@@ -107,15 +108,17 @@ static double oexp(double x)
 }
 
 /* Gaussian correlation, Sec. 2.1: isotropic exp(-r^2/d) when d_len == 1,
- * separable exp(-sum_k (a_k-b_k)^2/d_k) otherwise.  No nugget here. */
-static double kern(const double *a, const double *b, int p, const double *d, int d_len)
+ * separable exp(-sum_k (a_k-b_k)^2/d_k) otherwise.  No nugget here.  The
+ * lengthscales enter through their reciprocals w_k = 1/d_k (each rounded
+ * once): isotropic exp(-(r^2 w)), separable s <- fma(t_k t_k, w_k, s). */
+static double kern(const double *a, const double *b, int p, const double *w, int d_len)
 {
     if (d_len == 1)
-        return oexp(-(sqdist(a, b, p) / d[0]));
+        return oexp(-(sqdist(a, b, p) * w[0]));
     double s = 0.0;
     for (int k = 0; k < p; k++) {
         double t = a[k] - b[k];
-        s = s + (t * t) / d[k];
+        s = fma(t * t, w[k], s);
     }
     return oexp(-s);
 }
@@ -242,7 +245,7 @@ typedef struct {
     int64_t N;
     int p;
     int n0, n, ncand, search, numrays;
-    const double *d;
+    const double *d; /* reciprocal lengthscales 1/d_k */
     int d_len;
     double g;
     int brent_maxit;
@@ -715,9 +718,10 @@ int orc_predict(const double *X, const double *y, int64_t N, int p, const double
                 double *s2, double *df, int32_t *sel, double *diag, int32_t *status)
 {
     if (check_args(N, p, n0, n, ncand, search, numrays, d, d_len, g) != 0 || M < 0) return -1;
-    double lo[16], hi[16];
+    double lo[16], hi[16], w[16];
     bbox(X, N, p, lo, hi);
-    ctx_t c = {X, y, N, p, n0, n, ncand, search, numrays, d, d_len, g,
+    for (int k = 0; k < d_len; k++) w[k] = 1.0 / d[k];
+    ctx_t c = {X, y, N, p, n0, n, ncand, search, numrays, w, d_len, g,
                brent_maxit > 0 ? brent_maxit : 100, brent_tol > 0.0 ? brent_tol : ldexp(1.0, -13), lo, hi};
     int nd = (search == 2) ? 0 : n - n0;
     int err = 0;
@@ -756,9 +760,10 @@ int orc_trace(const double *X, const double *y, int64_t N, int p, const double *
               double *diag, double *trace_alc, double *trace_Ki, int64_t *cand)
 {
     if (check_args(N, p, n0, n, ncand, search, numrays, d, d_len, g) != 0) return -1;
-    double lo[16], hi[16];
+    double lo[16], hi[16], w[16];
     bbox(X, N, p, lo, hi);
-    ctx_t c = {X, y, N, p, n0, n, ncand, search, numrays, d, d_len, g,
+    for (int k = 0; k < d_len; k++) w[k] = 1.0 / d[k];
+    ctx_t c = {X, y, N, p, n0, n, ncand, search, numrays, w, d_len, g,
                brent_maxit > 0 ? brent_maxit : 100, brent_tol > 0.0 ? brent_tol : ldexp(1.0, -13), lo, hi};
     scratch_t s;
     if (scratch_alloc(&s, n, ncand) != 0) return -2;
@@ -776,7 +781,9 @@ double orc_exp(double x)
 
 double orc_kern(const double *a, const double *b, int p, const double *d, int d_len)
 {
-    return kern(a, b, p, d, d_len);
+    double w[16];
+    for (int k = 0; k < d_len && k < 16; k++) w[k] = 1.0 / d[k];
+    return kern(a, b, p, w, d_len);
 }
 
 double orc_sqdist(const double *a, const double *b, int p)

@@ -57,11 +57,12 @@ int32_t check_params(const lagp_design* d, const lagp_params* P, int* rays) {
   const int p = d->p;
   if (P->search < LAGP_SEARCH_EXHAUSTIVE || P->search > LAGP_SEARCH_NN)
     return fail(LAGP_EINVAL, "search must be LAGP_SEARCH_EXHAUSTIVE, _RAY or _NN");
-  if (P->precision != LAGP_PREC_FP64 && P->precision != LAGP_PREC_MIXED && P->precision != LAGP_PREC_FP64_MFMA)
-    return fail(LAGP_EINVAL, "precision must be LAGP_PREC_FP64, LAGP_PREC_MIXED or LAGP_PREC_FP64_MFMA");
-  if (P->precision != LAGP_PREC_FP64 && P->search != LAGP_SEARCH_EXHAUSTIVE)
-    return fail(LAGP_EINVAL, "the screened precision forms apply to exhaustive search only");
-  if (P->precision == LAGP_PREC_MIXED) return fail(LAGP_EINVAL, "the mixed precision form is not built in this library");
+  if (P->precision != LAGP_PREC_FP64 && P->precision != LAGP_PREC_MIXED)
+    return fail(LAGP_EINVAL, "precision must be LAGP_PREC_FP64 or LAGP_PREC_MIXED");
+  if (P->precision == LAGP_PREC_MIXED && P->search != LAGP_SEARCH_EXHAUSTIVE)
+    return fail(LAGP_EINVAL, "the mixed precision form applies to exhaustive search only");
+  if (P->precision == LAGP_PREC_MIXED && (P->rescore_k < 1 || P->rescore_k > 64))
+    return fail(LAGP_EINVAL, "rescore_k must be in [1, 64]");
   if (P->n < 1 || P->n > LAGP_MAX_N) return fail(LAGP_EINVAL, "n must be in [1, LAGP_MAX_N]");
   if (P->search != LAGP_SEARCH_NN && (P->n0 < 1 || P->n0 > P->n)) return fail(LAGP_EINVAL, "n0 must be in [1, n]");
   if (P->ncand < P->n) return fail(LAGP_EINVAL, "ncand must be >= n");
@@ -84,6 +85,36 @@ int32_t check_params(const lagp_design* d, const lagp_params* P, int* rays) {
     *rays = R;
   }
   return LAGP_OK;
+}
+
+bool force_knn_fallback() {
+  const char* s = std::getenv("LAGP_KNN_FORCE_FALLBACK");
+  return s && s[0] == '1';
+}
+
+// Threshold-first kNN arguments over a workspace laid out as
+// [tau: chunk doubles][cnt: chunk ints][d2: chunk*CAP doubles][row: chunk*CAP ints].
+lagp::Knn2Args knn_args(const lagp_design* d, const double* XX, int32_t M, int ncand, void* ws, int64_t chunk,
+                        int32_t* out_idx, double* out_d2) {
+  lagp::Knn2Args k{};
+  const size_t cap = (lagp::knn2_bytes_per_location(ncand) - sizeof(double) - sizeof(int32_t)) /
+                     (sizeof(double) + sizeof(int32_t));
+  char* b = reinterpret_cast<char*>(ws);
+  k.tau = reinterpret_cast<double*>(b);
+  k.cnt = reinterpret_cast<int32_t*>(b + sizeof(double) * chunk);
+  const size_t o_d2 = ((sizeof(double) + sizeof(int32_t)) * chunk + 255) & ~size_t(255);
+  k.buf_d2 = reinterpret_cast<double*>(b + o_d2);
+  k.buf_idx = reinterpret_cast<int32_t*>(b + o_d2 + sizeof(double) * cap * chunk);
+  k.X = d->X;
+  k.XX = XX;
+  k.out_idx = out_idx;
+  k.out_d2 = out_d2;
+  k.N = d->N;
+  k.M = M;
+  k.p = d->p;
+  k.ncand = ncand;
+  k.force_fallback = force_knn_fallback() ? 1 : 0;
+  return k;
 }
 
 struct Workspace {
@@ -163,27 +194,18 @@ int32_t lagp_candidates(const lagp_design* d, const double* XX, int64_t M, int32
     return fail(LAGP_EINVAL, "ncand must be in [1, min(N, LAGP_MAX_NCAND)]");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int S = lagp::knn_sort_size(ncand);
-  if (lagp::knn_lds_bytes(S, d->p) > (size_t)max_lds_per_block()) return fail(LAGP_EINVAL, "ncand too large for LDS");
-  const size_t per = (size_t)S * (sizeof(double) + sizeof(int32_t));
-  int64_t chunk = std::max<int64_t>(lagp::KNN_QB, (int64_t)(workspace_budget() / per));
+  if (lagp::knn2_merge_lds_bytes(S) > (size_t)max_lds_per_block()) return fail(LAGP_EINVAL, "ncand too large for LDS");
+  const size_t per = lagp::knn2_bytes_per_location(ncand);
+  int64_t chunk = std::max<int64_t>(64, (int64_t)(workspace_budget() / per));
   chunk = std::min<int64_t>(chunk, M);
   Workspace ws;
   ws.s = s;
-  LAGP_HIP(hipMallocAsync(&ws.ptr, per * chunk, s));
+  LAGP_HIP(hipMallocAsync(&ws.ptr, per * chunk + 1024, s));
   for (int64_t m0 = 0; m0 < M; m0 += chunk) {
-    lagp::KnnArgs a{};
-    a.X = d->X;
-    a.XX = XX + m0 * d->p;
-    a.buf_d2 = reinterpret_cast<double*>(ws.ptr);
-    a.buf_idx = reinterpret_cast<int32_t*>(a.buf_d2 + (size_t)S * chunk);
-    a.out_idx = cand_idx + m0 * ncand;
-    a.out_d2 = cand_d2 ? cand_d2 + m0 * ncand : nullptr;
-    a.N = d->N;
-    a.M = (int32_t)std::min<int64_t>(chunk, M - m0);
-    a.p = d->p;
-    a.ncand = ncand;
-    a.S = S;
-    LAGP_HIP(lagp::launch_knn(a, s));
+    const int32_t mc = (int32_t)std::min<int64_t>(chunk, M - m0);
+    LAGP_HIP(lagp::launch_knn2(knn_args(d, XX + m0 * d->p, mc, ncand, ws.ptr, chunk, cand_idx + m0 * ncand,
+                                        cand_d2 ? cand_d2 + m0 * ncand : nullptr),
+                               s));
   }
   return LAGP_OK;
 }
@@ -200,10 +222,11 @@ size_t predict_per_location_bytes(const lagp_design* d, const lagp_params* P, bo
   const int n0 = P->search == LAGP_SEARCH_NN ? n : P->n0;
   const int ncs = (nc + 15) & ~15;
   const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? n : n0;
-  const size_t b_knn = have_cand ? 0 : (size_t)knn_sort_size(nc) * (sizeof(double) + sizeof(int32_t));
+  const size_t b_knn = have_cand ? 0 : knn2_bytes_per_location(nc) + 1024;
   const size_t b_cand = have_cand ? 0 : sizeof(int32_t) * (size_t)nc;
   (void)d;
-  return b_knn + b_cand + sizeof(double) * (size_t)kc_rows * ncs + sizeof(double) * (size_t)ncs +
+  const size_t b_kc32 = P->precision == LAGP_PREC_MIXED ? sizeof(float) * (size_t)kc_rows * ncs : 0;
+  return b_knn + b_cand + sizeof(double) * (size_t)kc_rows * ncs + b_kc32 + sizeof(double) * (size_t)ncs +
          sizeof(double) * 2 * (size_t)n0 * n0 + sizeof(int32_t);
 }
 
@@ -235,44 +258,35 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const int ncs = (nc + 15) & ~15;
   const int S = lagp::knn_sort_size(nc);
   const int lds_max = max_lds_per_block();
-  if (!cand_in && lagp::knn_lds_bytes(S, p) > (size_t)lds_max) return fail(LAGP_EINVAL, "ncand too large for LDS");
+  if (!cand_in && knn2_merge_lds_bytes(S) > (size_t)lds_max) return fail(LAGP_EINVAL, "ncand too large for LDS");
   if (lagp::local_lds_bytes(n, ncs, p, std::max(rays, 1)) > (size_t)lds_max)
     return fail(LAGP_EINVAL, "local design too large for LDS (n, p, numrays)");
   const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? n : n0;
   // per-location workspace: kNN buffers and candidate list (unless given),
   // kernel rows, k(x_c, x), starting-inverse scratch, status
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t b_knn = cand_in ? 0 : (size_t)S * (sizeof(double) + sizeof(int32_t));
+  const size_t b_knn = cand_in ? 0 : knn2_bytes_per_location(nc) + 1024;
   const size_t b_cand = cand_in ? 0 : sizeof(int32_t) * (size_t)nc;
   const size_t b_kc = sizeof(double) * (size_t)kc_rows * ncs;
+  const size_t b_kc32 = P->precision == LAGP_PREC_MIXED ? sizeof(float) * (size_t)kc_rows * ncs : 0;
   const size_t b_kxc = sizeof(double) * (size_t)ncs;
   const size_t b_chol = sizeof(double) * 2 * (size_t)n0 * n0;
   const int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget);
   Workspace ws;
   ws.s = s;
   const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_kc = o_cand + al(b_cand * chunk),
-               o_kxc = o_kc + al(b_kc * chunk), o_chol = o_kxc + al(b_kxc * chunk),
+               o_kc32 = o_kc + al(b_kc * chunk), o_kxc = o_kc32 + al(b_kc32 * chunk),
+               o_chol = o_kxc + al(b_kxc * chunk),
                o_st = o_chol + al(b_chol * chunk), total = o_st + al(sizeof(int32_t) * chunk);
   LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
   char* base = reinterpret_cast<char*>(ws.ptr);
   for (int64_t m0 = 0; m0 < M; m0 += chunk) {
     const int32_t mc = (int32_t)std::min<int64_t>(chunk, M - m0);
     const int32_t* cand = cand_in ? cand_in + m0 * nc : reinterpret_cast<const int32_t*>(base + o_cand);
-    if (!cand_in) {
-      lagp::KnnArgs k{};
-      k.X = d->X;
-      k.XX = XX + m0 * p;
-      k.buf_d2 = reinterpret_cast<double*>(base + o_knn);
-      k.buf_idx = reinterpret_cast<int32_t*>(k.buf_d2 + (size_t)S * chunk);
-      k.out_idx = reinterpret_cast<int32_t*>(base + o_cand);
-      k.out_d2 = nullptr;
-      k.N = d->N;
-      k.M = mc;
-      k.p = p;
-      k.ncand = nc;
-      k.S = S;
-      LAGP_HIP(lagp::launch_knn(k, s));
-    }
+    if (!cand_in)
+      LAGP_HIP(launch_knn2(knn_args(d, XX + m0 * p, mc, nc, base + o_knn, chunk,
+                                    reinterpret_cast<int32_t*>(base + o_cand), nullptr),
+                           s));
     lagp::LocalArgs a{};
     a.X = d->X;
     a.y = d->y;
@@ -281,6 +295,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.XX = XX + m0 * p;
     a.cand = cand;
     a.Kc = reinterpret_cast<double*>(base + o_kc);
+    a.Kc32 = b_kc32 ? reinterpret_cast<float*>(base + o_kc32) : nullptr;
     a.kxc = reinterpret_cast<double*>(base + o_kxc);
     a.chol = reinterpret_cast<double*>(base + o_chol);
     a.mean = mean + m0;
@@ -305,7 +320,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.brent_maxit = P->brent_maxit > 0 ? P->brent_maxit : 100;
     a.brent_tol = P->brent_tol > 0.0 ? P->brent_tol : std::ldexp(1.0, -13);
     a.g = P->g;
-    for (int q = 0; q < P->d_len; ++q) a.d[q] = P->d[q];
+    for (int q = 0; q < P->d_len; ++q) a.w[q] = 1.0 / P->d[q];
     LAGP_HIP(lagp::launch_local(a, s));
   }
   return LAGP_OK;

@@ -63,14 +63,16 @@ __device__ __forceinline__ double sqdist(const double* a, const double* b, int p
   return s;
 }
 
-// Gaussian correlation exp(-sum_k (a_k-b_k)^2/d_k): one lengthscale
-// (isotropic, dlen == 1) or one per dimension (separable).  No nugget.
-__device__ __forceinline__ double corr(const double* a, const double* b, int p, const double* d, int dlen) {
-  if (dlen == 1) return gexp(-(sqdist(a, b, p) / d[0]));
+// Gaussian correlation exp(-sum_k (a_k-b_k)^2/d_k) from the reciprocal
+// lengthscales w_k = 1/d_k: one value (isotropic, dlen == 1) gives
+// exp(-(r^2 w)), one per dimension (separable) accumulates
+// s <- fma(t_k t_k, w_k, s).  No nugget.
+__device__ __forceinline__ double corr(const double* a, const double* b, int p, const double* w, int dlen) {
+  if (dlen == 1) return gexp(-(sqdist(a, b, p) * w[0]));
   double s = 0.0;
   for (int k = 0; k < p; ++k) {
     const double t = a[k] - b[k];
-    s = s + (t * t) / d[k];
+    s = __builtin_fma(t * t, w[k], s);
   }
   return gexp(-s);
 }

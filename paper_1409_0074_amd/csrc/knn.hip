@@ -1,17 +1,7 @@
 // Exact nearest-candidate lists: for each location, the ncand design rows
 // with the smallest (squared distance, row) keys, in that order (the N'
 // nearest neighbours the local search is restricted to, Sec. 2.2).
-//
-// One workgroup serves KNN_QB locations and streams the whole design once.
-// Each thread takes one design row per pass, computes its squared distance to
-// every location of the group (one fma per dimension, in order) and appends
-// (d2, row) to that location's buffer when it beats the location's current
-// threshold key.  A buffer that could overflow on the next pass is compacted:
-// the workgroup sorts it in LDS (bitonic network) and keeps the ncand
-// smallest, whose largest key becomes the new threshold.  After the last pass
-// every buffer is sorted once more and its first ncand entries written out.
-// Because the threshold is always the ncand-th smallest key seen so far, no
-// row of the final answer is ever dropped, and the result is exact.
+// Squared distances accumulate the dimensions in order, one fma each.
 #include "dev_math.h"
 #include "lagp_internal.h"
 
@@ -23,17 +13,13 @@ int knn_sort_size(int ncand) {
   return S;
 }
 
-size_t knn_lds_bytes(int S, int p) {
-  return (size_t)S * (sizeof(double) + sizeof(int)) + (size_t)KNN_QB * p * sizeof(double) +
-         KNN_QB * (sizeof(double) + 2 * sizeof(int));
-}
-
 // Bitonic sort of S = 2^k (key, row) pairs in LDS, ascending.
 __device__ void lds_bitonic_sort(double* kd, int* ki, int S) {
   for (int size = 2; size <= S; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const int ls = __builtin_ctz(stride);  // strides are powers of two
       for (int t = threadIdx.x; t < (S >> 1); t += blockDim.x) {
-        const int lo = 2 * stride * (t / stride) + (t % stride);
+        const int lo = ((t >> ls) << (ls + 1)) + (t & (stride - 1));
         const int hi = lo + stride;
         const bool up = (lo & size) == 0;
         const double a = kd[lo], b = kd[hi];
@@ -66,118 +52,342 @@ __device__ void load_and_sort(const double* bd, const int32_t* bi, int count, do
   lds_bitonic_sort(kd, ki, S);
 }
 
+// ------------------------------------------------ threshold-first kNN ---
+//
+// For large designs the lists come from three passes:
+//  1. threshold: one lane per location; the KT-th smallest squared distance
+//     over a subsample of the design (rows t*A mod N, t < Ns, A coprime with
+//     N, so structured designs such as grids are sampled without a regular
+//     pattern).  Ns is chosen so that about 2 N' rows of the full design are
+//     expected below that value.
+//  2. scan: one lane per location, each wave one slice of the design; every
+//     design row is read at a wave-uniform address (scalar loads) and shared
+//     by the 64 locations of the wave; rows with d2 <= threshold are appended
+//     to the location's buffer (capacity CAP) through a per-location atomic.
+//  3. merge: one workgroup per location keeps the exact ncand smallest
+//     (d2, row) keys of its buffer (LDS bitonic sorts, streaming when the
+//     buffer exceeds the sort size).  If the threshold caught fewer than
+//     ncand rows, or more than CAP, the workgroup falls back to the exact
+//     single-pass compaction scan of the whole design for that location.
+// Every key and order is exact; the threshold only decides how much work is
+// done, never which rows are returned.
+
+constexpr int KT = 32;  // subsample order statistic
+
+// The design never changes while these kernels run: reading it through the
+// constant address space lets wave-uniform row reads become scalar loads
+// into SGPRs (one 64-byte row feeds the 64 lanes' fmas directly).
+typedef const double __attribute__((address_space(4))) cdouble;
+__device__ __forceinline__ const cdouble* as_const(const double* p) { return (const cdouble*)p; }
+
+// Threshold pass, part 1: wave (w, group) takes subsample rows
+// t = w*Ns/TS .. (w+1)*Ns/TS - 1 and leaves, per location, its KT smallest
+// squared distances in the location's buffer (scratch until the scan).
 template <int P>
-__global__ __launch_bounds__(KNN_THREADS) void k_knn(KnnArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int S = a.S;
+__global__ __launch_bounds__(64) void k_knn_tau(Knn2Args a) {
+  const int q = blockIdx.y * 64 + threadIdx.x;
+  const bool live = q < a.M;
   const int p = P > 0 ? P : a.p;
-  double* kd = reinterpret_cast<double*>(smem);
-  double* qx = kd + S;                       // KNN_QB x p
-  double* thr_d = qx + KNN_QB * p;           // KNN_QB
-  int* ki = reinterpret_cast<int*>(thr_d + KNN_QB);  // S
-  int* thr_i = ki + S;                       // KNN_QB
-  int* cnt = thr_i + KNN_QB;                 // KNN_QB
-
-  const int m0 = blockIdx.x * KNN_QB;
-  const int nq = min(KNN_QB, a.M - m0);
-  for (int t = threadIdx.x; t < KNN_QB * p; t += blockDim.x) {
-    const int q = t / p;
-    qx[t] = (q < nq) ? a.XX[(int64_t)(m0 + q) * p + (t % p)] : 0.0;
-  }
-  if (threadIdx.x < KNN_QB) {
-    thr_d[threadIdx.x] = __builtin_huge_val();
-    thr_i[threadIdx.x] = 0x7fffffff;
-    cnt[threadIdx.x] = 0;
-  }
-  __syncthreads();
-
-  double* bd = a.buf_d2 + (int64_t)m0 * S;
-  int32_t* bi = a.buf_idx + (int64_t)m0 * S;
-
-  for (int64_t base = 0; base < a.N; base += KNN_THREADS) {
-    const int64_t i = base + threadIdx.x;
-    if (i < a.N) {
-      double xi[P > 0 ? P : LAGP_MAX_DIM];
-      const double* src = a.X + i * p;
+  double xq[P > 0 ? P : LAGP_MAX_DIM];
 #pragma unroll
-      for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k)
-        if (P > 0 || k < p) xi[k] = src[k];
-      for (int q = 0; q < nq; ++q) {
-        const double* xq = qx + q * p;
-        double s = 0.0;
+  for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k)
+    if (P > 0 || k < p) xq[k] = live ? a.XX[(int64_t)q * p + k] : 0.0;
+  double best[KT];
 #pragma unroll
-        for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k) {
-          if (P > 0 || k < p) {
-            const double t = xi[k] - xq[k];
-            s = __builtin_fma(t, t, s);
-          }
-        }
-        if (key_less(s, (int)i, thr_d[q], thr_i[q])) {
-          const int pos = atomicAdd(&cnt[q], 1);
-          bd[(int64_t)q * S + pos] = s;
-          bi[(int64_t)q * S + pos] = (int32_t)i;
-        }
+  for (int k = 0; k < KT; ++k) best[k] = __builtin_huge_val();
+  double cur = __builtin_huge_val();
+  const int64_t t0 = (a.sub_count * blockIdx.x) / gridDim.x;
+  const int64_t t1 = (a.sub_count * (blockIdx.x + 1)) / gridDim.x;
+  int64_t idx = (t0 * a.sub_stride) % a.N;  // t0, stride < N < 2^31: no overflow
+  for (int64_t t = t0; t < t1; ++t) {
+    const cdouble* xr = as_const(a.X) + idx * p;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k) {
+      if (P > 0 || k < p) {
+        const double u = xq[k] - xr[k];
+        s = __builtin_fma(u, u, s);
       }
     }
-    __syncthreads();
-    // compact every buffer that the next pass could overflow
-    for (int q = 0; q < nq; ++q) {
-      const int c = cnt[q];
-      if (c > S - KNN_THREADS) {
-        load_and_sort(bd + (int64_t)q * S, bi + (int64_t)q * S, c, kd, ki, S);
-        for (int t = threadIdx.x; t < a.ncand; t += blockDim.x) {
-          bd[(int64_t)q * S + t] = kd[t];
-          bi[(int64_t)q * S + t] = ki[t];
+    if (s < cur) {
+      bool done = false;
+      double mx = 0.0;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        if (!done && best[k] == cur) {
+          best[k] = s;
+          done = true;
         }
-        if (threadIdx.x == 0) {
-          thr_d[q] = kd[a.ncand - 1];
-          thr_i[q] = ki[a.ncand - 1];
-          cnt[q] = a.ncand;
-        }
-        __syncthreads();
+        mx = fmax(mx, best[k]);
       }
+      cur = mx;
     }
+    idx += a.sub_stride;
+    if (idx >= a.N) idx -= a.N;
   }
-  // final exact order
-  for (int q = 0; q < nq; ++q) {
-    const int c = cnt[q];
-    load_and_sort(bd + (int64_t)q * S, bi + (int64_t)q * S, c, kd, ki, S);
-    const int64_t m = m0 + q;
-    for (int t = threadIdx.x; t < a.ncand; t += blockDim.x) {
-      a.out_idx[m * a.ncand + t] = ki[t];
-      if (a.out_d2) a.out_d2[m * a.ncand + t] = kd[t];
-    }
-    __syncthreads();
+  if (live) {
+    double* dst = a.buf_d2 + (int64_t)q * a.CAP + blockIdx.x * KT;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) dst[k] = best[k];
   }
 }
 
-hipError_t launch_knn(const KnnArgs& a, hipStream_t s) {
-  if (a.M <= 0) return hipSuccess;
-  const size_t lds = knn_lds_bytes(a.S, a.p);
-  const dim3 grid((a.M + KNN_QB - 1) / KNN_QB);
-#define LAGP_KNN_CASE(PP)                                                                          \
-  case PP: {                                                                                       \
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_knn<PP>),                   \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
-    if (e != hipSuccess) return e;                                                                 \
-    hipLaunchKernelGGL(k_knn<PP>, grid, dim3(KNN_THREADS), lds, s, a);                             \
-    break;                                                                                         \
-  }
-  switch (a.p) {
-    LAGP_KNN_CASE(1)
-    LAGP_KNN_CASE(2)
-    LAGP_KNN_CASE(3)
-    LAGP_KNN_CASE(4)
-    LAGP_KNN_CASE(8)
-    default: {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_knn<0>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_knn<0>, grid, dim3(KNN_THREADS), lds, s, a);
+// Threshold pass, part 2: the KT-th smallest over the partial lists.
+__global__ __launch_bounds__(64) void k_knn_tau_reduce(Knn2Args a, int parts) {
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  if (q >= a.M) return;
+  double best[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) best[k] = __builtin_huge_val();
+  double cur = __builtin_huge_val();
+  const double* src = a.buf_d2 + (int64_t)q * a.CAP;
+  for (int t = 0; t < parts * KT; ++t) {
+    const double s = src[t];
+    if (s < cur) {
+      bool done = false;
+      double mx = 0.0;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        if (!done && best[k] == cur) {
+          best[k] = s;
+          done = true;
+        }
+        mx = fmax(mx, best[k]);
+      }
+      cur = mx;
     }
   }
-#undef LAGP_KNN_CASE
+  a.tau[q] = a.force_fallback ? -1.0 : cur;
+  a.cnt[q] = 0;
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_knn_scan(Knn2Args a) {
+  const int q = blockIdx.y * 64 + threadIdx.x;
+  const bool live = q < a.M;
+  const int p = P > 0 ? P : a.p;
+  double xq[P > 0 ? P : LAGP_MAX_DIM];
+#pragma unroll
+  for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k)
+    if (P > 0 || k < p) xq[k] = live ? a.XX[(int64_t)q * p + k] : 0.0;
+  const double tau = live ? a.tau[q] : -1.0;  // d2 >= 0: a dead lane never appends
+  const int64_t i0 = (int64_t)blockIdx.x * a.slice;
+  const int64_t i1 = i0 + a.slice < a.N ? i0 + a.slice : a.N;
+  const cdouble* X = as_const(a.X);
+  // U rows per iteration so that their scalar loads are in flight together
+  constexpr int U = (P > 0 && P <= 4) ? 4 : 2;
+  int64_t i = i0;
+  for (; i + U <= i1; i += U) {
+    double s[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const cdouble* xr = X + (i + u) * p;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k) {
+        if (P > 0 || k < p) {
+          const double d = xq[k] - xr[k];
+          acc = __builtin_fma(d, d, acc);
+        }
+      }
+      s[u] = acc;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (s[u] <= tau) {
+        const int pos = atomicAdd(&a.cnt[q], 1);
+        if (pos < a.CAP) {
+          a.buf_d2[(int64_t)q * a.CAP + pos] = s[u];
+          a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)(i + u);
+        }
+      }
+    }
+  }
+  for (; i < i1; ++i) {
+    const cdouble* xr = X + i * p;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k) {
+      if (P > 0 || k < p) {
+        const double d = xq[k] - xr[k];
+        acc = __builtin_fma(d, d, acc);
+      }
+    }
+    if (acc <= tau) {
+      const int pos = atomicAdd(&a.cnt[q], 1);
+      if (pos < a.CAP) {
+        a.buf_d2[(int64_t)q * a.CAP + pos] = acc;
+        a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)i;
+      }
+    }
+  }
+}
+
+// Exact single-location scan with compaction (the fallback): the buffer
+// (capacity >= S) receives rows beating the running threshold; whenever it
+// could overflow it is sorted in LDS and cut back to the ncand best.
+template <int P>
+__device__ void knn_exact_one(const Knn2Args& a, int q, double* kd, int* ki, double* bd, int32_t* bi, double* sc,
+                              int* si) {
+  const int S = a.S;
+  const int p = P > 0 ? P : a.p;
+  const double* xq = a.XX + (int64_t)q * p;
+  if (threadIdx.x == 0) {
+    sc[0] = __builtin_huge_val();
+    si[0] = 0x7fffffff;
+    si[1] = 0;
+  }
+  __syncthreads();
+  for (int64_t base = 0; base < a.N; base += blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    if (i < a.N) {
+      const double* xr = a.X + i * p;
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k) {
+        if (P > 0 || k < p) {
+          const double u = xq[k] - xr[k];
+          s = __builtin_fma(u, u, s);
+        }
+      }
+      if (key_less(s, (int)i, sc[0], si[0])) {
+        const int pos = atomicAdd(&si[1], 1);
+        bd[pos] = s;
+        bi[pos] = (int32_t)i;
+      }
+    }
+    __syncthreads();
+    const int c = si[1];
+    if (c > S - (int)blockDim.x) {
+      load_and_sort(bd, bi, c, kd, ki, S);
+      for (int t = threadIdx.x; t < a.ncand; t += blockDim.x) {
+        bd[t] = kd[t];
+        bi[t] = ki[t];
+      }
+      if (threadIdx.x == 0) {
+        sc[0] = kd[a.ncand - 1];
+        si[0] = ki[a.ncand - 1];
+        si[1] = a.ncand;
+      }
+      __syncthreads();
+    }
+  }
+  load_and_sort(bd, bi, si[1], kd, ki, S);
+}
+
+template <int P>
+__global__ __launch_bounds__(KNN_THREADS) void k_knn_merge(Knn2Args a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int S = a.S;
+  double* kd = reinterpret_cast<double*>(smem);
+  double* sc = kd + S;
+  int* ki = reinterpret_cast<int*>(sc + 2);
+  int* si = ki + S;
+  const int q = blockIdx.x;
+  const int nc = a.ncand;
+  double* bd = a.buf_d2 + (int64_t)q * a.CAP;
+  int32_t* bi = a.buf_idx + (int64_t)q * a.CAP;
+  const int c = a.cnt[q];
+  if (c >= nc && c <= a.CAP) {
+    int taken = c < S ? c : S;
+    load_and_sort(bd, bi, taken, kd, ki, S);
+    while (taken < c) {
+      const int add = (c - taken) < (S - nc) ? (c - taken) : (S - nc);
+      for (int t = threadIdx.x; t < S - nc; t += blockDim.x) {
+        if (t < add) {
+          kd[nc + t] = bd[taken + t];
+          ki[nc + t] = bi[taken + t];
+        } else {
+          kd[nc + t] = __builtin_huge_val();
+          ki[nc + t] = 0x7fffffff;
+        }
+      }
+      __syncthreads();
+      lds_bitonic_sort(kd, ki, S);
+      taken += add;
+    }
+  } else {
+    knn_exact_one<P>(a, q, kd, ki, bd, bi, sc, si);
+  }
+  for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+    a.out_idx[(int64_t)q * nc + t] = ki[t];
+    if (a.out_d2) a.out_d2[(int64_t)q * nc + t] = kd[t];
+  }
+}
+
+static int64_t gcd64(int64_t x, int64_t y) {
+  while (y) {
+    const int64_t t = x % y;
+    x = y;
+    y = t;
+  }
+  return x;
+}
+
+int knn2_capacity(int ncand) {
+  const int S = knn_sort_size(ncand);
+  return 4 * ncand > S ? 4 * ncand : S;
+}
+
+size_t knn2_bytes_per_location(int ncand) {
+  return (size_t)knn2_capacity(ncand) * (sizeof(double) + sizeof(int32_t)) + sizeof(double) + sizeof(int32_t);
+}
+
+size_t knn2_merge_lds_bytes(int S) { return (size_t)S * (sizeof(double) + sizeof(int)) + 2 * sizeof(double) + 2 * sizeof(int); }
+
+template <int P>
+static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
+  const int groups = (a.M + 63) / 64;
+  // enough subsample parts to occupy the chip; KT * parts <= 512 <= CAP
+  int parts = (2048 + groups - 1) / groups;
+  if (parts > 16) parts = 16;
+  if ((int64_t)parts > a.sub_count) parts = (int)a.sub_count;
+  if (parts < 1) parts = 1;
+  hipLaunchKernelGGL(k_knn_tau<P>, dim3(parts, groups), dim3(64), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_knn_tau_reduce, dim3(groups), dim3(64), 0, s, a, parts);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_knn_scan<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), groups), dim3(64), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = knn2_merge_lds_bytes(a.S);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_knn_merge<P>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_knn_merge<P>, dim3(a.M), dim3(KNN_THREADS), lds, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_knn2(Knn2Args a, hipStream_t s) {
+  if (a.M <= 0) return hipSuccess;
+  a.S = knn_sort_size(a.ncand);
+  a.CAP = knn2_capacity(a.ncand);
+  // subsample: r rows per sample so that about r * KT ~ 2 ncand rows fall
+  // under the KT-th smallest sampled distance
+  int64_t r = (2 * (int64_t)a.ncand) / KT;
+  if (r < 1) r = 1;
+  a.sub_count = (a.N + r - 1) / r;
+  int64_t A = (int64_t)((double)a.N * 0.6180339887498949) | 1;
+  if (A >= a.N) A = 1;
+  while (gcd64(A, a.N) != 1) A += 2;
+  a.sub_stride = A % a.N;
+  if (a.N == 1) a.sub_stride = 0;
+  const int groups = (a.M + 63) / 64;
+  int64_t nsl = (8192 + groups - 1) / groups;
+  const int64_t maxsl = (a.N + 1023) / 1024;
+  if (nsl > maxsl) nsl = maxsl;
+  if (nsl < 1) nsl = 1;
+  a.slice = (a.N + nsl - 1) / nsl;
+  switch (a.p) {
+    case 1: return launch_knn2_p<1>(a, s);
+    case 2: return launch_knn2_p<2>(a, s);
+    case 3: return launch_knn2_p<3>(a, s);
+    case 4: return launch_knn2_p<4>(a, s);
+    case 8: return launch_knn2_p<8>(a, s);
+    default: return launch_knn2_p<0>(a, s);
+  }
 }
 
 // Per-dimension min and max of the design (bounding box that cuts rays).

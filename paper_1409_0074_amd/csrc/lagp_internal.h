@@ -26,6 +26,7 @@ struct LocalArgs {
   const double* XX;    // chunk locations, M x p
   const int32_t* cand; // M x ncand nearest rows, nearest first
   double* Kc;          // workspace, M x n x ncs: K(x_{J_i}, x_c) rows
+  float* Kc32;         // workspace (mixed form only), the same rows in FP32
   double* kxc;         // workspace, M x ncs: K(x_c, x)
   double* chol;        // workspace, M x n0 x n0 (starting inverse scratch)
   double* mean;
@@ -44,30 +45,39 @@ struct LocalArgs {
   int32_t brent_maxit;
   double brent_tol;
   double g;
-  double d[LAGP_MAX_DIM];
+  double w[LAGP_MAX_DIM];  // reciprocal lengthscales 1/d_k
 };
 
-struct KnnArgs {
+// Arguments of the threshold-first kNN (knn.hip).
+struct Knn2Args {
   const double* X;
   const double* XX;   // M x p
-  double* buf_d2;     // workspace, ceil(M/QB)*QB x S
-  int32_t* buf_idx;   // workspace
+  double* tau;        // workspace, M
+  int32_t* cnt;       // workspace, M
+  double* buf_d2;     // workspace, M x CAP
+  int32_t* buf_idx;   // workspace, M x CAP
   int32_t* out_idx;   // M x ncand
   double* out_d2;     // nullable, M x ncand
   int64_t N;
+  int64_t sub_stride;
+  int64_t sub_count;
+  int64_t slice;
   int32_t M;
   int32_t p;
   int32_t ncand;
-  int32_t S;          // sort size (power of two) == buffer capacity
+  int32_t S;
+  int32_t CAP;
+  int32_t force_fallback;  // test hook: every location takes the exact fallback scan
 };
 
-constexpr int KNN_QB = 8;        // locations per kNN workgroup
+constexpr int KNN_QB = 8;        // smallest location chunk
 constexpr int KNN_THREADS = 256;
 constexpr int LOCAL_THREADS = 256;
 
 int knn_sort_size(int ncand);
-size_t knn_lds_bytes(int S, int p);
-hipError_t launch_knn(const KnnArgs& a, hipStream_t s);
+hipError_t launch_knn2(Knn2Args a, hipStream_t s);
+size_t knn2_bytes_per_location(int ncand);
+size_t knn2_merge_lds_bytes(int S);
 
 size_t local_lds_bytes(int n, int ncs, int p, int numrays);
 hipError_t launch_local(const LocalArgs& a, hipStream_t s);

@@ -60,6 +60,8 @@ struct Lds {
   int* J;        // NP: ranks of the local design, selection order
   int* starts;   // R
   int* ints;     // 8 scalars
+  int* shortlist;  // 64: mixed form, candidates re-scored in FP64
+  float* scr;      // ncs: mixed form, FP32 screened scores
   unsigned char* selm;  // ncs: 1 = not available (selected or padding)
 };
 
@@ -96,6 +98,8 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R) {
   take(sizeof(int) * P.NP);                // J
   take(sizeof(int) * P.R);                 // starts
   take(sizeof(int) * 8);                   // ints
+  take(sizeof(int) * 64);                  // shortlist
+  take(sizeof(float) * ncs);               // scr
   take(ncs);                               // selm
   P.bytes = o;
   return P;
@@ -113,6 +117,8 @@ __device__ inline Lds carve(unsigned char* s, const LdsPlan& P) {
   L.J = reinterpret_cast<int*>(s + P.off[k++]);
   L.starts = reinterpret_cast<int*>(s + P.off[k++]);
   L.ints = reinterpret_cast<int*>(s + P.off[k++]);
+  L.shortlist = reinterpret_cast<int*>(s + P.off[k++]);
+  L.scr = reinterpret_cast<float*>(s + P.off[k++]);
   L.selm = s + P.off[k++];
   return L;
 }
@@ -230,137 +236,202 @@ __device__ void block_best(const Lds& L, Best b) {
   __syncthreads();
 }
 
-// Score every available candidate at design size j on the vector ALUs, each
-// candidate's terms summed in index order exactly as the definitions fix it:
-//   w_i = sum_k fma(Kinv[i][k], k_c[k]),  v_c = (1+g) - sum_i fma(k_c[i], w_i),
-//   cov_c = K(x_c, x) - sum_i fma(w_i, k_x[i]),  ALC_c = cov_c^2 / v_c,
-// so the scores, and hence every selection, are reproducible bit for bit.
-// One candidate per lane: its kernel column sits in registers (zero past j,
-// and Kinv is zero past j, so the padded terms fma(0, 0, w) leave w
-// unchanged); Kinv rows are read from LDS with wave-uniform addresses.
+// Score every available candidate at design size j, exactly in the defined
+// order, on f64 MFMA.  v_mfma_f64_16x16x4f64 computes D = C + sum_k A[.][k]
+// B[k][.] as a chain of fused multiply-adds in ascending k (checked bit for
+// bit on gfx950), so chaining it over K-chunks in ascending order gives the
+// sequential sums of the definitions:
+//   W[i][c]  = sum_k fma(Kinv[i][k], k_c[k])        (A = Kinv rows, B = k_c chunk)
+//   v_c      = (1+g) - sum_i fma(k_c[i], W[i][c])  (A = k_c chunk^T, B = W chunk;
+//                                                   the diagonal of D)
+//   cov_c    = K(x_c,x) - sum_i fma(W[i][c], k_x[i]) (A = k_x broadcast, B = W chunk)
+// Lane layout (gfx950): A[i][k] from lane 16k + i, B[k][n] from lane 16k + n,
+// D[i][n] in register i/4 of lane 16(i%4) + n.  With chunk q = rows
+// 4q..4q+3, lane quarter g holds row 4q + g of a B operand, and register r
+// of row block I holds W rows 16I + 4r + g: exactly the B operand of chunk
+// 4I + r, and the loaded k_c chunk is exactly the A operand of the v chain.
+// Rows and columns past j are zero, and fma(0, 0, s) = s, so the padding
+// leaves every sum unchanged.
+// Exact ALC of one tile of 16 candidate columns (lane column cl holds
+// candidate `col`); the value is valid in lanes 0..15.
 template <int NP>
-__device__ Best score_exact(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc, int j,
-                            int* vflag) {
-  constexpr int KB = 8;
-  const int nkb = (j + KB - 1) / KB;
-  const int ncs = a.ncs;
-  const double one_g = 1.0 + a.g;
-  Best best = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
-  for (int c0 = 0; c0 < a.ncand; c0 += blockDim.x) {
-    const int c = c0 + threadIdx.x;
-    const bool live = c < a.ncand && !L.selm[c];
-    double kc[NP];
-#pragma unroll
-    for (int k = 0; k < NP; ++k) kc[k] = (live && k < j) ? Kc[(int64_t)k * ncs + c] : 0.0;
-    double v = 0.0, cv = 0.0;
-    // four rows at a time: four independent fma chains, each summed in
-    // ascending k; rows j.. of Kinv, k_x and k_c are zero, so the padded
-    // rows add fma(0, ., v) = v and fma(0, 0, cv) = cv exactly
-    for (int i = 0; i < j; i += 4) {
-      const double* k0 = L.Ki + i * LD;
-      const double* k1 = k0 + LD;
-      const double* k2 = k1 + LD;
-      const double* k3 = k2 + LD;
-      double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-#pragma unroll
-      for (int b = 0; b < NP / KB; ++b) {
-        if (b < nkb) {
-#pragma unroll
-          for (int u = 0; u < KB; ++u) {
-            const double x = kc[b * KB + u];
-            w0 = __builtin_fma(k0[b * KB + u], x, w0);
-            w1 = __builtin_fma(k1[b * KB + u], x, w1);
-            w2 = __builtin_fma(k2[b * KB + u], x, w2);
-            w3 = __builtin_fma(k3[b * KB + u], x, w3);
-          }
-        }
-      }
-      const double* col = Kc + c;
-      const double c0v = (live && i < j) ? col[(int64_t)i * ncs] : 0.0;
-      const double c1v = (live && i + 1 < j) ? col[(int64_t)(i + 1) * ncs] : 0.0;
-      const double c2v = (live && i + 2 < j) ? col[(int64_t)(i + 2) * ncs] : 0.0;
-      const double c3v = (live && i + 3 < j) ? col[(int64_t)(i + 3) * ncs] : 0.0;
-      v = __builtin_fma(c0v, w0, v);
-      cv = __builtin_fma(w0, L.kx[i], cv);
-      v = __builtin_fma(c1v, w1, v);
-      cv = __builtin_fma(w1, L.kx[i + 1], cv);
-      v = __builtin_fma(c2v, w2, v);
-      cv = __builtin_fma(w2, L.kx[i + 2], cv);
-      v = __builtin_fma(c3v, w3, v);
-      cv = __builtin_fma(w3, L.kx[i + 3], cv);
-    }
-    if (live) {
-      const double vv = one_g - v;
-      const double cov = kxc[c] - cv;
-      double alc = 0.0;
-      if (vv > 0.0) alc = cov * cov / vv;
-      else *vflag = 1;
-      best_push(best, alc, c);
-    }
-  }
-  return best;
-}
-
-// Score every available candidate at design size j with f64 MFMA.
-// Lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950): A[i][k] from
-// lane 16k + i, B[k][n] from lane 16k + n, D[i][n] in register i/4 of lane
-// 16(i%4) + n.  With K-chunk q holding design rows 4q..4q+3 (lane quarter g
-// holds row 4q+g), the B register of chunk q is exactly the factor that D
-// register q%4 of row block q/4 needs in the epilogue sum_i k_c[i] W[i][c].
-template <int NP>
-__device__ Best score_exhaustive(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc,
-                                 int j, int* vflag) {
+__device__ double alc_tile_exact(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc, int j,
+                                 int col, int* vflag) {
   constexpr int QMAX = NP / 4;
   constexpr int RBMAX = NP / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int g4 = lane >> 4, cl = lane & 15;
   const int nq = (j + 3) >> 2;
   const int nrb = (j + 15) >> 4;
   const int ncs = a.ncs;
-  const int ntiles = ncs >> 4;
-  const double one_g = 1.0 + a.g;
+  double b[QMAX];
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    b[q] = 0.0;
+    if (q < nq) {
+      const int row = 4 * q + g4;
+      if (row < j) b[q] = Kc[(int64_t)row * ncs + col];
+    }
+  }
+  v4d acc[RBMAX];
+#pragma unroll
+  for (int I = 0; I < RBMAX; ++I) acc[I] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // W, all row blocks interleaved: independent MFMA chains
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    if (q < nq) {
+#pragma unroll
+      for (int I = 0; I < RBMAX; ++I)
+        if (I < nrb)
+          acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.Ki[(16 * I + cl) * LD + 4 * q + g4], b[q], acc[I], 0, 0, 0);
+    }
+  }
+  // v and cov chains over the chunks in ascending order
+  v4d accv = {0.0, 0.0, 0.0, 0.0}, accc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int I = 0; I < RBMAX; ++I) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = 4 * I + r;
+      if (q < nq) {
+        accv = __builtin_amdgcn_mfma_f64_16x16x4f64(b[q], acc[I][r], accv, 0, 0, 0);
+        accc = __builtin_amdgcn_mfma_f64_16x16x4f64(L.kx[4 * q + g4], acc[I][r], accc, 0, 0, 0);
+      }
+    }
+  }
+  // D_v[n][n] sits in register n/4 of lane 16(n%4) + n; D_c[0][n] in register 0 of lane n
+  const int rsel = cl >> 2;
+  const double dv = rsel == 0 ? accv[0] : rsel == 1 ? accv[1] : rsel == 2 ? accv[2] : accv[3];
+  const double vsum = __shfl(dv, 16 * (cl & 3) + cl, 64);
+  const double v = (1.0 + a.g) - vsum;
+  const double cov = kxc[col] - accc[0];
+  if (v > 0.0) return cov * cov / v;
+  if (g4 == 0) *vflag = 1;
+  return 0.0;
+}
+
+template <int NP>
+__device__ Best score_exact(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc, int j,
+                            int* vflag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15;
+  const int ntiles = a.ncs >> 4;
   Best best = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
   for (int t = wave; t < ntiles; t += NW) {
     const int c = (t << 4) + cl;
-    double b[QMAX];
+    const double alc = alc_tile_exact<NP>(a, L, LD, Kc, kxc, j, c, vflag);
+    if (lane < 16 && !L.selm[c]) best_push(best, alc, c);
+  }
+  return best;
+}
+
+// --------------------------------------------------------- mixed form ----
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// FP32 screen of every candidate at design size j on f32 MFMA (FP32
+// products and accumulation): the same ALC expression, from an FP32 copy of
+// the kernel rows and of Kinv.  Results go to scr[c] (-inf if unavailable).
+// Lane layout of v_mfma_f32_16x16x4f32 (gfx950): A[i][k] from lane 16k + i,
+// B[k][n] from lane 16k + n, D[i][n] in register i%4 of lane 16(i/4) + n.
+// K-chunk (I', c) holds rows 16I' + 4g + c in lane quarter g, so register r
+// of row block I (rows 16I + 4g + r) pairs with chunk (I, r) in the epilogue.
+template <int NP>
+__device__ void screen_f32(const LocalArgs& a, const Lds& L, int LD, const float* Kc32, const double* kxc, int j,
+                           float* scr) {
+  constexpr int RBMAX = NP / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g4 = lane >> 4, cl = lane & 15;
+  const int nrb = (j + 15) >> 4;
+  const int ncs = a.ncs;
+  const int ntiles = ncs >> 4;
+  const float one_g = (float)(1.0 + a.g);
+  for (int t = wave; t < ntiles; t += NW) {
+    const int c = (t << 4) + cl;
+    float b[RBMAX][4];
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      b[q] = 0.0;
-      if (q < nq) {
-        const int row = 4 * q + g4;
-        if (row < j) b[q] = Kc[(int64_t)row * ncs + c];
+    for (int I = 0; I < RBMAX; ++I)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * I + 4 * g4 + r;
+        b[I][r] = (I < nrb && row < j) ? Kc32[(int64_t)row * ncs + c] : 0.0f;
       }
-    }
-    double cv = 0.0;
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q)
-      if (q < nq) cv = __builtin_fma(L.h[4 * q + g4], b[q], cv);
-    double qf = 0.0;
+    float qf = 0.0f, cv = 0.0f;
 #pragma unroll
     for (int I = 0; I < RBMAX; ++I) {
       if (I < nrb) {
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        const double* arow = L.Ki + (16 * I + cl) * LD + g4;
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const double* arow = L.Ki + (16 * I + cl) * LD + 4 * g4;
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q)
-          if (q < nq) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[4 * q], b[q], acc, 0, 0, 0);
+        for (int I2 = 0; I2 < RBMAX; ++I2)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (4 * I + r < nq) qf = __builtin_fma(b[4 * I + r], acc[r], qf);
+          for (int r = 0; r < 4; ++r)
+            if (I2 < nrb && 16 * I2 + r < j)
+              acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)arow[16 * I2 + r], b[I2][r], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          qf = __builtin_fmaf(b[I][r], acc[r], qf);
+          cv = __builtin_fmaf((float)L.h[16 * I + 4 * g4 + r], b[I][r], cv);
+        }
       }
     }
-    qf += shfl_xor_d(qf, 16);
-    qf += shfl_xor_d(qf, 32);
-    cv += shfl_xor_d(cv, 16);
-    cv += shfl_xor_d(cv, 32);
-    if (g4 == 0 && !L.selm[c]) {
-      const double v = one_g - qf;
-      const double cov = kxc[c] - cv;
-      double alc = 0.0;
-      if (v > 0.0) alc = cov * cov / v;
-      else *vflag = 1;
-      best_push(best, alc, c);
+    qf += __shfl_xor(qf, 16, 64);
+    qf += __shfl_xor(qf, 32, 64);
+    cv += __shfl_xor(cv, 16, 64);
+    cv += __shfl_xor(cv, 32, 64);
+    if (g4 == 0) {
+      float alc = -__builtin_huge_valf();
+      if (!L.selm[c]) {
+        const float v = one_g - qf;
+        const float cov = (float)kxc[c] - cv;
+        alc = v > 0.0f ? cov * cov / v : 0.0f;
+      }
+      scr[c] = alc;
     }
+  }
+}
+
+// Mixed step: FP32 screen, then the rescore_k best screened candidates
+// re-scored exactly in FP64 (one exact tile per 16), argmax of the exact
+// values (ties to the smaller rank).
+template <int NP>
+__device__ Best score_mixed(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const float* Kc32,
+                            const double* kxc, int j, int* vflag) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float* scr = L.scr;
+  // h = Kinv k_x for the screen's covariance term
+  for (int i = tid; i < j; i += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < j; ++k) s = __builtin_fma(L.Ki[k * LD + i], L.kx[k], s);
+    L.h[i] = s;
+  }
+  __syncthreads();
+  screen_f32<NP>(a, L, LD, Kc32, kxc, j, scr);
+  __syncthreads();
+  // shortlist: K rounds of a block-wide argmax over the screened values
+  const int K = a.rescore_k;
+  for (int k = 0; k < K; ++k) {
+    Best b = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
+    for (int c = tid; c < a.ncs; c += blockDim.x) {
+      const float v = scr[c];
+      if (v != -__builtin_huge_valf()) best_push(b, (double)v, c);
+    }
+    block_best(L, b);
+    if (tid == 0) {
+      const int w = L.ints[0];
+      L.shortlist[k] = (w >= 0 && w < a.ncs) ? w : -1;
+      if (w >= 0 && w < a.ncs) scr[w] = -__builtin_huge_valf();
+    }
+    __syncthreads();
+  }
+  // exact FP64 rescore of the shortlist, one tile of 16 per wave
+  Best best = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
+  const int ntl = (K + 15) >> 4;
+  for (int t = wave; t < ntl; t += NW) {
+    const int slot = (t << 4) + (lane & 15);
+    const int c = slot < K ? L.shortlist[slot] : -1;
+    const double alc = alc_tile_exact<NP>(a, L, LD, Kc, kxc, j, c >= 0 ? c : 0, vflag);
+    if (lane < 16 && c >= 0) best_push(best, alc, c);
   }
   return best;
 }
@@ -370,7 +441,7 @@ __device__ Best score_exhaustive(const LocalArgs& a, const Lds& L, int LD, const
 // Grow K^{-1} from j x j to (j+1) x (j+1) with candidate rank cs (the
 // partitioned inverse of Sec. 3.1), append cs to the design, and compute its
 // kernel row against every candidate.  Returns v_j of the added point.
-__device__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc, const double* kxc,
+__device__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc, float* Kc32, const double* kxc,
                             const int32_t* C, int j, int cs) {
   const int tid = threadIdx.x;
   const int ncs = a.ncs, p = a.p;
@@ -379,12 +450,15 @@ __device__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc
     for (int i = tid; i < j; i += blockDim.x) L.col[i] = Kc[(int64_t)i * ncs + cs];
   } else {
     // same arguments as the stored rows K(x_{J_i}, x_c), hence the same bits
-    for (int i = tid; i < j; i += blockDim.x) L.col[i] = corr(L.xj + i * p, xs, p, a.d, a.dlen);
+    for (int i = tid; i < j; i += blockDim.x) L.col[i] = corr(L.xj + i * p, xs, p, a.w, a.dlen);
   }
   __syncthreads();
+  // Kinv is exactly symmetric (every update adds g_i g_k v with
+  // g_i g_k == g_k g_i), so thread i reads column i: same values, same
+  // order, and consecutive threads hit consecutive LDS banks
   for (int i = tid; i < j; i += blockDim.x) {
     double s = 0.0;
-    for (int k = 0; k < j; ++k) s = __builtin_fma(L.Ki[i * LD + k], L.col[k], s);
+    for (int k = 0; k < j; ++k) s = __builtin_fma(L.Ki[k * LD + i], L.col[k], s);
     L.wv[i] = s;
   }
   __syncthreads();
@@ -414,8 +488,11 @@ __device__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc
   for (int k = tid; k < p; k += blockDim.x) L.xj[j * p + k] = xs[k];
   if (j + 1 < a.n && a.search == LAGP_SEARCH_EXHAUSTIVE) {
     double* row = Kc + (int64_t)j * ncs;
-    for (int c = tid; c < ncs; c += blockDim.x)
-      row[c] = (c < a.ncand) ? corr(xs, a.X + (int64_t)C[c] * p, p, a.d, a.dlen) : 0.0;
+    for (int c = tid; c < ncs; c += blockDim.x) {
+      const double kv = (c < a.ncand) ? corr(xs, a.X + (int64_t)C[c] * p, p, a.w, a.dlen) : 0.0;
+      row[c] = kv;
+      if (Kc32) Kc32[(int64_t)j * ncs + c] = (float)kv;
+    }
   }
   __syncthreads();
   return v;
@@ -443,12 +520,12 @@ __device__ double ray_alc(const LocalArgs& a, const Lds& L, int LD, int j, int r
         const double t = xi[k] - zk;
         acc = __builtin_fma(t, t, acc);
       }
-      kz[i] = gexp(-(acc / a.d[0]));
+      kz[i] = gexp(-(acc * a.w[0]));
     } else {
       for (int k = 0; k < p; ++k) {
         const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
         const double t = xi[k] - zk;
-        acc = acc + (t * t) / a.d[k];
+        acc = __builtin_fma(t * t, a.w[k], acc);
       }
       kz[i] = gexp(-acc);
     }
@@ -456,7 +533,7 @@ __device__ double ray_alc(const LocalArgs& a, const Lds& L, int LD, int j, int r
   wave_sync();
   for (int i = lane; i < j; i += 64) {
     double t = 0.0;
-    for (int k = 0; k < j; ++k) t = __builtin_fma(L.Ki[i * LD + k], kz[k], t);
+    for (int k = 0; k < j; ++k) t = __builtin_fma(L.Ki[k * LD + i], kz[k], t);  // column i == row i
     wz[i] = t;
   }
   wave_sync();
@@ -475,12 +552,12 @@ __device__ double ray_alc(const LocalArgs& a, const Lds& L, int LD, int j, int r
         const double u = zk - L.x[k];
         acc = __builtin_fma(u, u, acc);
       }
-      val = gexp(-(acc / a.d[0])) - t;
+      val = gexp(-(acc * a.w[0])) - t;
     } else {
       for (int k = 0; k < p; ++k) {
         const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
         const double u = zk - L.x[k];
-        acc = acc + (u * u) / a.d[k];
+        acc = __builtin_fma(u * u, a.w[k], acc);
       }
       val = gexp(-acc) - t;
     }
@@ -661,7 +738,7 @@ __device__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t*
 
 // Kernel variants: one instantiation per search / scoring form so each
 // carries only its own register footprint.
-enum Mode { MODE_EXACT = 0, MODE_MFMA64 = 1, MODE_RAY = 3, MODE_NN = 4 };
+enum Mode { MODE_EXACT = 0, MODE_MIXED = 1, MODE_RAY = 3, MODE_NN = 4 };
 
 template <int NP, int MODE>
 __global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
@@ -676,6 +753,7 @@ __global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
   const int n0 = (a.search == LAGP_SEARCH_NN) ? n : a.n0;
   const int32_t* C = a.cand + (int64_t)m * nc;
   double* Kc = a.Kc + (int64_t)m * a.kc_rows * ncs;
+  float* Kc32 = a.Kc32 ? a.Kc32 + (int64_t)m * a.kc_rows * ncs : nullptr;
   double* kxc = a.kxc + (int64_t)m * ncs;
   double* Li = a.chol + (int64_t)m * 2 * n0 * n0;
 
@@ -690,11 +768,12 @@ __global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
   // kernel vector to x, and the starting rows of the kernel matrix
   // exhaustive search keeps whole kernel rows; otherwise only K_J is needed
   const int kcols = (a.search == LAGP_SEARCH_EXHAUSTIVE) ? ncs : n0;
-  for (int c = tid; c < ncs; c += blockDim.x) kxc[c] = (c < nc) ? corr(a.X + (int64_t)C[c] * p, L.x, p, a.d, a.dlen) : 0.0;
+  for (int c = tid; c < ncs; c += blockDim.x) kxc[c] = (c < nc) ? corr(a.X + (int64_t)C[c] * p, L.x, p, a.w, a.dlen) : 0.0;
   for (int t = tid; t < n0 * kcols; t += blockDim.x) {
     const int i = t / kcols, c = t - i * kcols;
-    Kc[(int64_t)i * ncs + c] =
-        (c < nc) ? corr(a.X + (int64_t)C[i] * p, a.X + (int64_t)C[c] * p, p, a.d, a.dlen) : 0.0;
+    const double kv = (c < nc) ? corr(a.X + (int64_t)C[i] * p, a.X + (int64_t)C[c] * p, p, a.w, a.dlen) : 0.0;
+    Kc[(int64_t)i * ncs + c] = kv;
+    if (Kc32) Kc32[(int64_t)i * ncs + c] = (float)kv;
   }
   for (int i = tid; i < n0; i += blockDim.x) {
     L.J[i] = i;
@@ -716,24 +795,17 @@ __global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
         cs = ray_step(a, L, LD, C, j, n0, &b1, &b2, &vflag);
       } else {
         Best b;
-        if constexpr (MODE == MODE_EXACT || MODE == MODE_NN) {
+        if constexpr (MODE == MODE_MIXED)
+          b = score_mixed<NP>(a, L, LD, Kc, Kc32, kxc, j, &vflag);
+        else
           b = score_exact<NP>(a, L, LD, Kc, kxc, j, &vflag);  // (NN never runs a step)
-        } else {
-          for (int i = tid; i < j; i += blockDim.x) {
-            double s = 0.0;
-            for (int k = 0; k < j; ++k) s = __builtin_fma(L.Ki[i * LD + k], L.kx[k], s);
-            L.h[i] = s;
-          }
-          __syncthreads();
-          b = score_exhaustive<NP>(a, L, LD, Kc, kxc, j, &vflag);
-        }
         block_best(L, b);
         cs = L.ints[0];
         b1 = L.scal[1];
         b2 = L.scal[2];
       }
       if (cs < 0 || cs >= nc) break;  // no finite score anywhere: give up on x
-      const double v = add_point(a, L, LD, Kc, kxc, C, j, cs);
+      const double v = add_point(a, L, LD, Kc, Kc32, kxc, C, j, cs);
       done = j + 1;
       if (!(v > 0.0)) vflag = 1;
       if (tid == 0 && a.diag) {
@@ -752,8 +824,9 @@ __global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
     for (int i = tid; i < n; i += blockDim.x) {
       double s = 0.0, t = 0.0;
       for (int k = 0; k < n; ++k) {
-        s = __builtin_fma(L.Ki[i * LD + k], L.kx[k], s);
-        t = __builtin_fma(L.Ki[i * LD + k], L.yJ[k], t);
+        const double kik = L.Ki[k * LD + i];  // column i == row i
+        s = __builtin_fma(kik, L.kx[k], s);
+        t = __builtin_fma(kik, L.yJ[k], t);
       }
       L.h[i] = s;
       L.wv[i] = t;
@@ -799,7 +872,7 @@ template <int NP>
 static hipError_t launch_np(const LocalArgs& a, size_t lds, hipStream_t s) {
   if (a.search == LAGP_SEARCH_RAY) return launch_mode<NP, MODE_RAY>(a, lds, s);
   if (a.search == LAGP_SEARCH_NN) return launch_mode<NP, MODE_NN>(a, lds, s);
-  if (a.precision == LAGP_PREC_FP64_MFMA) return launch_mode<NP, MODE_MFMA64>(a, lds, s);
+  if (a.precision == LAGP_PREC_MIXED) return launch_mode<NP, MODE_MIXED>(a, lds, s);
   return launch_mode<NP, MODE_EXACT>(a, lds, s);
 }
 

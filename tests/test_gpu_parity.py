@@ -58,6 +58,30 @@ def test_candidates_bit_exact(lg, case):
     assert np.array_equal(gd, od)
 
 
+@pytest.mark.parametrize("case", ["uniform8d", "grid_ties"])
+def test_candidates_forced_fallback_bit_exact(lg, case, monkeypatch):
+    """The exact fallback scan (taken when the sampled threshold catches too
+    few or too many rows) forced for every location."""
+    monkeypatch.setenv("LAGP_KNN_FORCE_FALLBACK", "1")
+    rng = np.random.default_rng(109)
+    if case == "uniform8d":
+        X, XX, nc = rng.random((20000, 8)), rng.random((10, 8)), 1000
+    else:
+        X = W.grid2(150)
+        XX, nc = np.concatenate([X[[3, 11000]], rng.random((3, 2))]), 400
+    gi, gd = _cands(lg, X, np.zeros(len(X)), XX, nc)
+    oi, od = oracle.knn(X, XX, nc)
+    assert np.array_equal(gi.astype(np.int64), oi) and np.array_equal(gd, od)
+
+
+def test_candidates_large_design_bit_exact(lg):
+    """The full-size 8-d design (N = 1e6) on a sample of locations."""
+    w = W.uniform8d(M=12)
+    gi, gd = _cands(lg, w.X, w.y, w.XX, 1000)
+    oi, od = oracle.knn(w.X, w.XX, 1000)
+    assert np.array_equal(gi.astype(np.int64), oi) and np.array_equal(gd, od)
+
+
 def test_candidates_edge_sizes(lg):
     """ncand = N returns every row, in (d2, row) order."""
     rng = np.random.default_rng(102)
