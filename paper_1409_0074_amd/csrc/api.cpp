@@ -221,7 +221,7 @@ size_t predict_per_location_bytes(const lagp_design* d, const lagp_params* P, bo
   const int n = P->n, nc = P->ncand;
   const int n0 = P->search == LAGP_SEARCH_NN ? n : P->n0;
   const int ncs = (nc + 15) & ~15;
-  const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? n : n0;
+  const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? (n + 3) / 4 * 4 : n0;  // exact tiles read whole chunks
   const size_t b_knn = have_cand ? 0 : knn2_bytes_per_location(nc) + 1024;
   const size_t b_cand = have_cand ? 0 : sizeof(int32_t) * (size_t)nc;
   (void)d;
@@ -259,9 +259,9 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const int S = lagp::knn_sort_size(nc);
   const int lds_max = max_lds_per_block();
   if (!cand_in && knn2_merge_lds_bytes(S) > (size_t)lds_max) return fail(LAGP_EINVAL, "ncand too large for LDS");
-  if (lagp::local_lds_bytes(n, ncs, p, std::max(rays, 1)) > (size_t)lds_max)
+  if (lagp::local_lds_bytes(n, ncs, p, rays, P->precision == LAGP_PREC_MIXED) > (size_t)lds_max)
     return fail(LAGP_EINVAL, "local design too large for LDS (n, p, numrays)");
-  const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? n : n0;
+  const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? (n + 3) / 4 * 4 : n0;  // exact tiles read whole chunks
   // per-location workspace: kNN buffers and candidate list (unless given),
   // kernel rows, k(x_c, x), starting-inverse scratch, status
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };

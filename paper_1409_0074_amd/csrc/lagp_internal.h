@@ -79,7 +79,7 @@ hipError_t launch_knn2(Knn2Args a, hipStream_t s);
 size_t knn2_bytes_per_location(int ncand);
 size_t knn2_merge_lds_bytes(int S);
 
-size_t local_lds_bytes(int n, int ncs, int p, int numrays);
+size_t local_lds_bytes(int n, int ncs, int p, int numrays, bool mixed);
 hipError_t launch_local(const LocalArgs& a, hipStream_t s);
 
 hipError_t launch_bbox(const double* X, int64_t N, int p, double* lo, double* hi, hipStream_t s);

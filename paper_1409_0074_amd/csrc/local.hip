@@ -73,12 +73,14 @@ struct LdsPlan {
   size_t bytes;
 };
 
-__host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R) {
+// R > 0: ray scratch for R rays; mixed: screened scores and shortlist.
+__host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool mixed) {
   LdsPlan P;
   P.NP = n <= 64 ? 64 : 128;
   P.NR = (n + 15) & ~15;
-  P.LD = P.NP + 4;
-  P.R = R < 1 ? 1 : R;
+  P.LD = P.NP + 1;  // odd: the 16 rows of an MFMA operand fall in distinct banks
+  P.R = R < 1 ? 0 : R;
+  const bool ray = R > 0;
   size_t o = 0;
   int k = 0;
   auto take = [&](size_t b) { P.off[k++] = o; o = align16(o + b); };
@@ -86,8 +88,8 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R) {
   for (int i = 0; i < 6; ++i) take(sizeof(double) * P.NP);  // kx h col wv gv yJ
   take(sizeof(double) * LAGP_MAX_DIM);     // x
   take(sizeof(double) * n * p);            // xj
-  take(sizeof(double) * NW * 128);         // kzb
-  take(sizeof(double) * NW * 128);         // wvb
+  take(ray ? sizeof(double) * NW * 128 : 0);  // kzb
+  take(ray ? sizeof(double) * NW * 128 : 0);  // wvb
   take(sizeof(double) * P.R * p);          // ra
   take(sizeof(double) * P.R * p);          // rdir
   take(sizeof(double) * P.R);              // rval
@@ -98,8 +100,8 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R) {
   take(sizeof(int) * P.NP);                // J
   take(sizeof(int) * P.R);                 // starts
   take(sizeof(int) * 8);                   // ints
-  take(sizeof(int) * 64);                  // shortlist
-  take(sizeof(float) * ncs);               // scr
+  take(mixed ? sizeof(int) * 64 : 0);      // shortlist
+  take(mixed ? sizeof(float) * ncs : 0);   // scr
   take(ncs);                               // selm
   P.bytes = o;
   return P;
@@ -130,7 +132,7 @@ __device__ inline Lds carve(unsigned char* s, const LdsPlan& P) {
 // (each entry's sum runs over the same index order), L^{-1} by forward
 // substitution (one thread per column, scratch in global memory), then
 // K^{-1} = L^{-T} L^{-1}.  Returns false if a pivot is not positive.
-__device__ bool start_inverse(const LocalArgs& a, const Lds& L, int LD, const double* Kc, double* Li, int n0) {
+__device__ __forceinline__ bool start_inverse(const LocalArgs& a, const Lds& L, int LD, const double* Kc, double* Li, int n0) {
   const int tid = threadIdx.x;
   const int ncs = a.ncs;
   for (int t = tid; t < n0 * n0; t += blockDim.x) {
@@ -208,7 +210,7 @@ __device__ __forceinline__ Best best_merge(Best a, Best b) {
 }
 
 // Block-wide argmax of the per-thread bests; result in L.ints[0], L.scal[1..2].
-__device__ void block_best(const Lds& L, Best b) {
+__device__ __forceinline__ void block_best(const Lds& L, Best b) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int m = 32; m >= 1; m >>= 1) {
     Best o;
@@ -252,50 +254,59 @@ __device__ void block_best(const Lds& L, Best b) {
 // 4I + r, and the loaded k_c chunk is exactly the A operand of the v chain.
 // Rows and columns past j are zero, and fma(0, 0, s) = s, so the padding
 // leaves every sum unchanged.
+// Buffer resource over one location's candidate-row block (gfx9 word 3).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t kc_rsrc(const LocalArgs& a, const double* Kc) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(Kc), (short)0, a.kc_rows * a.ncs * 8, 0x00020000);
+}
+
+// Column block of the candidate rows K(x_J, x_c), rows 4q + g4 of the
+// 16-column tile at `col`; rows at or past j read as zero.  The block has
+// kc_rows >= 4 ceil(j/4) rows (padded on the host), so every load is in
+// bounds; one lane offset plus a wave-uniform row offset per chunk.
+template <int NQ>
+__device__ __forceinline__ void load_tile_b(const LocalArgs& a, __amdgpu_buffer_rsrc_t rs, int j, int col,
+                                            double (&b)[NQ]) {
+  const int g4 = (threadIdx.x & 63) >> 4;
+  const int ncs = a.ncs;
+  const int voff = (g4 * ncs + col) * 8;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, q * 32 * ncs, 0));
+    b[q] = 4 * q + g4 < j ? v : 0.0;
+  }
+}
+
 // Exact ALC of one tile of 16 candidate columns (lane column cl holds
-// candidate `col`); the value is valid in lanes 0..15.
-template <int NP>
-__device__ double alc_tile_exact(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc, int j,
-                                 int col, int* vflag) {
-  constexpr int QMAX = NP / 4;
-  constexpr int RBMAX = NP / 16;
+// candidate `col`) at a design size j with NQ = ceil(j/4) K-chunks, from the
+// tile's candidate rows b; the value is valid in lanes 0..15.
+template <int NP, int NQ>
+__device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds& L, int LD, const double (&b)[NQ],
+                                                   const double* kxc, int col, int* vflag) {
+  constexpr int NRB = (NQ + 3) / 4;
   const int lane = threadIdx.x & 63;
   const int g4 = lane >> 4, cl = lane & 15;
-  const int nq = (j + 3) >> 2;
-  const int nrb = (j + 15) >> 4;
-  const int ncs = a.ncs;
-  double b[QMAX];
-#pragma unroll
-  for (int q = 0; q < QMAX; ++q) {
-    b[q] = 0.0;
-    if (q < nq) {
-      const int row = 4 * q + g4;
-      if (row < j) b[q] = Kc[(int64_t)row * ncs + col];
-    }
-  }
-  v4d acc[RBMAX];
-#pragma unroll
-  for (int I = 0; I < RBMAX; ++I) acc[I] = (v4d){0.0, 0.0, 0.0, 0.0};
-  // W, all row blocks interleaved: independent MFMA chains
-#pragma unroll
-  for (int q = 0; q < QMAX; ++q) {
-    if (q < nq) {
-#pragma unroll
-      for (int I = 0; I < RBMAX; ++I)
-        if (I < nrb)
-          acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.Ki[(16 * I + cl) * LD + 4 * q + g4], b[q], acc[I], 0, 0, 0);
-    }
-  }
-  // v and cov chains over the chunks in ascending order
+  // An opaque offset keeps the K_J^{-1} fragments in LDS: hoisted out of the
+  // tile loop they would need NRB * NQ register pairs.
+  int aoff = cl * LD + g4;
+  asm volatile("" : "+v"(aoff));
+  const double* arow = L.Ki + aoff;
+  // Row block by row block: the W chain of a block (NQ accumulations into one
+  // register set) is consumed at once by the v and cov chains, whose chunks
+  // 4I .. 4I+3 are exactly that block's rows, so the chunk order stays
+  // ascending and only one block of W is live.
   v4d accv = {0.0, 0.0, 0.0, 0.0}, accc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int I = 0; I < RBMAX; ++I) {
+  for (int I = 0; I < NRB; ++I) {
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * I * LD + 4 * q], b[q], acc, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int q = 4 * I + r;
-      if (q < nq) {
-        accv = __builtin_amdgcn_mfma_f64_16x16x4f64(b[q], acc[I][r], accv, 0, 0, 0);
-        accc = __builtin_amdgcn_mfma_f64_16x16x4f64(L.kx[4 * q + g4], acc[I][r], accc, 0, 0, 0);
+      if (q < NQ) {
+        accv = __builtin_amdgcn_mfma_f64_16x16x4f64(b[q], acc[r], accv, 0, 0, 0);
+        accc = __builtin_amdgcn_mfma_f64_16x16x4f64(L.kx[4 * q + g4], acc[r], accc, 0, 0, 0);
       }
     }
   }
@@ -310,19 +321,74 @@ __device__ double alc_tile_exact(const LocalArgs& a, const Lds& L, int LD, const
   return 0.0;
 }
 
-template <int NP>
-__device__ Best score_exact(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc, int j,
-                            int* vflag) {
+// Exhaustive scoring of one step: the waves take tiles round robin; the
+// candidate rows of a wave's next tile are loaded while it works on the
+// current one.
+template <int NP, int NQ>
+__device__ __forceinline__ Best score_exact_q(const LocalArgs& a, const Lds& L, int LD, const double* Kc,
+                                           const double* kxc, int j, int* vflag) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cl = lane & 15;
   const int ntiles = a.ncs >> 4;
   Best best = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
+  const __amdgpu_buffer_rsrc_t rs = kc_rsrc(a, Kc);
+  // Double buffering costs 2 NQ more registers: only for the shorter chains.
+  constexpr bool PREFETCH = NQ <= 16;
+  double bn[NQ];
+  if (PREFETCH && wave < ntiles) load_tile_b<NQ>(a, rs, j, (wave << 4) + cl, bn);
   for (int t = wave; t < ntiles; t += NW) {
+    double b[NQ];
+    if constexpr (PREFETCH) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) b[q] = bn[q];
+      if (t + NW < ntiles) load_tile_b<NQ>(a, rs, j, ((t + NW) << 4) + cl, bn);
+    } else {
+      load_tile_b<NQ>(a, rs, j, (t << 4) + cl, b);
+    }
     const int c = (t << 4) + cl;
-    const double alc = alc_tile_exact<NP>(a, L, LD, Kc, kxc, j, c, vflag);
+    const double alc = alc_tile_exact_q<NP, NQ>(a, L, LD, b, kxc, c, vflag);
     if (lane < 16 && !L.selm[c]) best_push(best, alc, c);
   }
   return best;
+}
+
+// Exact tile for a shortlist (mixed form): one tile, dispatched on NQ.
+template <int NP, int NQ>
+__device__ __forceinline__ double alc_tile_exact_n(const LocalArgs& a, const Lds& L, int LD, const double* Kc,
+                                                const double* kxc, int j, int col, int* vflag) {
+  double b[NQ];
+  load_tile_b<NQ>(a, kc_rsrc(a, Kc), j, col, b);
+  return alc_tile_exact_q<NP, NQ>(a, L, LD, b, kxc, col, vflag);
+}
+
+#define LAGP_CASES_16(M) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)
+#define LAGP_CASES_32(M) LAGP_CASES_16(M) M(17) M(18) M(19) M(20) M(21) M(22) M(23) M(24) M(25) M(26) M(27) \
+  M(28) M(29) M(30) M(31) M(32)
+
+template <int NP>
+__device__ __forceinline__ Best score_exact(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc, int j,
+                            int* vflag) {
+  const int nq = (j + 3) >> 2;
+#define LAGP_SCORE_CASE(Q) \
+  case Q:                  \
+    if constexpr (Q <= NP / 4) return score_exact_q<NP, Q>(a, L, LD, Kc, kxc, j, vflag); \
+    break;
+  switch (nq) { LAGP_CASES_32(LAGP_SCORE_CASE) default: break; }
+#undef LAGP_SCORE_CASE
+  return Best{-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
+}
+
+template <int NP>
+__device__ __forceinline__ double alc_tile_exact(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const double* kxc, int j,
+                                 int col, int* vflag) {
+  const int nq = (j + 3) >> 2;
+#define LAGP_TILE_CASE(Q) \
+  case Q:                 \
+    if constexpr (Q <= NP / 4) return alc_tile_exact_n<NP, Q>(a, L, LD, Kc, kxc, j, col, vflag); \
+    break;
+  switch (nq) { LAGP_CASES_32(LAGP_TILE_CASE) default: break; }
+#undef LAGP_TILE_CASE
+  return 0.0;
 }
 
 // --------------------------------------------------------- mixed form ----
@@ -337,7 +403,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // K-chunk (I', c) holds rows 16I' + 4g + c in lane quarter g, so register r
 // of row block I (rows 16I + 4g + r) pairs with chunk (I, r) in the epilogue.
 template <int NP>
-__device__ void screen_f32(const LocalArgs& a, const Lds& L, int LD, const float* Kc32, const double* kxc, int j,
+__device__ __forceinline__ void screen_f32(const LocalArgs& a, const Lds& L, int LD, const float* Kc32, const double* kxc, int j,
                            float* scr) {
   constexpr int RBMAX = NP / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -395,7 +461,7 @@ __device__ void screen_f32(const LocalArgs& a, const Lds& L, int LD, const float
 // re-scored exactly in FP64 (one exact tile per 16), argmax of the exact
 // values (ties to the smaller rank).
 template <int NP>
-__device__ Best score_mixed(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const float* Kc32,
+__device__ __forceinline__ Best score_mixed(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const float* Kc32,
                             const double* kxc, int j, int* vflag) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   float* scr = L.scr;
@@ -441,7 +507,7 @@ __device__ Best score_mixed(const LocalArgs& a, const Lds& L, int LD, const doub
 // Grow K^{-1} from j x j to (j+1) x (j+1) with candidate rank cs (the
 // partitioned inverse of Sec. 3.1), append cs to the design, and compute its
 // kernel row against every candidate.  Returns v_j of the added point.
-__device__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc, float* Kc32, const double* kxc,
+__device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc, float* Kc32, const double* kxc,
                             const int32_t* C, int j, int cs) {
   const int tid = threadIdx.x;
   const int ncs = a.ncs, p = a.p;
@@ -500,68 +566,87 @@ __device__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc
 
 // ---------------------------------------------------------- ray search ---
 
-// Ray objective ALC at z = a_r + s dir_r (z = a_r exactly when at_start),
-// computed by one wave: kernel vector on the lanes, K^{-1} k_z one row per
-// lane, the two inner products serially on lanes 0 and 1 (index order).
-__device__ double ray_alc(const LocalArgs& a, const Lds& L, int LD, int j, int r, double s, bool at_start,
-                          int* vflag) {
+// Per-wave registers of one ray: start a, clipped direction, the location x
+// (all wave-uniform) and the lane's design points J_lane, J_{lane+64}.  P is
+// the input dimension when known at compile time (0: runtime p).
+template <int P>
+struct RayRegs {
+  static constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
+  double a[PM], dir[PM], x[PM], xi0[PM], xi1[PM];
+};
+
+// Gaussian correlation of two register vectors, first argument first
+// (same arithmetic as corr()).
+template <int P>
+__device__ __forceinline__ double corr_regs(const double* u, const double* v, int p, const double* w, int dlen) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
+  double acc = 0.0;
+  if (dlen == 1) {
+#pragma unroll
+    for (int k = 0; k < PM; ++k)
+      if (P > 0 || k < p) {
+        const double t = u[k] - v[k];
+        acc = __builtin_fma(t, t, acc);
+      }
+    return gexp(-(acc * w[0]));
+  }
+#pragma unroll
+  for (int k = 0; k < PM; ++k)
+    if (P > 0 || k < p) {
+      const double t = u[k] - v[k];
+      acc = __builtin_fma(t * t, w[k], acc);
+    }
+  return gexp(-acc);
+}
+
+// Ray objective ALC at z = a + s dir (z = a exactly when at_start), one wave:
+// kernel vector on the lanes, K^{-1} k_z one row per lane (column reads of
+// the symmetric inverse), the two inner products on lanes 0 and 1 in the same
+// instruction stream.  Sums run in index order; the LDS vectors are zero past
+// j (as is K^{-1}), so the 8-wide blocks add fma(0, 0, t) = t only.
+template <int P>
+__device__ __forceinline__ double ray_alc(const LocalArgs& a, const Lds& L, int LD, int j, const RayRegs<P>& R, double s,
+                          bool at_start, int* vflag) {
+  constexpr int PM = RayRegs<P>::PM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = a.p;
   double* kz = L.kzb + wave * 128;
   double* wz = L.wvb + wave * 128;
-  const double* ar = L.ra + r * p;
-  const double* dr = L.rdir + r * p;
-  for (int i = lane; i < j; i += 64) {
-    const double* xi = L.xj + i * p;
-    double acc = 0.0;
-    if (a.dlen == 1) {
-      for (int k = 0; k < p; ++k) {
-        const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
-        const double t = xi[k] - zk;
-        acc = __builtin_fma(t, t, acc);
+  double z[PM];
+#pragma unroll
+  for (int k = 0; k < PM; ++k)
+    if (P > 0 || k < p) z[k] = at_start ? R.a[k] : __builtin_fma(s, R.dir[k], R.a[k]);
+  if (lane < j) kz[lane] = corr_regs<P>(R.xi0, z, p, a.w, a.dlen);
+  if (lane + 64 < j) kz[lane + 64] = corr_regs<P>(R.xi1, z, p, a.w, a.dlen);
+  wave_sync();
+  const int nb = (j + 7) >> 3;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = lane + 64 * h;
+    if (i < j) {
+      double t = 0.0;
+      for (int b = 0; b < nb; ++b) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = 8 * b + u;
+          t = __builtin_fma(L.Ki[k * LD + i], kz[k], t);  // column i == row i
+        }
       }
-      kz[i] = gexp(-(acc * a.w[0]));
-    } else {
-      for (int k = 0; k < p; ++k) {
-        const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
-        const double t = xi[k] - zk;
-        acc = __builtin_fma(t * t, a.w[k], acc);
-      }
-      kz[i] = gexp(-acc);
+      wz[i] = t;
     }
   }
   wave_sync();
-  for (int i = lane; i < j; i += 64) {
-    double t = 0.0;
-    for (int k = 0; k < j; ++k) t = __builtin_fma(L.Ki[k * LD + i], kz[k], t);  // column i == row i
-    wz[i] = t;
-  }
-  wave_sync();
-  double val = 0.0;
-  if (lane == 0) {
-    double t = 0.0;
-    for (int i = 0; i < j; ++i) t = __builtin_fma(kz[i], wz[i], t);
-    val = (1.0 + a.g) - t;
-  } else if (lane == 1) {
-    double t = 0.0;
-    for (int i = 0; i < j; ++i) t = __builtin_fma(wz[i], L.kx[i], t);
-    double acc = 0.0;
-    if (a.dlen == 1) {
-      for (int k = 0; k < p; ++k) {
-        const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
-        const double u = zk - L.x[k];
-        acc = __builtin_fma(u, u, acc);
-      }
-      val = gexp(-(acc * a.w[0])) - t;
-    } else {
-      for (int k = 0; k < p; ++k) {
-        const double zk = at_start ? ar[k] : __builtin_fma(s, dr[k], ar[k]);
-        const double u = zk - L.x[k];
-        acc = __builtin_fma(u * u, a.w[k], acc);
-      }
-      val = gexp(-acc) - t;
+  const double* pa = lane == 0 ? kz : wz;
+  const double* pb = lane == 0 ? wz : L.kx;
+  double t = 0.0;
+  if (lane < 2) {
+    for (int b = 0; b < nb; ++b) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t = __builtin_fma(pa[8 * b + u], pb[8 * b + u], t);
     }
   }
+  const double kzx = corr_regs<P>(z, R.x, p, a.w, a.dlen);
+  const double val = lane == 0 ? (1.0 + a.g) - t : kzx - t;
   const double v = __shfl(val, 0, 64);
   const double cov = __shfl(val, 1, 64);
   wave_sync();
@@ -576,14 +661,16 @@ __device__ double ray_alc(const LocalArgs& a, const Lds& L, int LD, int j, int r
 // closer than tol1 = 2^-26 |x| + tol/3 to the best point; stop when the
 // bracket half-width about the best point is within 2 tol1.  Every lane of
 // the wave runs the same scalar recurrence.
-__device__ double brent_ray(const LocalArgs& a, const Lds& L, int LD, int j, int r, double* fbest, int* vflag) {
+template <int P>
+__device__ __forceinline__ double brent_ray(const LocalArgs& a, const Lds& L, int LD, int j, const RayRegs<P>& R, double* fbest,
+                            int* vflag) {
   const double gold = 0x1.8722191a02d60p-2;  // (3 - sqrt 5)/2
   const double sqeps = 0x1p-26;              // sqrt(2^-52)
   const double tol = a.brent_tol;
   double lo = 0.0, hi = 1.0;
   double x = lo + gold * (hi - lo);
   double w = x, v = x;
-  double fx = -ray_alc(a, L, LD, j, r, x, false, vflag);
+  double fx = -ray_alc<P>(a, L, LD, j, R, x, false, vflag);
   double fw = fx, fv = fx;
   double step = 0.0, prev = 0.0;
   for (int it = 0; it < a.brent_maxit; ++it) {
@@ -613,7 +700,7 @@ __device__ double brent_ray(const LocalArgs& a, const Lds& L, int LD, int j, int
       step = gold * prev;
     }
     const double u = (fabs(step) >= tol1) ? x + step : x + ((step >= 0.0) ? tol1 : -tol1);
-    const double fu = -ray_alc(a, L, LD, j, r, u, false, vflag);
+    const double fu = -ray_alc<P>(a, L, LD, j, R, u, false, vflag);
     if (fu <= fx) {
       if (u >= x) lo = x; else hi = x;
       v = w; fv = fw;
@@ -635,8 +722,10 @@ __device__ double brent_ray(const LocalArgs& a, const Lds& L, int LD, int j, int
 
 // One ray-search step at design size j: returns the chosen candidate rank,
 // the best and runner-up ray values in *b1, *b2.
-__device__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, int j, int n0, double* b1,
+template <int P>
+__device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, int j, int n0, double* b1,
                         double* b2, int* vflag) {
+  constexpr int PM = RayRegs<P>::PM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = a.p;
   const int R = a.numrays;
@@ -654,29 +743,40 @@ __device__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t*
   }
   __syncthreads();
   const int ns = L.ints[2];
+  RayRegs<P> RR;
+#pragma unroll
+  for (int k = 0; k < PM; ++k) {
+    const bool in = P > 0 || k < p;
+    RR.x[k] = in ? L.x[k] : 0.0;
+    RR.xi0[k] = (in && lane < j) ? L.xj[lane * p + k] : 0.0;
+    RR.xi1[k] = (in && lane + 64 < j) ? L.xj[(lane + 64) * p + k] : 0.0;
+  }
   for (int r = wave; r < ns; r += NW) {
     const double* src = a.X + (int64_t)C[L.starts[r]] * p;
-    for (int k = lane; k < p; k += 64) L.ra[r * p + k] = src[k];
-    wave_sync();
-    if (lane == 0) {
-      double tau = 1.0;
-      for (int k = 0; k < p; ++k) {
-        const double dk = 10.0 * (L.ra[r * p + k] - L.x[k]);
-        L.rdir[r * p + k] = dk;
-        if (dk > 0.0) tau = fmin(tau, (a.hi[k] - L.ra[r * p + k]) / dk);
-        else if (dk < 0.0) tau = fmin(tau, (a.lo[k] - L.ra[r * p + k]) / dk);
+    // segment from the start, away from x, ten times |a - x| long, cut at the
+    // design's bounding box (every lane computes the same values)
+    double tau = 1.0;
+#pragma unroll
+    for (int k = 0; k < PM; ++k) {
+      if (P > 0 || k < p) {
+        RR.a[k] = src[k];
+        const double dk = 10.0 * (RR.a[k] - RR.x[k]);
+        RR.dir[k] = dk;
+        if (dk > 0.0) tau = fmin(tau, (a.hi[k] - RR.a[k]) / dk);
+        else if (dk < 0.0) tau = fmin(tau, (a.lo[k] - RR.a[k]) / dk);
+      } else {
+        RR.a[k] = 0.0;
+        RR.dir[k] = 0.0;
       }
-      if (tau < 0.0) tau = 0.0;
-      for (int k = 0; k < p; ++k) L.rdir[r * p + k] = tau * L.rdir[r * p + k];
-      L.rs[r] = tau;
     }
-    wave_sync();
-    const double tau = L.rs[r];
-    const double a0 = ray_alc(a, L, LD, j, r, 0.0, true, vflag);
+    if (tau < 0.0) tau = 0.0;
+#pragma unroll
+    for (int k = 0; k < PM; ++k) RR.dir[k] = tau * RR.dir[k];
+    const double a0 = ray_alc<P>(a, L, LD, j, RR, 0.0, true, vflag);
     double sst = 0.0, val = a0;
     if (tau > 0.0) {
       double fb;
-      sst = brent_ray(a, L, LD, j, r, &fb, vflag);
+      sst = brent_ray<P>(a, L, LD, j, RR, &fb, vflag);
       val = -fb;
       if (a0 >= val) {
         sst = 0.0;
@@ -686,6 +786,12 @@ __device__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t*
     if (lane == 0) {
       L.rval[r] = val;
       L.rs[r] = sst;
+#pragma unroll
+      for (int k = 0; k < PM; ++k)
+        if (P > 0 || k < p) {
+          L.ra[r * p + k] = RR.a[k];
+          L.rdir[r * p + k] = RR.dir[k];
+        }
     }
     wave_sync();
   }
@@ -740,13 +846,13 @@ __device__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t*
 // carries only its own register footprint.
 enum Mode { MODE_EXACT = 0, MODE_MIXED = 1, MODE_RAY = 3, MODE_NN = 4 };
 
-template <int NP, int MODE>
-__global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
+template <int NP, int MODE, int P>
+__global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_local(LocalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 1;
-  const LdsPlan P = plan_lds(a.n, a.ncs, a.p, R);
-  const Lds L = carve(smem, P);
-  const int LD = P.LD;
+  const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 0;
+  const LdsPlan plan = plan_lds(a.n, a.ncs, a.p, R, MODE == MODE_MIXED);
+  const Lds L = carve(smem, plan);
+  const int LD = plan.LD;
   const int tid = threadIdx.x;
   const int m = blockIdx.x;
   const int p = a.p, n = a.n, nc = a.ncand, ncs = a.ncs;
@@ -758,11 +864,16 @@ __global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
   double* Li = a.chol + (int64_t)m * 2 * n0 * n0;
 
   for (int k = tid; k < p; k += blockDim.x) L.x[k] = a.XX[(int64_t)m * p + k];
-  for (int t = tid; t < P.NR * LD; t += blockDim.x) L.Ki[t] = 0.0;
-  for (int t = tid; t < P.NP; t += blockDim.x) {
+  for (int t = tid; t < plan.NR * LD; t += blockDim.x) L.Ki[t] = 0.0;
+  for (int t = tid; t < plan.NP; t += blockDim.x) {
     L.kx[t] = 0.0; L.h[t] = 0.0; L.col[t] = 0.0; L.wv[t] = 0.0; L.gv[t] = 0.0; L.yJ[t] = 0.0;
   }
   for (int c = tid; c < ncs; c += blockDim.x) L.selm[c] = (c < nc) ? 0 : 1;
+  if constexpr (MODE == MODE_RAY)
+    for (int t = tid; t < NW * 128; t += blockDim.x) {
+      L.kzb[t] = 0.0;  // zero past j: the ray sums run in zero-padded blocks
+      L.wvb[t] = 0.0;
+    }
   __syncthreads();
 
   // kernel vector to x, and the starting rows of the kernel matrix
@@ -792,13 +903,16 @@ __global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
       int cs;
       double b1, b2;
       if constexpr (MODE == MODE_RAY) {
-        cs = ray_step(a, L, LD, C, j, n0, &b1, &b2, &vflag);
+        cs = ray_step<P>(a, L, LD, C, j, n0, &b1, &b2, &vflag);
+      } else if constexpr (MODE == MODE_NN) {
+        cs = -1;  // (the nearest neighbours fill the design: no step runs)
+        b1 = b2 = 0.0;
       } else {
         Best b;
         if constexpr (MODE == MODE_MIXED)
           b = score_mixed<NP>(a, L, LD, Kc, Kc32, kxc, j, &vflag);
         else
-          b = score_exact<NP>(a, L, LD, Kc, kxc, j, &vflag);  // (NN never runs a step)
+          b = score_exact<NP>(a, L, LD, Kc, kxc, j, &vflag);
         block_best(L, b);
         cs = L.ints[0];
         b1 = L.scal[1];
@@ -857,30 +971,44 @@ __global__ __launch_bounds__(LOCAL_THREADS) void k_local(LocalArgs a) {
     for (int i = tid; i < n; i += blockDim.x) a.sel[(int64_t)m * n + i] = (i < done) ? C[L.J[i]] : -1;
 }
 
-size_t local_lds_bytes(int n, int ncs, int p, int numrays) { return plan_lds(n, ncs, p, numrays).bytes; }
+size_t local_lds_bytes(int n, int ncs, int p, int numrays, bool mixed) {
+  return plan_lds(n, ncs, p, numrays, mixed).bytes;
+}
 
-template <int NP, int MODE>
+template <int NP, int MODE, int P = 0>
 static hipError_t launch_mode(const LocalArgs& a, size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_local<NP, MODE>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_local<NP, MODE, P>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_local<NP, MODE>), dim3(a.M), dim3(LOCAL_THREADS), lds, s, a);
+  hipLaunchKernelGGL((k_local<NP, MODE, P>), dim3(a.M), dim3(LOCAL_THREADS), lds, s, a);
   return hipGetLastError();
 }
 
+// The scoring width NP matters to the exhaustive forms only; ray and
+// nearest-neighbour kernels are instantiated once (their LDS plan is sized at
+// run time either way).
 template <int NP>
-static hipError_t launch_np(const LocalArgs& a, size_t lds, hipStream_t s) {
-  if (a.search == LAGP_SEARCH_RAY) return launch_mode<NP, MODE_RAY>(a, lds, s);
-  if (a.search == LAGP_SEARCH_NN) return launch_mode<NP, MODE_NN>(a, lds, s);
+static hipError_t launch_exhaustive(const LocalArgs& a, size_t lds, hipStream_t s) {
   if (a.precision == LAGP_PREC_MIXED) return launch_mode<NP, MODE_MIXED>(a, lds, s);
   return launch_mode<NP, MODE_EXACT>(a, lds, s);
 }
 
 hipError_t launch_local(const LocalArgs& a, hipStream_t s) {
   if (a.M <= 0) return hipSuccess;
-  const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 1;
-  const size_t lds = local_lds_bytes(a.n, a.ncs, a.p, R);
-  return a.n <= 64 ? launch_np<64>(a, lds, s) : launch_np<128>(a, lds, s);
+  const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 0;
+  const size_t lds = local_lds_bytes(a.n, a.ncs, a.p, R, a.precision == LAGP_PREC_MIXED);
+  if (a.search == LAGP_SEARCH_RAY) {
+    switch (a.p) {
+      case 1: return launch_mode<64, MODE_RAY, 1>(a, lds, s);
+      case 2: return launch_mode<64, MODE_RAY, 2>(a, lds, s);
+      case 3: return launch_mode<64, MODE_RAY, 3>(a, lds, s);
+      case 4: return launch_mode<64, MODE_RAY, 4>(a, lds, s);
+      case 8: return launch_mode<64, MODE_RAY, 8>(a, lds, s);
+      default: return launch_mode<64, MODE_RAY, 0>(a, lds, s);
+    }
+  }
+  if (a.search == LAGP_SEARCH_NN) return launch_mode<64, MODE_NN>(a, lds, s);
+  return a.n <= 64 ? launch_exhaustive<64>(a, lds, s) : launch_exhaustive<128>(a, lds, s);
 }
 
 }  // namespace lagp
