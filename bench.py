@@ -147,6 +147,8 @@ def main() -> int:
     ap.add_argument("--serving-requests", type=int, default=400)
     ap.add_argument("--grid", action="store_true", help="also run the 2-d grid workload, FP64 and mixed")
     ap.add_argument("--grid-M", type=int, default=2000)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run 3 plain device-to-device copies of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -160,6 +162,16 @@ def main() -> int:
     from paper_1409_0074_amd import workloads as W
 
     lg.lib()
+    calib = None
+    if args.copy_calibration_mb > 0:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        calib = {"bytes_read": nbytes, "bytes_written": nbytes, "copies": 3}
+        del src, dst
     w = W.uniform8d(M=args.M, search=W.SEARCH_EXHAUSTIVE)
     prm = w.params
     M, nc = w.XX.shape[0], prm.ncand
@@ -219,6 +231,8 @@ def main() -> int:
                              f"FLOP/location x {M} locations per launch"},
         "status_nonzero": int((st != 0).sum()),
     }
+    if calib is not None:
+        result["copy_calibration"] = calib
 
     if not args.no_ray:
         Pr = lg.make_params(prm, search=W.SEARCH_RAY, numrays=10)

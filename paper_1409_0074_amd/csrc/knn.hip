@@ -60,9 +60,10 @@ __device__ void load_and_sort(const double* bd, const int32_t* bi, int count, do
 //     N, so structured designs such as grids are sampled without a regular
 //     pattern).  Ns is chosen so that about 2 N' rows of the full design are
 //     expected below that value.
-//  2. scan: one lane per location, each wave one slice of the design; every
-//     design row is read at a wave-uniform address (scalar loads) and shared
-//     by the 64 locations of the wave; rows with d2 <= threshold are appended
+//  2. scan: each lane holds up to 4 locations, each wave one slice of the
+//     design; every design row is read at a wave-uniform address (scalar
+//     loads) and shared by the wave's locations; rows with d2 <= threshold
+//     are appended
 //     to the location's buffer (capacity CAP) through a per-location atomic.
 //  3. merge: one workgroup per location keeps the exact ncand smallest
 //     (d2, row) keys of its buffer (LDS bitonic sorts, streaming when the
@@ -161,65 +162,73 @@ __global__ __launch_bounds__(64) void k_knn_tau_reduce(Knn2Args a, int parts) {
   a.cnt[q] = 0;
 }
 
+// Locations per lane in the scan: every row read (64 bytes of scalar loads
+// at p = 8) feeds QL distance computations per lane.
+template <int P>
+constexpr int scan_ql() { return P > 0 && P <= 8 ? 4 : 1; }
+
 template <int P>
 __global__ __launch_bounds__(64) void k_knn_scan(Knn2Args a) {
-  const int q = blockIdx.y * 64 + threadIdx.x;
-  const bool live = q < a.M;
+  constexpr int QL = scan_ql<P>();
+  constexpr int PD = P > 0 ? P : LAGP_MAX_DIM;
   const int p = P > 0 ? P : a.p;
-  double xq[P > 0 ? P : LAGP_MAX_DIM];
+  const int qb = blockIdx.y * 64 * QL + threadIdx.x;  // lane's locations: qb + 64u
+  double xq[QL][PD], tau[QL];
 #pragma unroll
-  for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k)
-    if (P > 0 || k < p) xq[k] = live ? a.XX[(int64_t)q * p + k] : 0.0;
-  const double tau = live ? a.tau[q] : -1.0;  // d2 >= 0: a dead lane never appends
+  for (int u = 0; u < QL; ++u) {
+    const int q = qb + 64 * u;
+    const bool live = q < a.M;
+#pragma unroll
+    for (int k = 0; k < PD; ++k)
+      if (P > 0 || k < p) xq[u][k] = live ? a.XX[(int64_t)q * p + k] : 0.0;
+    tau[u] = live ? a.tau[q] : -1.0;  // d2 >= 0: a dead slot never appends
+  }
   const int64_t i0 = (int64_t)blockIdx.x * a.slice;
   const int64_t i1 = i0 + a.slice < a.N ? i0 + a.slice : a.N;
   const cdouble* X = as_const(a.X);
-  // U rows per iteration so that their scalar loads are in flight together
-  constexpr int U = (P > 0 && P <= 4) ? 4 : 2;
-  int64_t i = i0;
-  for (; i + U <= i1; i += U) {
-    double s[U];
+  // U rows per iteration, one branch for the (rare) appends of all of them
+  constexpr int U = P > 0 && P <= 8 ? 4 : 1;
+  for (int64_t i = i0; i < i1; i += U) {
+    double s[U][QL];
+    bool hit = false;
+    double xr[U][PD];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const cdouble* xr = X + (i + u) * p;
-      double acc = 0.0;
+    for (int r = 0; r < U; ++r) {
+      const int64_t row = i + r < i1 ? i + r : i1 - 1;  // a clamped row repeats the last: skipped below
 #pragma unroll
-      for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k) {
-        if (P > 0 || k < p) {
-          const double d = xq[k] - xr[k];
-          acc = __builtin_fma(d, d, acc);
+      for (int k = 0; k < PD; ++k)
+        if (P > 0 || k < p) xr[r][k] = X[row * p + k];
+    }
+#pragma unroll
+    for (int r = 0; r < U; ++r) {
+#pragma unroll
+      for (int u = 0; u < QL; ++u) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < PD; ++k) {
+          if (P > 0 || k < p) {
+            const double d = xq[u][k] - xr[r][k];
+            acc = __builtin_fma(d, d, acc);
+          }
+        }
+        s[r][u] = acc;
+        hit |= (acc <= tau[u]) && (i + r < i1);
+      }
+    }
+    if (!hit) continue;
+#pragma unroll
+    for (int r = 0; r < U; ++r)
+#pragma unroll
+      for (int u = 0; u < QL; ++u) {
+        if (i + r < i1 && s[r][u] <= tau[u]) {
+          const int q = qb + 64 * u;
+          const int pos = atomicAdd(&a.cnt[q], 1);
+          if (pos < a.CAP) {
+            a.buf_d2[(int64_t)q * a.CAP + pos] = s[r][u];
+            a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)(i + r);
+          }
         }
       }
-      s[u] = acc;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (s[u] <= tau) {
-        const int pos = atomicAdd(&a.cnt[q], 1);
-        if (pos < a.CAP) {
-          a.buf_d2[(int64_t)q * a.CAP + pos] = s[u];
-          a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)(i + u);
-        }
-      }
-    }
-  }
-  for (; i < i1; ++i) {
-    const cdouble* xr = X + i * p;
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k) {
-      if (P > 0 || k < p) {
-        const double d = xq[k] - xr[k];
-        acc = __builtin_fma(d, d, acc);
-      }
-    }
-    if (acc <= tau) {
-      const int pos = atomicAdd(&a.cnt[q], 1);
-      if (pos < a.CAP) {
-        a.buf_d2[(int64_t)q * a.CAP + pos] = acc;
-        a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)i;
-      }
-    }
   }
 }
 
@@ -349,7 +358,14 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   hipLaunchKernelGGL(k_knn_tau_reduce, dim3(groups), dim3(64), 0, s, a, parts);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_knn_scan<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), groups), dim3(64), 0, s, a);
+  // scan: slices of the design x groups of 64 QL locations, about 8192 waves
+  const int sgroups = (a.M + 64 * scan_ql<P>() - 1) / (64 * scan_ql<P>());
+  int64_t nsl = (8192 + sgroups - 1) / sgroups;
+  const int64_t maxsl = (a.N + 1023) / 1024;
+  if (nsl > maxsl) nsl = maxsl;
+  if (nsl < 1) nsl = 1;
+  a.slice = (a.N + nsl - 1) / nsl;
+  hipLaunchKernelGGL(k_knn_scan<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), sgroups), dim3(64), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = knn2_merge_lds_bytes(a.S);
@@ -374,12 +390,6 @@ hipError_t launch_knn2(Knn2Args a, hipStream_t s) {
   while (gcd64(A, a.N) != 1) A += 2;
   a.sub_stride = A % a.N;
   if (a.N == 1) a.sub_stride = 0;
-  const int groups = (a.M + 63) / 64;
-  int64_t nsl = (8192 + groups - 1) / groups;
-  const int64_t maxsl = (a.N + 1023) / 1024;
-  if (nsl > maxsl) nsl = maxsl;
-  if (nsl < 1) nsl = 1;
-  a.slice = (a.N + nsl - 1) / nsl;
   switch (a.p) {
     case 1: return launch_knn2_p<1>(a, s);
     case 2: return launch_knn2_p<2>(a, s);

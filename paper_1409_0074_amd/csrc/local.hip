@@ -239,10 +239,10 @@ __device__ __forceinline__ void block_best(const Lds& L, Best b) {
 }
 
 // Score every available candidate at design size j, exactly in the defined
-// order, on f64 MFMA.  v_mfma_f64_16x16x4f64 computes D = C + sum_k A[.][k]
-// B[k][.] as a chain of fused multiply-adds in ascending k (checked bit for
-// bit on gfx950), so chaining it over K-chunks in ascending order gives the
-// sequential sums of the definitions:
+// order, on f64 MFMA.  v_mfma_f64_16x16x4f64 and v_mfma_f64_4x4x4f64 both
+// compute D = C + sum_k A[.][k] B[k][.] as a chain of fused multiply-adds in
+// ascending k (checked bit for bit on gfx950), so chaining them over K-chunks
+// in ascending order gives the sequential sums of the definitions:
 //   W[i][c]  = sum_k fma(Kinv[i][k], k_c[k])        (A = Kinv rows, B = k_c chunk)
 //   v_c      = (1+g) - sum_i fma(k_c[i], W[i][c])  (A = k_c chunk^T, B = W chunk;
 //                                                   the diagonal of D)
@@ -253,7 +253,8 @@ __device__ __forceinline__ void block_best(const Lds& L, Best b) {
 // of row block I holds W rows 16I + 4r + g: exactly the B operand of chunk
 // 4I + r, and the loaded k_c chunk is exactly the A operand of the v chain.
 // Rows and columns past j are zero, and fma(0, 0, s) = s, so the padding
-// leaves every sum unchanged.
+// leaves every sum unchanged (up to the sign of a zero sum, which no later
+// step can see: the scores square cov and subtract v from 1 + g).
 // Buffer resource over one location's candidate-row block (gfx9 word 3).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t kc_rsrc(const LocalArgs& a, const double* Kc) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(Kc), (short)0, a.kc_rows * a.ncs * 8, 0x00020000);
@@ -294,7 +295,12 @@ __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds
   // register set) is consumed at once by the v and cov chains, whose chunks
   // 4I .. 4I+3 are exactly that block's rows, so the chunk order stays
   // ascending and only one block of W is live.
-  v4d accv = {0.0, 0.0, 0.0, 0.0}, accc = {0.0, 0.0, 0.0, 0.0};
+  // The v and cov chains run on the four-block 4x4x4 FP64 MFMA (a quarter of
+  // the work of a 16x16x4 step): block b covers candidates 4b .. 4b+3, its
+  // operands A[b][i][k] (lane 16k + 4b + i) and B[b][k][n] (lane 16k + 4b + n)
+  // are exactly the loaded kernel-row chunk and a W register, and
+  // D[b][i][n] lands in lane 16i + 4b + n.
+  double accv = 0.0, accc = 0.0;
 #pragma unroll
   for (int I = 0; I < NRB; ++I) {
     v4d acc = {0.0, 0.0, 0.0, 0.0};
@@ -305,17 +311,16 @@ __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds
     for (int r = 0; r < 4; ++r) {
       const int q = 4 * I + r;
       if (q < NQ) {
-        accv = __builtin_amdgcn_mfma_f64_16x16x4f64(b[q], acc[r], accv, 0, 0, 0);
-        accc = __builtin_amdgcn_mfma_f64_16x16x4f64(L.kx[4 * q + g4], acc[r], accc, 0, 0, 0);
+        accv = __builtin_amdgcn_mfma_f64_4x4x4f64(b[q], acc[r], accv, 0, 0, 0);
+        accc = __builtin_amdgcn_mfma_f64_4x4x4f64(L.kx[4 * q + g4], acc[r], accc, 0, 0, 0);
       }
     }
   }
-  // D_v[n][n] sits in register n/4 of lane 16(n%4) + n; D_c[0][n] in register 0 of lane n
-  const int rsel = cl >> 2;
-  const double dv = rsel == 0 ? accv[0] : rsel == 1 ? accv[1] : rsel == 2 ? accv[2] : accv[3];
-  const double vsum = __shfl(dv, 16 * (cl & 3) + cl, 64);
+  // v_c is the diagonal entry of candidate c = 4b + i: lane 16(c%4) + c; the
+  // rows of the cov product are all equal, so every lane holds its column's.
+  const double vsum = __shfl(accv, 16 * (cl & 3) + cl, 64);
   const double v = (1.0 + a.g) - vsum;
-  const double cov = kxc[col] - accc[0];
+  const double cov = kxc[col] - accc;
   if (v > 0.0) return cov * cov / v;
   if (g4 == 0) *vflag = 1;
   return 0.0;
