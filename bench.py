@@ -24,6 +24,35 @@ import numpy as np
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of one exhaustive k_local launch over the uniform 8-d workload
+# (M = 1e4), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
+# `bench.py --steps 1 --warmup 0 --no-ray --no-cpu --no-serving
+# --copy-calibration-mb 1024`, each scaled by what the counter read for a
+# 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the
+# kernel sources it was taken on (sha256 below); otherwise reported as null.
+KERNEL_SOURCES = ("paper_1409_0074_amd/csrc/local.hip", "paper_1409_0074_amd/csrc/dev_math.h",
+                  "paper_1409_0074_amd/csrc/lagp_internal.h", "paper_1409_0074_amd/csrc/api.cpp")
+MEASURED_TRAFFIC = {"sha256": "61259b697c6a3af8a45b499663acc37c75f967f0258899169cdd25ced2430459",
+                    "bytes": 1.40436e+11, "fetch_kib": 66285304.4, "write_kib": 4577384.9}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(here, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def scoring_bytes(n0: int, n: int, ncand: int) -> float:
+    """Algorithmic bytes of exhaustive scoring per location: at design size j
+    the j kernel-row entries of each of the ncand - j remaining candidates
+    are read once, 8 j (ncand - j)."""
+    return float(sum(8.0 * j * (ncand - j) for j in range(n0, n)))
+
 
 def scoring_flops(n0: int, n: int, ncand: int) -> float:
     """Algorithmic FLOPs of exhaustive scoring per location: at design size j
@@ -207,6 +236,11 @@ def main() -> int:
 
     flops = scoring_flops(prm.n0, prm.n, nc) * M
     achieved = flops / (t_local / 1e3) / 1e12
+    nbytes = scoring_bytes(prm.n0, prm.n, nc) * M
+    achieved_gbs = nbytes / (t_local / 1e3) / 1e9
+    traffic = None
+    if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC["sha256"] == kernel_sources_sha256() and M == 10000:
+        traffic = MEASURED_TRAFFIC["bytes"]
     result = {
         "metric": "local-GP predictions/sec at N=1e6, n=50 (exhaustive vs ray); p99 latency",
         "value": round(value, 2),
@@ -224,11 +258,17 @@ def main() -> int:
                    "ncand": nc, "search": "exhaustive", "kernel": "separable gaussian, d=0.5, g=1e-6",
                    "parallelism": "one GPU, data parallel over locations"},
         "phases_ms": {"knn": round(float(t_knn), 3), "local_design": round(float(t_local), 3)},
-        "roofline": {"bound": "mfma", "kernel": "k_local (exhaustive scoring)", "achieved": round(achieved, 3),
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": None,
-                     "work": f"sum_j 2 j^2 (ncand - j), j = n0..n-1: {scoring_flops(prm.n0, prm.n, nc):.4g} "
-                             f"FLOP/location x {M} locations per launch"},
+        # the candidate rows stream from HBM once per step: 8.3 FLOP/B, under
+        # the FP64 ridge (78.6 TF/s / 8 TB/s = 9.8), so HBM is the bound
+        "roofline": {"bound": "hbm", "kernel": "k_local (exhaustive)", "achieved": round(achieved_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "work": f"sum_j 8 j (ncand - j), j = n0..n-1: {scoring_bytes(prm.n0, prm.n, nc):.4g} "
+                             f"B/location x {M} locations per launch",
+                     "mfma": {"achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                              "work": f"sum_j 2 j^2 (ncand - j): {scoring_flops(prm.n0, prm.n, nc):.4g} "
+                                      f"FLOP/location"}},
         "status_nonzero": int((st != 0).sum()),
     }
     if calib is not None:

@@ -142,7 +142,10 @@ int32_t lagp_candidates(const lagp_design* design, const double* XX, int64_t M, 
  * two best ray optima); status (nullable, M int32) LAGP_STATUS_* bits.
  * Locations are independent; their results do not depend on M or on which
  * other locations share the call.  Workspace is allocated on the stream
- * (stream-ordered) and released on it.  The call is asynchronous: it
+ * (stream-ordered) and released on it; locations are processed in chunks
+ * whose workspace fits a budget (16 GiB, or LAGP_WORKSPACE_MB from the
+ * environment; about 0.5 MB per location at n = 50, N' = 1000, p = 8).
+ * The call is asynchronous: it
  * returns LAGP_OK once the work is enqueued, and numerical trouble at a
  * location shows only in its status word. */
 int32_t lagp_predict(const lagp_design* design, const double* XX, int64_t M, const lagp_params* params,

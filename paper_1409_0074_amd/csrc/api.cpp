@@ -31,7 +31,7 @@ size_t workspace_budget() {
     const long mb = std::atol(s);
     if (mb > 0) return (size_t)mb << 20;
   }
-  return (size_t)4 << 30;
+  return (size_t)16 << 30;  // a small share of the 288 GB of HBM
 }
 
 int max_lds_per_block() {
@@ -216,7 +216,8 @@ namespace lagp {
 
 // Bytes run_predict allocates for M locations under a workspace cap, and the
 // per-location figure (kNN buffers when candidates are not given, the kernel
-// rows, k(x_c, x), the starting-inverse scratch and a status word).
+// rows, k(x_c, x), the candidates' coordinates, the starting-inverse scratch
+// and a status word).
 size_t predict_per_location_bytes(const lagp_design* d, const lagp_params* P, bool have_cand) {
   const int n = P->n, nc = P->ncand;
   const int n0 = P->search == LAGP_SEARCH_NN ? n : P->n0;
@@ -224,10 +225,9 @@ size_t predict_per_location_bytes(const lagp_design* d, const lagp_params* P, bo
   const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? (n + 3) / 4 * 4 : n0;  // exact tiles read whole chunks
   const size_t b_knn = have_cand ? 0 : knn2_bytes_per_location(nc) + 1024;
   const size_t b_cand = have_cand ? 0 : sizeof(int32_t) * (size_t)nc;
-  (void)d;
   const size_t b_kc32 = P->precision == LAGP_PREC_MIXED ? sizeof(float) * (size_t)kc_rows * ncs : 0;
   return b_knn + b_cand + sizeof(double) * (size_t)kc_rows * ncs + b_kc32 + sizeof(double) * (size_t)ncs +
-         sizeof(double) * 2 * (size_t)n0 * n0 + sizeof(int32_t);
+         sizeof(double) * (size_t)ncs * d->p + sizeof(double) * 2 * (size_t)n0 * n0 + sizeof(int32_t);
 }
 
 int64_t predict_chunk(const lagp_design* d, const lagp_params* P, bool have_cand, int64_t M, size_t ws_budget) {
@@ -239,7 +239,7 @@ int64_t predict_chunk(const lagp_design* d, const lagp_params* P, bool have_cand
 size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool have_cand, int64_t M,
                                size_t ws_budget) {
   if (M <= 0) return 0;
-  return predict_per_location_bytes(d, P, have_cand) * (size_t)predict_chunk(d, P, have_cand, M, ws_budget) + 6 * 256;
+  return predict_per_location_bytes(d, P, have_cand) * (size_t)predict_chunk(d, P, have_cand, M, ws_budget) + 8 * 256;  // 8 aligned sections
 }
 
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
@@ -263,20 +263,22 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     return fail(LAGP_EINVAL, "local design too large for LDS (n, p, numrays)");
   const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? (n + 3) / 4 * 4 : n0;  // exact tiles read whole chunks
   // per-location workspace: kNN buffers and candidate list (unless given),
-  // kernel rows, k(x_c, x), starting-inverse scratch, status
+  // kernel rows, k(x_c, x), candidate coordinates, starting-inverse scratch,
+  // status
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t b_knn = cand_in ? 0 : knn2_bytes_per_location(nc) + 1024;
   const size_t b_cand = cand_in ? 0 : sizeof(int32_t) * (size_t)nc;
   const size_t b_kc = sizeof(double) * (size_t)kc_rows * ncs;
   const size_t b_kc32 = P->precision == LAGP_PREC_MIXED ? sizeof(float) * (size_t)kc_rows * ncs : 0;
   const size_t b_kxc = sizeof(double) * (size_t)ncs;
+  const size_t b_xc = sizeof(double) * (size_t)ncs * p;
   const size_t b_chol = sizeof(double) * 2 * (size_t)n0 * n0;
   const int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget);
   Workspace ws;
   ws.s = s;
   const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_kc = o_cand + al(b_cand * chunk),
                o_kc32 = o_kc + al(b_kc * chunk), o_kxc = o_kc32 + al(b_kc32 * chunk),
-               o_chol = o_kxc + al(b_kxc * chunk),
+               o_xc = o_kxc + al(b_kxc * chunk), o_chol = o_xc + al(b_xc * chunk),
                o_st = o_chol + al(b_chol * chunk), total = o_st + al(sizeof(int32_t) * chunk);
   LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
   char* base = reinterpret_cast<char*>(ws.ptr);
@@ -297,6 +299,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.Kc = reinterpret_cast<double*>(base + o_kc);
     a.Kc32 = b_kc32 ? reinterpret_cast<float*>(base + o_kc32) : nullptr;
     a.kxc = reinterpret_cast<double*>(base + o_kxc);
+    a.Xc = reinterpret_cast<double*>(base + o_xc);
     a.chol = reinterpret_cast<double*>(base + o_chol);
     a.mean = mean + m0;
     a.s2 = s2 + m0;

@@ -28,6 +28,7 @@ struct LocalArgs {
   double* Kc;          // workspace, M x n x ncs: K(x_{J_i}, x_c) rows
   float* Kc32;         // workspace (mixed form only), the same rows in FP32
   double* kxc;         // workspace, M x ncs: K(x_c, x)
+  double* Xc;          // workspace, M x ncs x p: candidate coordinates (rows past ncand zero)
   double* chol;        // workspace, M x n0 x n0 (starting inverse scratch)
   double* mean;
   double* s2;

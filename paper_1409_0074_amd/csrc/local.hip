@@ -184,6 +184,104 @@ __device__ __forceinline__ bool start_inverse(const LocalArgs& a, const Lds& L, 
 
 // ------------------------------------------------------- exhaustive ------
 
+// Gaussian correlation with the dimension loop unrolled to PM >= p (same
+// arithmetic as corr(): t = u_k - v_k, first argument first).
+template <int PM>
+__device__ __forceinline__ double corr_pm(const double* u, const double* v, int p, const double* w, int dlen) {
+  double acc = 0.0;
+  if (dlen == 1) {
+#pragma unroll
+    for (int k = 0; k < PM; ++k)
+      if (k < p) {
+        const double t = u[k] - v[k];
+        acc = __builtin_fma(t, t, acc);
+      }
+    return gexp(-(acc * w[0]));
+  }
+#pragma unroll
+  for (int k = 0; k < PM; ++k)
+    if (k < p) {
+      const double t = u[k] - v[k];
+      acc = __builtin_fma(t * t, w[k], acc);
+    }
+  return gexp(-acc);
+}
+
+// Candidates handled per thread and pass when gathering coordinates (their
+// loads are all issued before the first use), by the unrolled dimension.
+template <int PM>
+constexpr int gather_width() { return PM <= 8 ? 4 : 1; }
+
+// Prologue, one pass over the candidates (thread t takes c = t + k*blockDim):
+// gather x_c into Xc, K(x_c, x) into kxc, and the n0 starting rows
+// K(x_{J_i}, x_c) for c < kcols.  Rows past ncand hold zeros.
+template <int PM>
+__device__ __forceinline__ void gather_candidates(const LocalArgs& a, const Lds& L, const int32_t* C, double* Xc,
+                                                  double* Kc, float* Kc32, double* kxc, int n0, int kcols) {
+  constexpr int GATHER = gather_width<PM>();
+  const int p = a.p, nc = a.ncand, ncs = a.ncs, nt = blockDim.x;
+  for (int c0 = threadIdx.x; c0 < ncs; c0 += GATHER * nt) {
+    int64_t row[GATHER];
+#pragma unroll
+    for (int u = 0; u < GATHER; ++u) {
+      const int c = c0 + u * nt;
+      row[u] = c < nc ? (int64_t)C[c] : 0;
+    }
+    double r[GATHER][PM];
+#pragma unroll
+    for (int u = 0; u < GATHER; ++u)
+#pragma unroll
+      for (int k = 0; k < PM; ++k) r[u][k] = a.X[row[u] * p + (k < p ? k : 0)];  // always in bounds
+#pragma unroll
+    for (int u = 0; u < GATHER; ++u) {
+      const int c = c0 + u * nt;
+      if (c >= ncs) break;
+      const bool live = c < nc;
+#pragma unroll
+      for (int k = 0; k < PM; ++k) {
+        if (!live) r[u][k] = 0.0;
+        if (k < p) Xc[(int64_t)c * p + k] = r[u][k];
+      }
+      kxc[c] = live ? corr_pm<PM>(r[u], L.x, p, a.w, a.dlen) : 0.0;
+      if (c < kcols)
+        for (int i = 0; i < n0; ++i) {
+          const double kv = live ? corr_pm<PM>(L.xj + i * p, r[u], p, a.w, a.dlen) : 0.0;
+          Kc[(int64_t)i * ncs + c] = kv;
+          if (Kc32) Kc32[(int64_t)i * ncs + c] = (float)kv;
+        }
+    }
+  }
+}
+
+// New kernel row K(x_s, x_c) for every candidate from the gathered
+// coordinates (each thread reads back the rows it gathered).
+template <int PM>
+__device__ __forceinline__ void kernel_row(const LocalArgs& a, const double* xs, const double* Xc, double* row,
+                                           float* row32) {
+  constexpr int GATHER = gather_width<PM>();
+  const int p = a.p, nc = a.ncand, ncs = a.ncs, nt = blockDim.x;
+  double s[PM];
+#pragma unroll
+  for (int k = 0; k < PM; ++k) s[k] = k < p ? xs[k] : 0.0;
+  for (int c0 = threadIdx.x; c0 < ncs; c0 += GATHER * nt) {
+    double r[GATHER][PM];
+#pragma unroll
+    for (int u = 0; u < GATHER; ++u) {
+      const int c = c0 + u * nt < ncs ? c0 + u * nt : ncs - 1;  // in bounds
+#pragma unroll
+      for (int k = 0; k < PM; ++k) r[u][k] = Xc[(int64_t)c * p + (k < p ? k : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < GATHER; ++u) {
+      const int c = c0 + u * nt;
+      if (c >= ncs) break;
+      const double kv = c < nc ? corr_pm<PM>(s, r[u], p, a.w, a.dlen) : 0.0;
+      row[c] = kv;
+      if (row32) row32[c] = (float)kv;
+    }
+  }
+}
+
 struct Best {
   double v1, v2;
   int i1;
@@ -513,16 +611,16 @@ __device__ __forceinline__ Best score_mixed(const LocalArgs& a, const Lds& L, in
 // partitioned inverse of Sec. 3.1), append cs to the design, and compute its
 // kernel row against every candidate.  Returns v_j of the added point.
 __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc, float* Kc32, const double* kxc,
-                            const int32_t* C, int j, int cs) {
+                            const double* Xc, int j, int cs) {
   const int tid = threadIdx.x;
   const int ncs = a.ncs, p = a.p;
-  const double* xs = a.X + (int64_t)C[cs] * p;
-  if (a.search == LAGP_SEARCH_EXHAUSTIVE) {
-    for (int i = tid; i < j; i += blockDim.x) L.col[i] = Kc[(int64_t)i * ncs + cs];
-  } else {
-    // same arguments as the stored rows K(x_{J_i}, x_c), hence the same bits
-    for (int i = tid; i < j; i += blockDim.x) L.col[i] = corr(L.xj + i * p, xs, p, a.w, a.dlen);
-  }
+  // the new point's coordinates (gathered in the prologue) join the design's
+  for (int k = tid; k < p; k += blockDim.x) L.xj[j * p + k] = Xc[(int64_t)cs * p + k];
+  __syncthreads();
+  const double* xs = L.xj + j * p;
+  // K(x_J, x_s): the same arguments, in the same order, as the stored rows
+  // K(x_{J_i}, x_c) (design point first), hence the same bits
+  for (int i = tid; i < j; i += blockDim.x) L.col[i] = corr(L.xj + i * p, xs, p, a.w, a.dlen);
   __syncthreads();
   // Kinv is exactly symmetric (every update adds g_i g_k v with
   // g_i g_k == g_k g_i), so thread i reads column i: same values, same
@@ -556,13 +654,17 @@ __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, in
     L.selm[cs] = 1;
     L.kx[j] = kxc[cs];
   }
-  for (int k = tid; k < p; k += blockDim.x) L.xj[j * p + k] = xs[k];
   if (j + 1 < a.n && a.search == LAGP_SEARCH_EXHAUSTIVE) {
     double* row = Kc + (int64_t)j * ncs;
-    for (int c = tid; c < ncs; c += blockDim.x) {
-      const double kv = (c < a.ncand) ? corr(xs, a.X + (int64_t)C[c] * p, p, a.w, a.dlen) : 0.0;
-      row[c] = kv;
-      if (Kc32) Kc32[(int64_t)j * ncs + c] = (float)kv;
+    float* row32 = Kc32 ? Kc32 + (int64_t)j * ncs : nullptr;
+    if (p <= 8) {
+      kernel_row<8>(a, xs, Xc, row, row32);
+    } else {
+      for (int c = tid; c < ncs; c += blockDim.x) {
+        const double kv = c < a.ncand ? corr(xs, Xc + (int64_t)c * p, p, a.w, a.dlen) : 0.0;
+        row[c] = kv;
+        if (row32) row32[c] = (float)kv;
+      }
     }
   }
   __syncthreads();
@@ -728,7 +830,8 @@ __device__ __forceinline__ double brent_ray(const LocalArgs& a, const Lds& L, in
 // One ray-search step at design size j: returns the chosen candidate rank,
 // the best and runner-up ray values in *b1, *b2.
 template <int P>
-__device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, int j, int n0, double* b1,
+__device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, const double* Xc, int j,
+                                       int n0, double* b1,
                         double* b2, int* vflag) {
   constexpr int PM = RayRegs<P>::PM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -832,7 +935,7 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
     bool start = false;
     for (int r = 0; r < ns; ++r) start |= (L.starts[r] == c);
     if (start) continue;
-    const double* xc = a.X + (int64_t)C[c] * p;
+    const double* xc = Xc + (int64_t)c * p;  // gathered by this thread in the prologue
     double acc = 0.0;
     for (int k = 0; k < p; ++k) {
       const double zk = __builtin_fma(sw, dr[k], ar[k]);
@@ -884,19 +987,18 @@ __global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(2
   // kernel vector to x, and the starting rows of the kernel matrix
   // exhaustive search keeps whole kernel rows; otherwise only K_J is needed
   const int kcols = (a.search == LAGP_SEARCH_EXHAUSTIVE) ? ncs : n0;
-  for (int c = tid; c < ncs; c += blockDim.x) kxc[c] = (c < nc) ? corr(a.X + (int64_t)C[c] * p, L.x, p, a.w, a.dlen) : 0.0;
-  for (int t = tid; t < n0 * kcols; t += blockDim.x) {
-    const int i = t / kcols, c = t - i * kcols;
-    const double kv = (c < nc) ? corr(a.X + (int64_t)C[i] * p, a.X + (int64_t)C[c] * p, p, a.w, a.dlen) : 0.0;
-    Kc[(int64_t)i * ncs + c] = kv;
-    if (Kc32) Kc32[(int64_t)i * ncs + c] = (float)kv;
-  }
+  double* Xc = a.Xc + (int64_t)m * ncs * p;
   for (int i = tid; i < n0; i += blockDim.x) {
     L.J[i] = i;
     L.selm[i] = 1;
   }
   for (int t = tid; t < n0 * p; t += blockDim.x) L.xj[t] = a.X[(int64_t)C[t / p] * p + (t % p)];
   if (tid == 0) L.ints[4] = 0;
+  __syncthreads();
+  if (p <= 8)
+    gather_candidates<8>(a, L, C, Xc, Kc, Kc32, kxc, n0, kcols);
+  else
+    gather_candidates<LAGP_MAX_DIM>(a, L, C, Xc, Kc, Kc32, kxc, n0, kcols);
   __syncthreads();
   for (int i = tid; i < n0; i += blockDim.x) L.kx[i] = kxc[i];
   const bool pd = start_inverse(a, L, LD, Kc, Li, n0);
@@ -908,7 +1010,7 @@ __global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(2
       int cs;
       double b1, b2;
       if constexpr (MODE == MODE_RAY) {
-        cs = ray_step<P>(a, L, LD, C, j, n0, &b1, &b2, &vflag);
+        cs = ray_step<P>(a, L, LD, C, Xc, j, n0, &b1, &b2, &vflag);
       } else if constexpr (MODE == MODE_NN) {
         cs = -1;  // (the nearest neighbours fill the design: no step runs)
         b1 = b2 = 0.0;
@@ -924,7 +1026,7 @@ __global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(2
         b2 = L.scal[2];
       }
       if (cs < 0 || cs >= nc) break;  // no finite score anywhere: give up on x
-      const double v = add_point(a, L, LD, Kc, Kc32, kxc, C, j, cs);
+      const double v = add_point(a, L, LD, Kc, Kc32, kxc, Xc, j, cs);
       done = j + 1;
       if (!(v > 0.0)) vflag = 1;
       if (tid == 0 && a.diag) {
