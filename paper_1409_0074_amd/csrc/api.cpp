@@ -94,9 +94,12 @@ bool force_knn_fallback() {
 
 // Threshold-first kNN arguments over a workspace laid out as
 // [tau: chunk doubles][cnt: chunk ints][d2: chunk*CAP doubles][row: chunk*CAP ints].
+// ws: per-location buffers for `chunk` locations; sub: the per-call
+// subsample block (knn2_shared_bytes).
 lagp::Knn2Args knn_args(const lagp_design* d, const double* XX, int32_t M, int ncand, void* ws, int64_t chunk,
-                        int32_t* out_idx, double* out_d2) {
+                        void* sub, int32_t* out_idx, double* out_d2) {
   lagp::Knn2Args k{};
+  k.sub = reinterpret_cast<double*>(sub);
   const size_t cap = (lagp::knn2_bytes_per_location(ncand) - sizeof(double) - sizeof(int32_t)) /
                      (sizeof(double) + sizeof(int32_t));
   char* b = reinterpret_cast<char*>(ws);
@@ -196,15 +199,18 @@ int32_t lagp_candidates(const lagp_design* d, const double* XX, int64_t M, int32
   const int S = lagp::knn_sort_size(ncand);
   if (lagp::knn2_merge_lds_bytes(S) > (size_t)max_lds_per_block()) return fail(LAGP_EINVAL, "ncand too large for LDS");
   const size_t per = lagp::knn2_bytes_per_location(ncand);
+  const size_t shared = lagp::knn2_shared_bytes(d->N, d->p, ncand);
   int64_t chunk = std::max<int64_t>(64, (int64_t)(workspace_budget() / per));
   chunk = std::min<int64_t>(chunk, M);
+  const size_t o_sub = (per * chunk + 1024 + 255) & ~size_t(255);
   Workspace ws;
   ws.s = s;
-  LAGP_HIP(hipMallocAsync(&ws.ptr, per * chunk + 1024, s));
+  LAGP_HIP(hipMallocAsync(&ws.ptr, o_sub + shared, s));
+  char* base = reinterpret_cast<char*>(ws.ptr);
   for (int64_t m0 = 0; m0 < M; m0 += chunk) {
     const int32_t mc = (int32_t)std::min<int64_t>(chunk, M - m0);
-    LAGP_HIP(lagp::launch_knn2(knn_args(d, XX + m0 * d->p, mc, ncand, ws.ptr, chunk, cand_idx + m0 * ncand,
-                                        cand_d2 ? cand_d2 + m0 * ncand : nullptr),
+    LAGP_HIP(lagp::launch_knn2(knn_args(d, XX + m0 * d->p, mc, ncand, base, chunk, base + o_sub,
+                                        cand_idx + m0 * ncand, cand_d2 ? cand_d2 + m0 * ncand : nullptr),
                                s));
   }
   return LAGP_OK;
@@ -239,7 +245,9 @@ int64_t predict_chunk(const lagp_design* d, const lagp_params* P, bool have_cand
 size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool have_cand, int64_t M,
                                size_t ws_budget) {
   if (M <= 0) return 0;
-  return predict_per_location_bytes(d, P, have_cand) * (size_t)predict_chunk(d, P, have_cand, M, ws_budget) + 8 * 256;  // 8 aligned sections
+  const size_t shared = have_cand ? 0 : knn2_shared_bytes(d->N, d->p, P->ncand);
+  return predict_per_location_bytes(d, P, have_cand) * (size_t)predict_chunk(d, P, have_cand, M, ws_budget) +
+         shared + 9 * 256;  // 9 aligned sections
 }
 
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
@@ -279,14 +287,15 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_kc = o_cand + al(b_cand * chunk),
                o_kc32 = o_kc + al(b_kc * chunk), o_kxc = o_kc32 + al(b_kc32 * chunk),
                o_xc = o_kxc + al(b_kxc * chunk), o_chol = o_xc + al(b_xc * chunk),
-               o_st = o_chol + al(b_chol * chunk), total = o_st + al(sizeof(int32_t) * chunk);
+               o_st = o_chol + al(b_chol * chunk), o_sub = o_st + al(sizeof(int32_t) * chunk),
+               total = o_sub + (cand_in ? 0 : knn2_shared_bytes(d->N, p, nc));
   LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
   char* base = reinterpret_cast<char*>(ws.ptr);
   for (int64_t m0 = 0; m0 < M; m0 += chunk) {
     const int32_t mc = (int32_t)std::min<int64_t>(chunk, M - m0);
     const int32_t* cand = cand_in ? cand_in + m0 * nc : reinterpret_cast<const int32_t*>(base + o_cand);
     if (!cand_in)
-      LAGP_HIP(launch_knn2(knn_args(d, XX + m0 * p, mc, nc, base + o_knn, chunk,
+      LAGP_HIP(launch_knn2(knn_args(d, XX + m0 * p, mc, nc, base + o_knn, chunk, base + o_sub,
                                     reinterpret_cast<int32_t*>(base + o_cand), nullptr),
                            s));
     lagp::LocalArgs a{};

@@ -55,11 +55,12 @@ __device__ void load_and_sort(const double* bd, const int32_t* bi, int count, do
 // ------------------------------------------------ threshold-first kNN ---
 //
 // For large designs the lists come from three passes:
-//  1. threshold: one lane per location; the KT-th smallest squared distance
-//     over a subsample of the design (rows t*A mod N, t < Ns, A coprime with
-//     N, so structured designs such as grids are sampled without a regular
-//     pattern).  Ns is chosen so that about 2 N' rows of the full design are
-//     expected below that value.
+//  1. threshold: one lane per location; the KSEL-th smallest squared
+//     distance over a subsample of the design (rows t*A mod N, t < Ns, A
+//     coprime with N, gathered once per call).  Ns = N / r with
+//     r = 2 N' / KSEL, so that about 2 N' rows of the full design fall below
+//     that value (relative spread 1/sqrt(KSEL): fewer than N' with
+//     probability ~3e-5).
 //  2. scan: each lane holds up to 4 locations, each wave one slice of the
 //     design; every design row is read at a wave-uniform address (scalar
 //     loads) and shared by the wave's locations; rows with d2 <= threshold
@@ -73,7 +74,9 @@ __device__ void load_and_sort(const double* bd, const int32_t* bi, int count, do
 // Every key and order is exact; the threshold only decides how much work is
 // done, never which rows are returned.
 
-constexpr int KT = 32;  // subsample order statistic
+constexpr int KT = 16;    // per-part list length of the threshold pass
+constexpr int KSEL = 64;  // subsample order statistic taken as the threshold
+static_assert(16 * KT <= 256 && KSEL <= 256, "the reduce sorts at most 256 values per location");
 
 // The design never changes while these kernels run: reading it through the
 // constant address space lets wave-uniform row reads become scalar loads
@@ -81,17 +84,30 @@ constexpr int KT = 32;  // subsample order statistic
 typedef const double __attribute__((address_space(4))) cdouble;
 __device__ __forceinline__ const cdouble* as_const(const double* p) { return (const cdouble*)p; }
 
+// Subsample gather: row t of the subsample is design row t*A mod N (A coprime
+// with N, so structured designs such as grids are sampled without a regular
+// pattern); stored contiguously so the threshold pass streams it.
+__global__ __launch_bounds__(256) void k_knn_gather_sub(Knn2Args a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.sub_count * a.p) return;
+  const int64_t row = t / a.p, k = t - row * a.p;
+  const int64_t src = (row * a.sub_stride) % a.N;  // row, stride < 2^31: no overflow
+  a.sub[t] = a.X[src * a.p + k];
+}
+
 // Threshold pass, part 1: wave (w, group) takes subsample rows
-// t = w*Ns/TS .. (w+1)*Ns/TS - 1 and leaves, per location, its KT smallest
-// squared distances in the location's buffer (scratch until the scan).
+// t = w*Ns/parts .. (w+1)*Ns/parts - 1 and leaves, per location, its KT
+// smallest squared distances in the location's buffer (scratch until the
+// scan).
 template <int P>
 __global__ __launch_bounds__(64) void k_knn_tau(Knn2Args a) {
+  constexpr int PD = P > 0 ? P : LAGP_MAX_DIM;
   const int q = blockIdx.y * 64 + threadIdx.x;
   const bool live = q < a.M;
   const int p = P > 0 ? P : a.p;
-  double xq[P > 0 ? P : LAGP_MAX_DIM];
+  double xq[PD];
 #pragma unroll
-  for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k)
+  for (int k = 0; k < PD; ++k)
     if (P > 0 || k < p) xq[k] = live ? a.XX[(int64_t)q * p + k] : 0.0;
   double best[KT];
 #pragma unroll
@@ -99,32 +115,39 @@ __global__ __launch_bounds__(64) void k_knn_tau(Knn2Args a) {
   double cur = __builtin_huge_val();
   const int64_t t0 = (a.sub_count * blockIdx.x) / gridDim.x;
   const int64_t t1 = (a.sub_count * (blockIdx.x + 1)) / gridDim.x;
-  int64_t idx = (t0 * a.sub_stride) % a.N;  // t0, stride < N < 2^31: no overflow
-  for (int64_t t = t0; t < t1; ++t) {
-    const cdouble* xr = as_const(a.X) + idx * p;
-    double s = 0.0;
+  const cdouble* X = as_const(a.sub);
+  constexpr int U = 4;  // rows per iteration, their loads issued together
+  for (int64_t t = t0; t < t1; t += U) {
+    double s[U];
 #pragma unroll
-    for (int k = 0; k < (P > 0 ? P : LAGP_MAX_DIM); ++k) {
-      if (P > 0 || k < p) {
-        const double u = xq[k] - xr[k];
-        s = __builtin_fma(u, u, s);
-      }
-    }
-    if (s < cur) {
-      bool done = false;
-      double mx = 0.0;
+    for (int r = 0; r < U; ++r) {
+      const int64_t row = t + r < t1 ? t + r : t1 - 1;
+      double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < KT; ++k) {
-        if (!done && best[k] == cur) {
-          best[k] = s;
-          done = true;
+      for (int k = 0; k < PD; ++k) {
+        if (P > 0 || k < p) {
+          const double u = xq[k] - X[row * p + k];
+          acc = __builtin_fma(u, u, acc);
         }
-        mx = fmax(mx, best[k]);
       }
-      cur = mx;
+      s[r] = t + r < t1 ? acc : __builtin_huge_val();
     }
-    idx += a.sub_stride;
-    if (idx >= a.N) idx -= a.N;
+#pragma unroll
+    for (int r = 0; r < U; ++r) {
+      if (s[r] < cur) {
+        bool done = false;
+        double mx = 0.0;
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+          if (!done && best[k] == cur) {
+            best[k] = s[r];
+            done = true;
+          }
+          mx = fmax(mx, best[k]);
+        }
+        cur = mx;
+      }
+    }
   }
   if (live) {
     double* dst = a.buf_d2 + (int64_t)q * a.CAP + blockIdx.x * KT;
@@ -133,33 +156,37 @@ __global__ __launch_bounds__(64) void k_knn_tau(Knn2Args a) {
   }
 }
 
-// Threshold pass, part 2: the KT-th smallest over the partial lists.
+// Threshold pass, part 2: the KSEL-th smallest over the partial lists (the
+// KSEL-th smallest of the subsample unless one part held more than KT of the
+// KSEL smallest; either way only the amount of work depends on it).  One
+// 64-thread block per location sorts the parts * KT <= 256 values in LDS.
 __global__ __launch_bounds__(64) void k_knn_tau_reduce(Knn2Args a, int parts) {
-  const int q = blockIdx.x * 64 + threadIdx.x;
-  if (q >= a.M) return;
-  double best[KT];
-#pragma unroll
-  for (int k = 0; k < KT; ++k) best[k] = __builtin_huge_val();
-  double cur = __builtin_huge_val();
+  __shared__ double v[256];
+  const int q = blockIdx.x;
   const double* src = a.buf_d2 + (int64_t)q * a.CAP;
-  for (int t = 0; t < parts * KT; ++t) {
-    const double s = src[t];
-    if (s < cur) {
-      bool done = false;
-      double mx = 0.0;
-#pragma unroll
-      for (int k = 0; k < KT; ++k) {
-        if (!done && best[k] == cur) {
-          best[k] = s;
-          done = true;
+  const int nv = parts * KT;
+  for (int t = threadIdx.x; t < 256; t += 64) v[t] = t < nv ? src[t] : __builtin_huge_val();
+  __syncthreads();
+  for (int size = 2; size <= 256; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const int ls = __builtin_ctz(stride);
+      for (int t = threadIdx.x; t < 128; t += 64) {
+        const int lo = ((t >> ls) << (ls + 1)) + (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const double x = v[lo], y = v[hi];
+        if (up ? (y < x) : (x < y)) {
+          v[lo] = y;
+          v[hi] = x;
         }
-        mx = fmax(mx, best[k]);
       }
-      cur = mx;
+      __syncthreads();
     }
   }
-  a.tau[q] = a.force_fallback ? -1.0 : cur;
-  a.cnt[q] = 0;
+  if (threadIdx.x == 0) {
+    a.tau[q] = a.force_fallback ? -1.0 : v[KSEL - 1];
+    a.cnt[q] = 0;
+  }
 }
 
 // Locations per lane in the scan: every row read (64 bytes of scalar loads
@@ -333,6 +360,16 @@ static int64_t gcd64(int64_t x, int64_t y) {
   return x;
 }
 
+int64_t knn2_sub_rows(int64_t N, int ncand) {
+  int64_t r = (2 * (int64_t)ncand) / KSEL;
+  if (r < 1) r = 1;
+  return (N + r - 1) / r;
+}
+
+size_t knn2_shared_bytes(int64_t N, int p, int ncand) {
+  return ((size_t)knn2_sub_rows(N, ncand) * p * sizeof(double) + 255) & ~size_t(255);
+}
+
 int knn2_capacity(int ncand) {
   const int S = knn_sort_size(ncand);
   return 4 * ncand > S ? 4 * ncand : S;
@@ -347,15 +384,20 @@ size_t knn2_merge_lds_bytes(int S) { return (size_t)S * (sizeof(double) + sizeof
 template <int P>
 static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   const int groups = (a.M + 63) / 64;
-  // enough subsample parts to occupy the chip; KT * parts <= 512 <= CAP
+  // enough subsample parts to occupy the chip; KSEL <= KT * parts <= 256 <= CAP
   int parts = (2048 + groups - 1) / groups;
   if (parts > 16) parts = 16;
+  if (parts < KSEL / KT) parts = KSEL / KT;
   if ((int64_t)parts > a.sub_count) parts = (int)a.sub_count;
   if (parts < 1) parts = 1;
-  hipLaunchKernelGGL(k_knn_tau<P>, dim3(parts, groups), dim3(64), 0, s, a);
+  const int64_t gn = a.sub_count * a.p;
+  hipLaunchKernelGGL(k_knn_gather_sub, dim3((unsigned)((gn + 255) / 256)), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_knn_tau_reduce, dim3(groups), dim3(64), 0, s, a, parts);
+  hipLaunchKernelGGL(k_knn_tau<P>, dim3(parts, groups), dim3(64), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_knn_tau_reduce, dim3(a.M), dim3(64), 0, s, a, parts);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // scan: slices of the design x groups of 64 QL locations, about 8192 waves
@@ -382,9 +424,7 @@ hipError_t launch_knn2(Knn2Args a, hipStream_t s) {
   a.CAP = knn2_capacity(a.ncand);
   // subsample: r rows per sample so that about r * KT ~ 2 ncand rows fall
   // under the KT-th smallest sampled distance
-  int64_t r = (2 * (int64_t)a.ncand) / KT;
-  if (r < 1) r = 1;
-  a.sub_count = (a.N + r - 1) / r;
+  a.sub_count = knn2_sub_rows(a.N, a.ncand);
   int64_t A = (int64_t)((double)a.N * 0.6180339887498949) | 1;
   if (A >= a.N) A = 1;
   while (gcd64(A, a.N) != 1) A += 2;

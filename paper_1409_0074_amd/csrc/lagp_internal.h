@@ -58,6 +58,7 @@ struct Knn2Args {
   double* buf_d2;     // workspace, M x CAP
   int32_t* buf_idx;   // workspace, M x CAP
   int32_t* out_idx;   // M x ncand
+  double* sub;        // workspace, sub_count x p: the threshold subsample
   double* out_d2;     // nullable, M x ncand
   int64_t N;
   int64_t sub_stride;
@@ -77,6 +78,8 @@ constexpr int LOCAL_THREADS = 256;
 
 int knn_sort_size(int ncand);
 hipError_t launch_knn2(Knn2Args a, hipStream_t s);
+int64_t knn2_sub_rows(int64_t N, int ncand);
+size_t knn2_shared_bytes(int64_t N, int p, int ncand);  // per call, beside the per-location buffers
 size_t knn2_bytes_per_location(int ncand);
 size_t knn2_merge_lds_bytes(int S);
 
