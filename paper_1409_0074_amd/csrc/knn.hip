@@ -61,11 +61,10 @@ __device__ void load_and_sort(const double* bd, const int32_t* bi, int count, do
 //     r = 2 N' / KSEL, so that about 2 N' rows of the full design fall below
 //     that value (relative spread 1/sqrt(KSEL): fewer than N' with
 //     probability ~3e-5).
-//  2. scan: each lane holds up to 4 locations, each wave one slice of the
-//     design; every design row is read at a wave-uniform address (scalar
-//     loads) and shared by the wave's locations; rows with d2 <= threshold
-//     are appended
-//     to the location's buffer (capacity CAP) through a per-location atomic.
+//  2. scan: each wave takes 64 locations and one slice of the design, screens
+//     16 rows at a time with MFMA inner products, and appends the rows with
+//     d2 <= threshold to the location's buffer (capacity CAP) through a
+//     per-location atomic.
 //  3. merge: one workgroup per location keeps the exact ncand smallest
 //     (d2, row) keys of its buffer (LDS bitonic sorts, streaming when the
 //     buffer exceeds the sort size).  If the threshold caught fewer than
@@ -189,74 +188,161 @@ __global__ __launch_bounds__(64) void k_knn_tau_reduce(Knn2Args a, int parts) {
   }
 }
 
-// Locations per lane in the scan: every row read (64 bytes of scalar loads
-// at p = 8) feeds QL distance computations per lane.
-template <int P>
-constexpr int scan_ql() { return P > 0 && P <= 8 ? 4 : 1; }
+typedef double v4d __attribute__((ext_vector_type(4)));
 
+// Scan with an MFMA distance screen.  For 64 locations (four sets of 16) and
+// a tile of 16 design rows, 16x16x4 FP64 MFMAs give the inner products
+// <x_q, x_i>; t = ||x_i||^2 - 2 <x_q, x_i> then approximates d2 - ||x_q||^2.
+// With u = 2^-53, the defined squared distance (an fma chain over the
+// dimensions) is within (p+2)u d2 of the true one, and t within
+// (2p+6)u (||x_q||^2 + 2 max_i ||x_i||^2) of its true value, so the screen
+// t <= tau (1 + 2(p+2)u) - ||x_q||^2 + 4(p+4)u (||x_q||^2 + 2 max ||x_i||^2)
+// (twice each bound) passes every row whose defined squared distance is
+// <= tau.  Passing rows get the defined squared distance and are appended
+// only if it is <= tau: the rows collected are exactly those of a plain scan
+// (in another order, which the merge's sort by (d2, row) removes).
+// MFMA operands: A[i][k] from lane 16k + i (location 16s + i, dimension
+// 4c + k), B[k][n] from lane 16k + n (row n of the tile, dimension 4c + k),
+// D[i][n] in register i/4 of lane 16(i%4) + n.
 template <int P>
 __global__ __launch_bounds__(64) void k_knn_scan(Knn2Args a) {
-  constexpr int QL = scan_ql<P>();
   constexpr int PD = P > 0 ? P : LAGP_MAX_DIM;
+  constexpr int NCH = (PD + 3) / 4;  // K-chunks of 4 dimensions
   const int p = P > 0 ? P : a.p;
-  const int qb = blockIdx.y * 64 * QL + threadIdx.x;  // lane's locations: qb + 64u
-  double xq[QL][PD], tau[QL];
+  const int lane = threadIdx.x, g = lane >> 4, n = lane & 15;
+  const int q0 = blockIdx.y * 64;
+  double af[4][NCH];
 #pragma unroll
-  for (int u = 0; u < QL; ++u) {
-    const int q = qb + 64 * u;
-    const bool live = q < a.M;
+  for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int k = 0; k < PD; ++k)
-      if (P > 0 || k < p) xq[u][k] = live ? a.XX[(int64_t)q * p + k] : 0.0;
-    tau[u] = live ? a.tau[q] : -1.0;  // d2 >= 0: a dead slot never appends
-  }
+    for (int c = 0; c < NCH; ++c) {
+      const int q = q0 + 16 * s + n, d = 4 * c + g;
+      af[s][c] = (q < a.M && d < p) ? a.XX[(int64_t)q * p + d] : 0.0;
+    }
+  // screen bounds of this lane's outputs: set s, register r -> location
+  // q0 + 16 s + 4 r + g
+  const double u = 0x1p-53;
+  double th[4][4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = q0 + 16 * s + 4 * r + g;
+      double t = -__builtin_huge_val();
+      if (q < a.M) {
+        const double tau = a.tau[q];
+        double qn = 0.0;
+        for (int k = 0; k < p; ++k) qn = __builtin_fma(a.XX[(int64_t)q * p + k], a.XX[(int64_t)q * p + k], qn);
+        if (tau >= 0.0)
+          t = tau * (1.0 + 2.0 * (p + 2) * u) - qn + 4.0 * (p + 4) * u * (qn + 2.0 * a.rn_max);
+      }
+      th[s][r] = t;
+    }
   const int64_t i0 = (int64_t)blockIdx.x * a.slice;
   const int64_t i1 = i0 + a.slice < a.N ? i0 + a.slice : a.N;
-  const cdouble* X = as_const(a.X);
-  // U rows per iteration, one branch for the (rare) appends of all of them
-  constexpr int U = P > 0 && P <= 8 ? 4 : 1;
-  for (int64_t i = i0; i < i1; i += U) {
-    double s[U][QL];
-    bool hit = false;
-    double xr[U][PD];
-#pragma unroll
-    for (int r = 0; r < U; ++r) {
-      const int64_t row = i + r < i1 ? i + r : i1 - 1;  // a clamped row repeats the last: skipped below
-#pragma unroll
-      for (int k = 0; k < PD; ++k)
-        if (P > 0 || k < p) xr[r][k] = X[row * p + k];
-    }
-#pragma unroll
-    for (int r = 0; r < U; ++r) {
-#pragma unroll
-      for (int u = 0; u < QL; ++u) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < PD; ++k) {
-          if (P > 0 || k < p) {
-            const double d = xq[u][k] - xr[r][k];
-            acc = __builtin_fma(d, d, acc);
-          }
-        }
-        s[r][u] = acc;
-        hit |= (acc <= tau[u]) && (i + r < i1);
+  // Screened pairs are staged in LDS and settled in batches (one lane per
+  // pair): the defined squared distance, and for d2 <= tau an append to the
+  // location's buffer.
+  constexpr int STG = 2048;
+  __shared__ int32_t st_row[STG];
+  __shared__ uint8_t st_q[STG];
+  __shared__ int st_n;
+  if (lane == 0) st_n = 0;
+  __syncthreads();
+  auto flush = [&]() {
+    __syncthreads();
+    const int tot = st_n;
+    for (int e = lane; e < tot; e += 64) {
+      const int64_t row = st_row[e];
+      const int q = q0 + st_q[e];
+      const double* xq = a.XX + (int64_t)q * p;
+      const double* xr = a.X + row * p;
+      double acc = 0.0;
+      for (int k = 0; k < p; ++k) {
+        const double d = xq[k] - xr[k];
+        acc = __builtin_fma(d, d, acc);
       }
-    }
-    if (!hit) continue;
-#pragma unroll
-    for (int r = 0; r < U; ++r)
-#pragma unroll
-      for (int u = 0; u < QL; ++u) {
-        if (i + r < i1 && s[r][u] <= tau[u]) {
-          const int q = qb + 64 * u;
-          const int pos = atomicAdd(&a.cnt[q], 1);
-          if (pos < a.CAP) {
-            a.buf_d2[(int64_t)q * a.CAP + pos] = s[r][u];
-            a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)(i + r);
-          }
+      if (acc <= a.tau[q]) {
+        const int pos = atomicAdd(&a.cnt[q], 1);
+        if (pos < a.CAP) {
+          a.buf_d2[(int64_t)q * a.CAP + pos] = acc;
+          a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)row;
         }
       }
+    }
+    __syncthreads();
+    if (lane == 0) st_n = 0;
+    __syncthreads();
+  };
+  // the next tile's rows are loaded while the current one is screened
+  double bn[NCH], rnn;
+  auto load_tile = [&](int64_t i, double (&bf)[NCH], double& rn) {
+    const int64_t rr = i + n;
+    const int64_t rl = rr < i1 ? rr : i1 - 1;  // in bounds
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int d = 4 * c + g;
+      bf[c] = d < p ? a.X[rl * p + d] : 0.0;
+    }
+    rn = rr < i1 ? a.rn[rl] : __builtin_huge_val();
+  };
+  if (i0 < i1) load_tile(i0, bn, rnn);
+  for (int64_t i = i0; i < i1; i += 16) {
+    const int64_t rr = i + n;
+    const bool valid = rr < i1;
+    double bf[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) bf[c] = bn[c];
+    const double rn = rnn;
+    if (i + 16 < i1) load_tile(i + 16, bn, rnn);
+    unsigned hit = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s][c], bf[c], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (__builtin_fma(-2.0, acc[r], rn) <= th[s][r]) hit |= 1u << (4 * s + r);
+    }
+    if (!valid) hit = 0;  // (t = inf passes an infinite bound)
+    if (!__builtin_expect(__any(hit), 0)) continue;
+    // stage the screened pairs: (row, location within the wave's 64)
+    const int nh = __builtin_popcount(hit);
+    const int base = nh ? atomicAdd(&st_n, nh) : 0;
+    for (int k = 0; hit; ++k) {
+      const int b = __builtin_ctz(hit);  // b = 4 s + r: location 16 s + 4 r + g
+      hit &= hit - 1;
+      st_row[base + k] = (int32_t)rr;
+      st_q[base + k] = (uint8_t)(4 * b + g);
+    }
+    __syncthreads();
+    if (st_n > STG - 1024) flush();  // a tile stages at most 64 x 16
   }
+  flush();
+}
+
+// Squared row norms of the design and their maximum (for the scan's screen).
+__global__ __launch_bounds__(256) void k_row_norms(const double* X, int64_t N, int p, double* rn,
+                                                   unsigned long long* rmax_bits) {
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < p; ++k) s = __builtin_fma(X[i * p + k], X[i * p + k], s);
+    rn[i] = s;
+    m = fmax(m, s);
+  }
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  // non-negative doubles order like their bit patterns
+  if ((threadIdx.x & 63) == 0) atomicMax(rmax_bits, (unsigned long long)__builtin_bit_cast(long long, m));
+}
+
+hipError_t launch_row_norms(const double* X, int64_t N, int p, double* rn, double* rmax, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(rmax, 0, sizeof(double), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_norms, dim3(1024), dim3(256), 0, s, X, N, p, rn,
+                     reinterpret_cast<unsigned long long*>(rmax));
+  return hipGetLastError();
 }
 
 // Exact single-location scan with compaction (the fallback): the buffer
@@ -400,8 +486,8 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   hipLaunchKernelGGL(k_knn_tau_reduce, dim3(a.M), dim3(64), 0, s, a, parts);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // scan: slices of the design x groups of 64 QL locations, about 8192 waves
-  const int sgroups = (a.M + 64 * scan_ql<P>() - 1) / (64 * scan_ql<P>());
+  // scan: slices of the design x groups of 64 locations, about 8192 waves
+  const int sgroups = (a.M + 63) / 64;
   int64_t nsl = (8192 + sgroups - 1) / sgroups;
   const int64_t maxsl = (a.N + 1023) / 1024;
   if (nsl > maxsl) nsl = maxsl;

@@ -12,6 +12,8 @@ struct lagp_design {
   double* y;   // device, N
   double* lo;  // device, p: per-dimension minimum of X
   double* hi;  // device, p: per-dimension maximum of X
+  double* rn;  // device, N: squared row norms of X (screening only)
+  double rn_max;  // their maximum
   int device;
 };
 
@@ -59,6 +61,8 @@ struct Knn2Args {
   int32_t* buf_idx;   // workspace, M x CAP
   int32_t* out_idx;   // M x ncand
   double* sub;        // workspace, sub_count x p: the threshold subsample
+  const double* rn;   // N squared row norms of X
+  double rn_max;
   double* out_d2;     // nullable, M x ncand
   int64_t N;
   int64_t sub_stride;
@@ -78,6 +82,7 @@ constexpr int LOCAL_THREADS = 256;
 
 int knn_sort_size(int ncand);
 hipError_t launch_knn2(Knn2Args a, hipStream_t s);
+hipError_t launch_row_norms(const double* X, int64_t N, int p, double* rn, double* rmax, hipStream_t s);
 int64_t knn2_sub_rows(int64_t N, int ncand);
 size_t knn2_shared_bytes(int64_t N, int p, int ncand);  // per call, beside the per-location buffers
 size_t knn2_bytes_per_location(int ncand);
