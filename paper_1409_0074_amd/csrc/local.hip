@@ -381,11 +381,10 @@ __device__ __forceinline__ void load_tile_b(const LocalArgs& a, __amdgpu_buffer_
 template <int NP, int NQ>
 __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds& L, int LD, const double (&b)[NQ],
                                                    const double* kxc, int col, int* vflag) {
-  constexpr int NRB = (NQ + 3) / 4;
   const int lane = threadIdx.x & 63;
   const int g4 = lane >> 4, cl = lane & 15;
   // An opaque offset keeps the K_J^{-1} fragments in LDS: hoisted out of the
-  // tile loop they would need NRB * NQ register pairs.
+  // tile loop they would need about NQ * NQ / 4 register pairs.
   int aoff = cl * LD + g4;
   asm volatile("" : "+v"(aoff));
   const double* arow = L.Ki + aoff;
@@ -398,9 +397,17 @@ __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds
   // operands A[b][i][k] (lane 16k + 4b + i) and B[b][k][n] (lane 16k + 4b + n)
   // are exactly the loaded kernel-row chunk and a W register, and
   // D[b][i][n] lands in lane 16i + 4b + n.
+  //
+  // Whole 16-row blocks of W run on 16x16x4; the last NQ % 4 chunks of rows
+  // run on 4x4x4, four rows at a time (A[b][i][k] = K^{-1}[4q'+i][4q+k] in
+  // every block b, B = the loaded chunk), at the same cost per row, so rows
+  // are padded to a multiple of 4 rather than 16.  Its output
+  // D[b][i][n] = W[4q'+i][4b+n] sits in lane 16i + 4b + n: the B operand of
+  // chunk q' of the v and cov chains, like register r of a 16-row block.
+  constexpr int NFULL = NQ / 4;
   double accv = 0.0, accc = 0.0;
 #pragma unroll
-  for (int I = 0; I < NRB; ++I) {
+  for (int I = 0; I < NFULL; ++I) {
     v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
@@ -408,11 +415,21 @@ __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int q = 4 * I + r;
-      if (q < NQ) {
-        accv = __builtin_amdgcn_mfma_f64_4x4x4f64(b[q], acc[r], accv, 0, 0, 0);
-        accc = __builtin_amdgcn_mfma_f64_4x4x4f64(L.kx[4 * q + g4], acc[r], accc, 0, 0, 0);
-      }
+      accv = __builtin_amdgcn_mfma_f64_4x4x4f64(b[q], acc[r], accv, 0, 0, 0);
+      accc = __builtin_amdgcn_mfma_f64_4x4x4f64(L.kx[4 * q + g4], acc[r], accc, 0, 0, 0);
     }
+  }
+  int aoff4 = (cl & 3) * LD + g4;
+  asm volatile("" : "+v"(aoff4));
+  const double* a4 = L.Ki + aoff4;
+#pragma unroll
+  for (int qr = 4 * NFULL; qr < NQ; ++qr) {
+    double w4 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      w4 = __builtin_amdgcn_mfma_f64_4x4x4f64(a4[4 * qr * LD + 4 * q], b[q], w4, 0, 0, 0);
+    accv = __builtin_amdgcn_mfma_f64_4x4x4f64(b[qr], w4, accv, 0, 0, 0);
+    accc = __builtin_amdgcn_mfma_f64_4x4x4f64(L.kx[4 * qr + g4], w4, accc, 0, 0, 0);
   }
   // v_c is the diagonal entry of candidate c = 4b + i: lane 16(c%4) + c; the
   // rows of the cov product are all equal, so every lane holds its column's.
