@@ -1,0 +1,96 @@
+"""Full-size workloads in the launch configuration bench.py times, checked
+against the oracle on a seeded sample of locations (MI355X only).
+
+The GPU runs every location of the workload in one call sequence (kNN over
+the whole design, then the local designs), exactly as the benchmark does;
+the oracle recomputes a sample of those locations one by one from scratch
+(its own kNN over the full design).  The FP64 path sums in the defined
+order, so the sampled designs, means and scales must be identical."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_0074_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lg():
+    import torch
+
+    import paper_1409_0074_amd as lg
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lg.lib()
+    return lg
+
+
+def _bench_calls(lg, w, prm):
+    """lagp_candidates then lagp_predict_candidates over every location, on
+    device-resident inputs (the benchmark's step)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    M, nc = w.XX.shape[0], prm.ncand
+    X = torch.from_numpy(w.X).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    XX = torch.from_numpy(w.XX).to(dev)
+    design = lg.lagp_design_create(X, y)
+    try:
+        P = lg.make_params(prm)
+        cand = torch.empty((M, nc), dtype=torch.int32, device=dev)
+        f64 = dict(dtype=torch.float64, device=dev)
+        mean, s2, df = torch.empty(M, **f64), torch.empty(M, **f64), torch.empty(M, **f64)
+        status = torch.empty(M, dtype=torch.int32, device=dev)
+        sel = torch.empty((M, prm.n), dtype=torch.int32, device=dev)
+        lg.lagp_candidates(design, XX, nc, cand)
+        lg.lagp_predict_candidates(design, XX, cand, P, mean, s2, df, sel, None, status)
+        torch.cuda.synchronize()
+        return {"cand": cand.cpu().numpy(), "mean": mean.cpu().numpy(), "s2": s2.cpu().numpy(),
+                "df": df.cpu().numpy(), "sel": sel.cpu().numpy(), "status": status.cpu().numpy()}
+    finally:
+        lg.lagp_design_destroy(design)
+
+
+def _sample(M, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(M, size=k, replace=False))
+
+
+@pytest.mark.parametrize("search", [W.SEARCH_EXHAUSTIVE, W.SEARCH_RAY])
+def test_uniform8d_full_size_sampled(lg, search):
+    """N = 1e6, p = 8, all 1e4 locations, n = 50, N' = 1000; exhaustive and
+    10 rays; 24 sampled locations recomputed by the oracle."""
+    w = W.uniform8d(search=search)
+    prm = w.params
+    g = _bench_calls(lg, w, prm)
+    assert np.all(g["status"] == 0)
+    assert np.all(g["df"] == prm.n)
+    idx = _sample(w.XX.shape[0], 24, 501 + search)
+    oi, _ = oracle.knn(w.X, w.XX[idx], prm.ncand)
+    assert np.array_equal(g["cand"][idx].astype(np.int64), oi)
+    o = oracle.predict(w.X, w.y, w.XX[idx], prm)
+    assert np.array_equal(g["sel"][idx], o["sel"])
+    assert np.array_equal(g["mean"][idx], o["mean"]) and np.array_equal(g["s2"][idx], o["s2"])
+
+
+def test_grid2d_full_size_sampled(lg):
+    """1000 x 1000 grid design, n = 100, N' = 4000, the first 2000 locations
+    through lagp_predict (as the benchmark's grid leg), 6 sampled locations
+    recomputed by the oracle."""
+    import torch
+
+    w = W.grid2d(M=2000)
+    prm = w.params
+    d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
+    try:
+        out = d.predict(torch.from_numpy(w.XX), lg.make_params(prm), diag=False)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    finally:
+        d.close()
+    assert np.all(g["status"] == 0)
+    idx = _sample(w.XX.shape[0], 6, 503)
+    o = oracle.predict(w.X, w.y, w.XX[idx], prm)
+    assert np.array_equal(g["sel"][idx], o["sel"])
+    assert np.array_equal(g["mean"][idx], o["mean"]) and np.array_equal(g["s2"][idx], o["s2"])
