@@ -27,6 +27,10 @@ namespace lagp {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int NW = LOCAL_THREADS / 64;  // waves per workgroup
+// Rays of one wave searched in lockstep: their objective evaluations share
+// one pass (independent chains interleave), so a wave's step takes about the
+// longest of its rays' Brent searches instead of their sum.
+constexpr int RB = 3;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -48,8 +52,8 @@ struct Lds {
   double* yJ;    // NP
   double* x;     // LAGP_MAX_DIM: the location
   double* xj;    // n x p: coordinates of the local design
-  double* kzb;   // NW x 128: ray objective scratch, per wave
-  double* wvb;   // NW x 128
+  double* kzb;   // NW x RB x 128: ray objective scratch, per wave and slot
+  double* wvb;   // NW x RB x 128
   double* ra;    // R x p: ray starts
   double* rdir;  // R x p: clipped segment directions
   double* rval;  // R: best ALC along each ray
@@ -88,8 +92,8 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool m
   for (int i = 0; i < 6; ++i) take(sizeof(double) * P.NP);  // kx h col wv gv yJ
   take(sizeof(double) * LAGP_MAX_DIM);     // x
   take(sizeof(double) * n * p);            // xj
-  take(ray ? sizeof(double) * NW * 128 : 0);  // kzb
-  take(ray ? sizeof(double) * NW * 128 : 0);  // wvb
+  take(ray ? sizeof(double) * NW * RB * 128 : 0);  // kzb
+  take(ray ? sizeof(double) * NW * RB * 128 : 0);  // wvb
   take(sizeof(double) * P.R * p);          // ra
   take(sizeof(double) * P.R * p);          // rdir
   take(sizeof(double) * P.R);              // rval
@@ -627,6 +631,7 @@ __device__ __forceinline__ Best score_mixed(const LocalArgs& a, const Lds& L, in
 // Grow K^{-1} from j x j to (j+1) x (j+1) with candidate rank cs (the
 // partitioned inverse of Sec. 3.1), append cs to the design, and compute its
 // kernel row against every candidate.  Returns v_j of the added point.
+template <bool KROWS>  // exhaustive forms keep every candidate's kernel row
 __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc, float* Kc32, const double* kxc,
                             const double* Xc, int j, int cs) {
   const int tid = threadIdx.x;
@@ -671,7 +676,7 @@ __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, in
     L.selm[cs] = 1;
     L.kx[j] = kxc[cs];
   }
-  if (j + 1 < a.n && a.search == LAGP_SEARCH_EXHAUSTIVE) {
+  if (KROWS && j + 1 < a.n) {
     double* row = Kc + (int64_t)j * ncs;
     float* row32 = Kc32 ? Kc32 + (int64_t)j * ncs : nullptr;
     if (p <= 8) {
@@ -690,17 +695,9 @@ __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, in
 
 // ---------------------------------------------------------- ray search ---
 
-// Per-wave registers of one ray: start a, clipped direction, the location x
-// (all wave-uniform) and the lane's design points J_lane, J_{lane+64}.  P is
-// the input dimension when known at compile time (0: runtime p).
-template <int P>
-struct RayRegs {
-  static constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
-  double a[PM], dir[PM], x[PM], xi0[PM], xi1[PM];
-};
 
-// Gaussian correlation of two register vectors, first argument first
-// (same arithmetic as corr()).
+// Gaussian correlation of two vectors unrolled to the compile-time dimension
+// P (0: runtime p), first argument first (same arithmetic as corr()).
 template <int P>
 __device__ __forceinline__ double corr_regs(const double* u, const double* v, int p, const double* w, int dlen) {
   constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
@@ -723,120 +720,189 @@ __device__ __forceinline__ double corr_regs(const double* u, const double* v, in
   return gexp(-acc);
 }
 
-// Ray objective ALC at z = a + s dir (z = a exactly when at_start), one wave:
-// kernel vector on the lanes, K^{-1} k_z one row per lane (column reads of
-// the symmetric inverse), the two inner products on lanes 0 and 1 in the same
-// instruction stream.  Sums run in index order; the LDS vectors are zero past
-// j (as is K^{-1}), so the 8-wide blocks add fma(0, 0, t) = t only.
+// Point z = a + s dir of ray r (z = a exactly at the start), from the ray's
+// start and clipped direction in LDS.
 template <int P>
-__device__ __forceinline__ double ray_alc(const LocalArgs& a, const Lds& L, int LD, int j, const RayRegs<P>& R, double s,
-                          bool at_start, int* vflag) {
-  constexpr int PM = RayRegs<P>::PM;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int p = a.p;
-  double* kz = L.kzb + wave * 128;
-  double* wz = L.wvb + wave * 128;
-  double z[PM];
+__device__ __forceinline__ void ray_point(const Lds& L, int p, int r, double s, bool at_start, double* z) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
 #pragma unroll
   for (int k = 0; k < PM; ++k)
-    if (P > 0 || k < p) z[k] = at_start ? R.a[k] : __builtin_fma(s, R.dir[k], R.a[k]);
-  if (lane < j) kz[lane] = corr_regs<P>(R.xi0, z, p, a.w, a.dlen);
-  if (lane + 64 < j) kz[lane + 64] = corr_regs<P>(R.xi1, z, p, a.w, a.dlen);
+    if (P > 0 || k < p) z[k] = at_start ? L.ra[r * p + k] : __builtin_fma(s, L.rdir[r * p + k], L.ra[r * p + k]);
+}
+
+// Ray objective ALC for the wave's slots, one lane per slot: lane t (< RB)
+// passes its slot's ray rid, parameter s and flag ev and receives the value.
+// Kernel vectors k_z on the lanes; K^{-1} k_z one row per lane (column reads
+// of the symmetric inverse), the slots' chains interleaved; the six inner
+// products k_z.w and w.k_x (w = K^{-1} k_z) as chains of 4x4x4 FP64 MFMAs,
+// which add their four terms in order: chain c = 2t (v) or 2t+1 (cov) is the
+// diagonal entry i = c % 4 of block c / 4, its operands A[b][i][k] and
+// B[b][k][i] both in lane 16k + c.  Sums run in index order; the LDS vectors
+// are zero past j (as is K^{-1}), so padded terms add fma(0, 0, t) = t only.
+// xi: the lane's design point J_lane (registers).
+template <int P>
+__device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L, int LD, int j, const double* xi,
+                                                int rid, double s, bool ev, bool at_start, int* vflag) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = a.p;
+  int rids[RB];
+  double ss[RB];
+  bool evs[RB];
+#pragma unroll
+  for (int t = 0; t < RB; ++t) {
+    rids[t] = __shfl(rid, t, 64);
+    ss[t] = __shfl(s, t, 64);
+    evs[t] = __shfl((int)ev, t, 64) != 0;
+  }
+#pragma unroll
+  for (int t = 0; t < RB; ++t) {
+    if (!evs[t]) continue;
+    double z[PM];
+    ray_point<P>(L, p, rids[t], ss[t], at_start, z);
+    double* kz = L.kzb + (wave * RB + t) * 128;
+    if (lane < j) kz[lane] = corr_regs<P>(xi, z, p, a.w, a.dlen);
+    if (lane + 64 < j) kz[lane + 64] = corr_regs<P>(L.xj + (lane + 64) * p, z, p, a.w, a.dlen);
+  }
+  // K(z_t, x) on lane t
+  double kzx = 0.0;
+  if (lane < RB && ev) {
+    double z[PM];
+    ray_point<P>(L, p, rid, s, at_start, z);
+    kzx = corr_regs<P>(z, L.x, p, a.w, a.dlen);
+  }
   wave_sync();
   const int nb = (j + 7) >> 3;
+  const double* kzw = L.kzb + wave * RB * 128;
+  double* wzw = L.wvb + wave * RB * 128;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int i = lane + 64 * h;
     if (i < j) {
-      double t = 0.0;
+      double acc[RB];
+#pragma unroll
+      for (int t = 0; t < RB; ++t) acc[t] = 0.0;
       for (int b = 0; b < nb; ++b) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int k = 8 * b + u;
-          t = __builtin_fma(L.Ki[k * LD + i], kz[k], t);  // column i == row i
+          const double kik = L.Ki[k * LD + i];  // column i == row i
+#pragma unroll
+          for (int t = 0; t < RB; ++t) acc[t] = __builtin_fma(kik, kzw[t * 128 + k], acc[t]);
         }
       }
-      wz[i] = t;
-    }
-  }
-  wave_sync();
-  const double* pa = lane == 0 ? kz : wz;
-  const double* pb = lane == 0 ? wz : L.kx;
-  double t = 0.0;
-  if (lane < 2) {
-    for (int b = 0; b < nb; ++b) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t = __builtin_fma(pa[8 * b + u], pb[8 * b + u], t);
+      for (int t = 0; t < RB; ++t)
+        if (evs[t]) wzw[t * 128 + i] = acc[t];
     }
   }
-  const double kzx = corr_regs<P>(z, R.x, p, a.w, a.dlen);
-  const double val = lane == 0 ? (1.0 + a.g) - t : kzx - t;
-  const double v = __shfl(val, 0, 64);
-  const double cov = __shfl(val, 1, 64);
   wave_sync();
-  if (v > 0.0) return cov * cov / v;
-  *vflag = 1;
-  return 0.0;
+  // the inner products on 4x4x4 MFMA (chain c = lane % 16, term 4q + lane / 16)
+  const int cc = lane & 15, k4 = lane >> 4;
+  const bool on = cc < 2 * RB;
+  const int tc = on ? cc >> 1 : 0;
+  const double* pu = (cc & 1) ? wzw + tc * 128 : kzw + tc * 128;
+  const double* pv = (cc & 1) ? L.kx : wzw + tc * 128;
+  double dacc = 0.0;
+  const int nq = (j + 3) >> 2;
+  for (int q = 0; q < nq; ++q) {
+    const double av = on ? pu[4 * q + k4] : 0.0;
+    const double bv = on ? pv[4 * q + k4] : 0.0;
+    dacc = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv, dacc, 0, 0, 0);
+  }
+  // chain c's sum sits in lane 16 (c % 4) + c
+  const int cv = 2 * (lane < RB ? lane : 0), cw = cv + 1;
+  const double sv = __shfl(dacc, 16 * (cv & 3) + cv, 64);
+  const double sw = __shfl(dacc, 16 * (cw & 3) + cw, 64);
+  double out = 0.0;
+  if (lane < RB && ev) {
+    const double v = (1.0 + a.g) - sv;
+    const double cov = kzx - sw;
+    if (v > 0.0) {
+      out = cov * cov / v;
+    } else {
+      *vflag = 1;
+    }
+  }
+  wave_sync();
+  return out;
 }
 
-// Brent's (1973) minimiser of f(s) = -ALC on [0, 1]: golden-section steps,
-// replaced by the parabola through the three best points when that step lands
-// inside the bracket and is shorter than half the step before last; never
-// closer than tol1 = 2^-26 |x| + tol/3 to the best point; stop when the
-// bracket half-width about the best point is within 2 tol1.  Every lane of
-// the wave runs the same scalar recurrence.
+// Brent's (1973) minimiser of f(s) = -ALC on [0, 1], one slot per lane
+// (lane t < RB runs slot t's scalar recurrence; the evaluations of all slots
+// share one pass): golden-section steps, replaced by the parabola through
+// the three best points when that step lands inside the bracket and is
+// shorter than half the step before last; never closer than
+// tol1 = 2^-26 |x| + tol/3 to the best point; a slot stops when its bracket
+// half-width about the best point is within 2 tol1 (or after brent_maxit
+// steps).  Returns the minimiser on lane t, its value in *fbest.
 template <int P>
-__device__ __forceinline__ double brent_ray(const LocalArgs& a, const Lds& L, int LD, int j, const RayRegs<P>& R, double* fbest,
-                            int* vflag) {
+__device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, int LD, int j, const double* xi, int rid,
+                                              bool live, double* fbest, int* vflag) {
   const double gold = 0x1.8722191a02d60p-2;  // (3 - sqrt 5)/2
   const double sqeps = 0x1p-26;              // sqrt(2^-52)
   const double tol = a.brent_tol;
+  const int lane = threadIdx.x & 63;
   double lo = 0.0, hi = 1.0;
   double x = lo + gold * (hi - lo);
   double w = x, v = x;
-  double fx = -ray_alc<P>(a, L, LD, j, R, x, false, vflag);
-  double fw = fx, fv = fx;
+  bool run = live && lane < RB;
+  const double f0 = ray_alc_lanes<P>(a, L, LD, j, xi, rid, x, run, false, vflag);
+  double fx = -f0, fw = fx, fv = fx;
   double step = 0.0, prev = 0.0;
-  for (int it = 0; it < a.brent_maxit; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    const double tol1 = sqeps * fabs(x) + tol / 3.0;
-    const double tol2 = 2.0 * tol1;
-    if (fabs(x - mid) <= tol2 - 0.5 * (hi - lo)) break;
-    bool para = false;
-    if (fabs(prev) > tol1) {
-      const double rr = (x - w) * (fx - fv);
-      double q = (x - v) * (fx - fw);
-      double num = (x - v) * q - (x - w) * rr;
-      double den = 2.0 * (q - rr);
-      if (den > 0.0) num = -num;
-      den = fabs(den);
-      const double older = prev;
-      prev = step;
-      if (fabs(num) < fabs(0.5 * den * older) && num > den * (lo - x) && num < den * (hi - x)) {
-        step = num / den;
-        const double u = x + step;
-        if (u - lo < tol2 || hi - u < tol2) step = (mid - x >= 0.0) ? tol1 : -tol1;
-        para = true;
+  int it = 0;
+  for (;;) {
+    double u = x;
+    bool ev = false;
+    if (run) {
+      const double mid = 0.5 * (lo + hi);
+      const double tol1 = sqeps * fabs(x) + tol / 3.0;
+      const double tol2 = 2.0 * tol1;
+      if (it >= a.brent_maxit || fabs(x - mid) <= tol2 - 0.5 * (hi - lo)) {
+        run = false;
+      } else {
+        bool para = false;
+        if (fabs(prev) > tol1) {
+          const double rr = (x - w) * (fx - fv);
+          double q = (x - v) * (fx - fw);
+          double num = (x - v) * q - (x - w) * rr;
+          double den = 2.0 * (q - rr);
+          if (den > 0.0) num = -num;
+          den = fabs(den);
+          const double older = prev;
+          prev = step;
+          if (fabs(num) < fabs(0.5 * den * older) && num > den * (lo - x) && num < den * (hi - x)) {
+            step = num / den;
+            const double uu = x + step;
+            if (uu - lo < tol2 || hi - uu < tol2) step = (mid - x >= 0.0) ? tol1 : -tol1;
+            para = true;
+          }
+        }
+        if (!para) {
+          prev = (x >= mid) ? lo - x : hi - x;
+          step = gold * prev;
+        }
+        u = (fabs(step) >= tol1) ? x + step : x + ((step >= 0.0) ? tol1 : -tol1);
+        ev = true;
       }
     }
-    if (!para) {
-      prev = (x >= mid) ? lo - x : hi - x;
-      step = gold * prev;
-    }
-    const double u = (fabs(step) >= tol1) ? x + step : x + ((step >= 0.0) ? tol1 : -tol1);
-    const double fu = -ray_alc<P>(a, L, LD, j, R, u, false, vflag);
-    if (fu <= fx) {
-      if (u >= x) lo = x; else hi = x;
-      v = w; fv = fw;
-      w = x; fw = fx;
-      x = u; fx = fu;
-    } else {
-      if (u < x) lo = u; else hi = u;
-      if (fu <= fw || w == x) {
+    if (!__any(ev)) break;
+    const double fu = -ray_alc_lanes<P>(a, L, LD, j, xi, rid, u, ev, false, vflag);
+    if (ev) {
+      ++it;
+      if (fu <= fx) {
+        if (u >= x) lo = x; else hi = x;
         v = w; fv = fw;
-        w = u; fw = fu;
-      } else if (fu <= fv || v == x || v == w) {
-        v = u; fv = fu;
+        w = x; fw = fx;
+        x = u; fx = fu;
+      } else {
+        if (u < x) lo = u; else hi = u;
+        if (fu <= fw || w == x) {
+          v = w; fv = fw;
+          w = u; fw = fu;
+        } else if (fu <= fv || v == x || v == w) {
+          v = u; fv = fu;
+        }
       }
     }
   }
@@ -848,9 +914,8 @@ __device__ __forceinline__ double brent_ray(const LocalArgs& a, const Lds& L, in
 // the best and runner-up ray values in *b1, *b2.
 template <int P>
 __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, const double* Xc, int j,
-                                       int n0, double* b1,
-                        double* b2, int* vflag) {
-  constexpr int PM = RayRegs<P>::PM;
+                                       int n0, double* b1, double* b2, int* vflag) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = a.p;
   const int R = a.numrays;
@@ -868,55 +933,78 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
   }
   __syncthreads();
   const int ns = L.ints[2];
-  RayRegs<P> RR;
+  double xi[PM];
 #pragma unroll
-  for (int k = 0; k < PM; ++k) {
-    const bool in = P > 0 || k < p;
-    RR.x[k] = in ? L.x[k] : 0.0;
-    RR.xi0[k] = (in && lane < j) ? L.xj[lane * p + k] : 0.0;
-    RR.xi1[k] = (in && lane + 64 < j) ? L.xj[(lane + 64) * p + k] : 0.0;
-  }
-  for (int r = wave; r < ns; r += NW) {
-    const double* src = a.X + (int64_t)C[L.starts[r]] * p;
-    // segment from the start, away from x, ten times |a - x| long, cut at the
-    // design's bounding box (every lane computes the same values)
-    double tau = 1.0;
+  for (int k = 0; k < PM; ++k) xi[k] = ((P > 0 || k < p) && lane < j) ? L.xj[lane * p + k] : 0.0;
+  // wave w takes rays w, w + NW, ...: RB of them at a time
+  for (int r0 = wave; r0 < ns; r0 += NW * RB) {
+    int rid[RB];
+    bool valid[RB];
+    double tau[RB];
 #pragma unroll
-    for (int k = 0; k < PM; ++k) {
-      if (P > 0 || k < p) {
-        RR.a[k] = src[k];
-        const double dk = 10.0 * (RR.a[k] - RR.x[k]);
-        RR.dir[k] = dk;
-        if (dk > 0.0) tau = fmin(tau, (a.hi[k] - RR.a[k]) / dk);
-        else if (dk < 0.0) tau = fmin(tau, (a.lo[k] - RR.a[k]) / dk);
-      } else {
-        RR.a[k] = 0.0;
-        RR.dir[k] = 0.0;
+    for (int t = 0; t < RB; ++t) {
+      rid[t] = r0 + NW * t;
+      valid[t] = rid[t] < ns;
+      tau[t] = 0.0;
+      if (!valid[t]) {
+        rid[t] = r0;  // a valid index; the slot is never evaluated
+        continue;
       }
-    }
-    if (tau < 0.0) tau = 0.0;
+      // segment from the start, away from x, ten times |a - x| long, cut at
+      // the design's bounding box (every lane computes the same values)
+      const double* src = a.X + (int64_t)C[L.starts[rid[t]]] * p;
+      double ak[PM], dk[PM];
+      double tt = 1.0;
 #pragma unroll
-    for (int k = 0; k < PM; ++k) RR.dir[k] = tau * RR.dir[k];
-    const double a0 = ray_alc<P>(a, L, LD, j, RR, 0.0, true, vflag);
-    double sst = 0.0, val = a0;
-    if (tau > 0.0) {
-      double fb;
-      sst = brent_ray<P>(a, L, LD, j, RR, &fb, vflag);
-      val = -fb;
-      if (a0 >= val) {
-        sst = 0.0;
-        val = a0;
-      }
-    }
-    if (lane == 0) {
-      L.rval[r] = val;
-      L.rs[r] = sst;
-#pragma unroll
-      for (int k = 0; k < PM; ++k)
+      for (int k = 0; k < PM; ++k) {
+        ak[k] = 0.0;
+        dk[k] = 0.0;
         if (P > 0 || k < p) {
-          L.ra[r * p + k] = RR.a[k];
-          L.rdir[r * p + k] = RR.dir[k];
+          ak[k] = src[k];
+          dk[k] = 10.0 * (ak[k] - L.x[k]);
+          if (dk[k] > 0.0) tt = fmin(tt, (a.hi[k] - ak[k]) / dk[k]);
+          else if (dk[k] < 0.0) tt = fmin(tt, (a.lo[k] - ak[k]) / dk[k]);
         }
+      }
+      if (tt < 0.0) tt = 0.0;
+      tau[t] = tt;
+      if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < PM; ++k)
+          if (P > 0 || k < p) {
+            L.ra[rid[t] * p + k] = ak[k];
+            L.rdir[rid[t] * p + k] = tt * dk[k];
+          }
+    }
+    wave_sync();
+    // slot t on lane t from here on
+    int my_rid = rid[0];
+    bool my_valid = valid[0], my_live;
+    double my_tau = tau[0];
+#pragma unroll
+    for (int t = 1; t < RB; ++t)
+      if (lane == t) {
+        my_rid = rid[t];
+        my_valid = valid[t];
+        my_tau = tau[t];
+      }
+    my_valid = my_valid && lane < RB;
+    const double a0 = ray_alc_lanes<P>(a, L, LD, j, xi, my_rid, 0.0, my_valid, true, vflag);
+    my_live = my_valid && my_tau > 0.0;
+    double fb = 0.0;
+    const double xb = brent_lanes<P>(a, L, LD, j, xi, my_rid, my_live, &fb, vflag);
+    if (my_valid) {
+      double sst = 0.0, val = a0;
+      if (my_live) {
+        sst = xb;
+        val = -fb;
+        if (a0 >= val) {
+          sst = 0.0;
+          val = a0;
+        }
+      }
+      L.rval[my_rid] = val;
+      L.rs[my_rid] = sst;
     }
     wave_sync();
   }
@@ -995,7 +1083,7 @@ __global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(2
   }
   for (int c = tid; c < ncs; c += blockDim.x) L.selm[c] = (c < nc) ? 0 : 1;
   if constexpr (MODE == MODE_RAY)
-    for (int t = tid; t < NW * 128; t += blockDim.x) {
+    for (int t = tid; t < NW * RB * 128; t += blockDim.x) {
       L.kzb[t] = 0.0;  // zero past j: the ray sums run in zero-padded blocks
       L.wvb[t] = 0.0;
     }
@@ -1043,7 +1131,7 @@ __global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(2
         b2 = L.scal[2];
       }
       if (cs < 0 || cs >= nc) break;  // no finite score anywhere: give up on x
-      const double v = add_point(a, L, LD, Kc, Kc32, kxc, Xc, j, cs);
+      const double v = add_point<MODE == MODE_EXACT || MODE == MODE_MIXED>(a, L, LD, Kc, Kc32, kxc, Xc, j, cs);
       done = j + 1;
       if (!(v > 0.0)) vflag = 1;
       if (tid == 0 && a.diag) {
