@@ -31,6 +31,10 @@ constexpr int NW = LOCAL_THREADS / 64;  // waves per workgroup
 // one pass (independent chains interleave), so a wave's step takes about the
 // longest of its rays' Brent searches instead of their sum.
 constexpr int RB = 3;
+// Per-slot stride of the ray scratch vectors (in doubles): 16-byte aligned
+// but off the bank period, so the six MFMA inner-product chains, which read
+// different slots' vectors at the same index, fall in different LDS banks.
+constexpr int KZS = 130;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -52,8 +56,8 @@ struct Lds {
   double* yJ;    // NP
   double* x;     // LAGP_MAX_DIM: the location
   double* xj;    // n x p: coordinates of the local design
-  double* kzb;   // NW x RB x 128: ray objective scratch, per wave and slot
-  double* wvb;   // NW x RB x 128
+  double* kzb;   // NW x RB x KZS: ray objective scratch, per wave and slot
+  double* wvb;   // NW x RB x KZS
   double* ra;    // R x p: ray starts
   double* rdir;  // R x p: clipped segment directions
   double* rval;  // R: best ALC along each ray
@@ -92,8 +96,8 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool m
   for (int i = 0; i < 6; ++i) take(sizeof(double) * P.NP);  // kx h col wv gv yJ
   take(sizeof(double) * LAGP_MAX_DIM);     // x
   take(sizeof(double) * n * p);            // xj
-  take(ray ? sizeof(double) * NW * RB * 128 : 0);  // kzb
-  take(ray ? sizeof(double) * NW * RB * 128 : 0);  // wvb
+  take(ray ? sizeof(double) * NW * RB * KZS : 0);  // kzb
+  take(ray ? sizeof(double) * NW * RB * KZS : 0);  // wvb
   take(sizeof(double) * P.R * p);          // ra
   take(sizeof(double) * P.R * p);          // rdir
   take(sizeof(double) * P.R);              // rval
@@ -760,7 +764,7 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
     if (!evs[t]) continue;
     double z[PM];
     ray_point<P>(L, p, rids[t], ss[t], at_start, z);
-    double* kz = L.kzb + (wave * RB + t) * 128;
+    double* kz = L.kzb + (wave * RB + t) * KZS;
     if (lane < j) kz[lane] = corr_regs<P>(xi, z, p, a.w, a.dlen);
     if (lane + 64 < j) kz[lane + 64] = corr_regs<P>(L.xj + (lane + 64) * p, z, p, a.w, a.dlen);
   }
@@ -773,8 +777,8 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
   }
   wave_sync();
   const int nb = (j + 7) >> 3;
-  const double* kzw = L.kzb + wave * RB * 128;
-  double* wzw = L.wvb + wave * RB * 128;
+  const double* kzw = L.kzb + wave * RB * KZS;
+  double* wzw = L.wvb + wave * RB * KZS;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int i = lane + 64 * h;
@@ -788,12 +792,12 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
           const int k = 8 * b + u;
           const double kik = L.Ki[k * LD + i];  // column i == row i
 #pragma unroll
-          for (int t = 0; t < RB; ++t) acc[t] = __builtin_fma(kik, kzw[t * 128 + k], acc[t]);
+          for (int t = 0; t < RB; ++t) acc[t] = __builtin_fma(kik, kzw[t * KZS + k], acc[t]);
         }
       }
 #pragma unroll
       for (int t = 0; t < RB; ++t)
-        if (evs[t]) wzw[t * 128 + i] = acc[t];
+        if (evs[t]) wzw[t * KZS + i] = acc[t];
     }
   }
   wave_sync();
@@ -801,8 +805,8 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
   const int cc = lane & 15, k4 = lane >> 4;
   const bool on = cc < 2 * RB;
   const int tc = on ? cc >> 1 : 0;
-  const double* pu = (cc & 1) ? wzw + tc * 128 : kzw + tc * 128;
-  const double* pv = (cc & 1) ? L.kx : wzw + tc * 128;
+  const double* pu = (cc & 1) ? wzw + tc * KZS : kzw + tc * KZS;
+  const double* pv = (cc & 1) ? L.kx : wzw + tc * KZS;
   double dacc = 0.0;
   const int nq = (j + 3) >> 2;
   for (int q = 0; q < nq; ++q) {
@@ -1083,7 +1087,7 @@ __global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(2
   }
   for (int c = tid; c < ncs; c += blockDim.x) L.selm[c] = (c < nc) ? 0 : 1;
   if constexpr (MODE == MODE_RAY)
-    for (int t = tid; t < NW * RB * 128; t += blockDim.x) {
+    for (int t = tid; t < NW * RB * KZS; t += blockDim.x) {
       L.kzb[t] = 0.0;  // zero past j: the ray sums run in zero-padded blocks
       L.wvb[t] = 0.0;
     }
