@@ -388,7 +388,7 @@ __device__ __forceinline__ void load_tile_b(const LocalArgs& a, __amdgpu_buffer_
 // tile's candidate rows b; the value is valid in lanes 0..15.
 template <int NP, int NQ>
 __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds& L, int LD, const double (&b)[NQ],
-                                                   const double* kxc, int col, int* vflag) {
+                                                   double kxcol, int* vflag) {
   const int lane = threadIdx.x & 63;
   const int g4 = lane >> 4, cl = lane & 15;
   // An opaque offset keeps the K_J^{-1} fragments in LDS: hoisted out of the
@@ -443,7 +443,7 @@ __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds
   // rows of the cov product are all equal, so every lane holds its column's.
   const double vsum = __shfl(accv, 16 * (cl & 3) + cl, 64);
   const double v = (1.0 + a.g) - vsum;
-  const double cov = kxc[col] - accc;
+  const double cov = kxcol - accc;
   if (v > 0.0) return cov * cov / v;
   if (g4 == 0) *vflag = 1;
   return 0.0;
@@ -461,20 +461,32 @@ __device__ __forceinline__ Best score_exact_q(const LocalArgs& a, const Lds& L, 
   Best best = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
   const __amdgpu_buffer_rsrc_t rs = kc_rsrc(a, Kc);
   // Double buffering costs 2 NQ more registers: only for the shorter chains.
+  // K(x_c, x) of the tile travels with its rows: a load issued before the
+  // next tile's prefetch is waited for without waiting for that prefetch.
   constexpr bool PREFETCH = NQ <= 16;
   double bn[NQ];
-  if (PREFETCH && wave < ntiles) load_tile_b<NQ>(a, rs, j, (wave << 4) + cl, bn);
+  double kxn = 0.0;
+  if (PREFETCH && wave < ntiles) {
+    kxn = kxc[(wave << 4) + cl];
+    load_tile_b<NQ>(a, rs, j, (wave << 4) + cl, bn);
+  }
   for (int t = wave; t < ntiles; t += NW) {
     double b[NQ];
+    double kxcol;
     if constexpr (PREFETCH) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) b[q] = bn[q];
-      if (t + NW < ntiles) load_tile_b<NQ>(a, rs, j, ((t + NW) << 4) + cl, bn);
+      kxcol = kxn;
+      if (t + NW < ntiles) {
+        kxn = kxc[((t + NW) << 4) + cl];
+        load_tile_b<NQ>(a, rs, j, ((t + NW) << 4) + cl, bn);
+      }
     } else {
+      kxcol = kxc[(t << 4) + cl];
       load_tile_b<NQ>(a, rs, j, (t << 4) + cl, b);
     }
     const int c = (t << 4) + cl;
-    const double alc = alc_tile_exact_q<NP, NQ>(a, L, LD, b, kxc, c, vflag);
+    const double alc = alc_tile_exact_q<NP, NQ>(a, L, LD, b, kxcol, vflag);
     if (lane < 16 && !L.selm[c]) best_push(best, alc, c);
   }
   return best;
@@ -485,8 +497,9 @@ template <int NP, int NQ>
 __device__ __forceinline__ double alc_tile_exact_n(const LocalArgs& a, const Lds& L, int LD, const double* Kc,
                                                 const double* kxc, int j, int col, int* vflag) {
   double b[NQ];
+  const double kxcol = kxc[col];
   load_tile_b<NQ>(a, kc_rsrc(a, Kc), j, col, b);
-  return alc_tile_exact_q<NP, NQ>(a, L, LD, b, kxc, col, vflag);
+  return alc_tile_exact_q<NP, NQ>(a, L, LD, b, kxcol, vflag);
 }
 
 #define LAGP_CASES_16(M) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)
