@@ -31,10 +31,6 @@ constexpr int NW = LOCAL_THREADS / 64;  // waves per workgroup
 // one pass (independent chains interleave), so a wave's step takes about the
 // longest of its rays' Brent searches instead of their sum.
 constexpr int RB = 3;
-// Per-slot stride of the ray scratch vectors (in doubles): 16-byte aligned
-// but off the bank period, so the six MFMA inner-product chains, which read
-// different slots' vectors at the same index, fall in different LDS banks.
-constexpr int KZS = 130;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -56,8 +52,8 @@ struct Lds {
   double* yJ;    // NP
   double* x;     // LAGP_MAX_DIM: the location
   double* xj;    // n x p: coordinates of the local design
-  double* kzb;   // NW x RB x KZS: ray objective scratch, per wave and slot
-  double* wvb;   // NW x RB x KZS
+  double* kzb;   // NW x RB x kzs: ray objective scratch, per wave and slot
+  double* wvb;   // NW x RB x kzs
   double* ra;    // R x p: ray starts
   double* rdir;  // R x p: clipped segment directions
   double* rval;  // R: best ALC along each ray
@@ -69,14 +65,19 @@ struct Lds {
   int* starts;   // R
   int* ints;     // 8 scalars
   int* shortlist;  // 64: mixed form, candidates re-scored in FP64
+  int kzs;         // per-slot stride of kzb / wvb
   float* scr;      // ncs: mixed form, FP32 screened scores
   unsigned char* selm;  // ncs: 1 = not available (selected or padding)
 };
 
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
+// kzs = NP + 2: room for the zero-padded 8-wide blocks of the ray sums,
+// 16-byte aligned but off the bank period, so the six MFMA inner-product
+// chains, which read different slots' vectors at the same index, fall in
+// different LDS banks.
 struct LdsPlan {
-  int NP, NR, LD, R;
+  int NP, NR, LD, R, KZS;
   size_t off[24];
   size_t bytes;
 };
@@ -85,7 +86,10 @@ struct LdsPlan {
 __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool mixed) {
   LdsPlan P;
   P.NP = n <= 64 ? 64 : 128;
-  P.NR = (n + 15) & ~15;
+  // exact scoring and rays read rows below 4 ceil(j/4); the FP32 screen
+  // reads whole 16-row blocks
+  P.NR = mixed ? (n + 15) & ~15 : (n + 3) & ~3;
+  P.KZS = P.NP + 2;
   P.LD = P.NP + 1;  // odd: the 16 rows of an MFMA operand fall in distinct banks
   P.R = R < 1 ? 0 : R;
   const bool ray = R > 0;
@@ -96,8 +100,8 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool m
   for (int i = 0; i < 6; ++i) take(sizeof(double) * P.NP);  // kx h col wv gv yJ
   take(sizeof(double) * LAGP_MAX_DIM);     // x
   take(sizeof(double) * n * p);            // xj
-  take(ray ? sizeof(double) * NW * RB * KZS : 0);  // kzb
-  take(ray ? sizeof(double) * NW * RB * KZS : 0);  // wvb
+  take(ray ? sizeof(double) * NW * RB * P.KZS : 0);  // kzb
+  take(ray ? sizeof(double) * NW * RB * P.KZS : 0);  // wvb
   take(sizeof(double) * P.R * p);          // ra
   take(sizeof(double) * P.R * p);          // rdir
   take(sizeof(double) * P.R);              // rval
@@ -130,6 +134,7 @@ __device__ inline Lds carve(unsigned char* s, const LdsPlan& P) {
   L.shortlist = reinterpret_cast<int*>(s + P.off[k++]);
   L.scr = reinterpret_cast<float*>(s + P.off[k++]);
   L.selm = s + P.off[k++];
+  L.kzs = P.KZS;
   return L;
 }
 
@@ -777,7 +782,7 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
     if (!evs[t]) continue;
     double z[PM];
     ray_point<P>(L, p, rids[t], ss[t], at_start, z);
-    double* kz = L.kzb + (wave * RB + t) * KZS;
+    double* kz = L.kzb + (wave * RB + t) * L.kzs;
     if (lane < j) kz[lane] = corr_regs<P>(xi, z, p, a.w, a.dlen);
     if (lane + 64 < j) kz[lane + 64] = corr_regs<P>(L.xj + (lane + 64) * p, z, p, a.w, a.dlen);
   }
@@ -790,6 +795,7 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
   }
   wave_sync();
   const int nb = (j + 7) >> 3;
+  const int KZS = L.kzs;
   const double* kzw = L.kzb + wave * RB * KZS;
   double* wzw = L.wvb + wave * RB * KZS;
 #pragma unroll
@@ -1076,8 +1082,16 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
 // carries only its own register footprint.
 enum Mode { MODE_EXACT = 0, MODE_MIXED = 1, MODE_RAY = 3, MODE_NN = 4 };
 
+// Register budget per form: the ray form is held to three waves per SIMD
+// (its LDS admits three workgroups per CU); the exhaustive forms schedule
+// for two and fit three at n <= 64 by themselves (asking the scheduler for
+// three there measured slower).
+template <int NP, int MODE>
+constexpr int local_waves_per_eu() { return MODE == MODE_RAY ? 3 : 2; }
+
 template <int NP, int MODE, int P>
-__global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_local(LocalArgs a) {
+__global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(local_waves_per_eu<NP, MODE>())))
+void k_local(LocalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 0;
   const LdsPlan plan = plan_lds(a.n, a.ncs, a.p, R, MODE == MODE_MIXED);
@@ -1100,7 +1114,7 @@ __global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(2
   }
   for (int c = tid; c < ncs; c += blockDim.x) L.selm[c] = (c < nc) ? 0 : 1;
   if constexpr (MODE == MODE_RAY)
-    for (int t = tid; t < NW * RB * KZS; t += blockDim.x) {
+    for (int t = tid; t < NW * RB * plan.KZS; t += blockDim.x) {
       L.kzb[t] = 0.0;  // zero past j: the ray sums run in zero-padded blocks
       L.wvb[t] = 0.0;
     }
