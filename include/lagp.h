@@ -65,6 +65,15 @@ extern "C" {
 #define LAGP_PREC_FP64 0  /* everything in FP64, every sum in its defined order (bit-reproducible) */
 #define LAGP_PREC_MIXED 1 /* candidate screening in FP32 on MFMA, shortlist re-scored in FP64 */
 
+/* scoring forms of exhaustive search (both FP64) */
+#define LAGP_SCORING_PARTINV 0 /* partitioned-inverse updates as the paper writes them; every sum in a
+                                  defined order, bit-reproducible */
+#define LAGP_SCORING_CHOL 1    /* incremental Cholesky columns: u_c = L^{-1} k_J(x_c) grows by one
+                                  entry per step, so a step costs O(j) per candidate instead of
+                                  O(j^2); the same criterion and prediction to rounding (not bit
+                                  for bit).  Needs precision FP64, n <= 50 and ncand <= 1024
+                                  (ncand <= 512 when p > 8). */
+
 /* per-location status bits */
 #define LAGP_STATUS_VNONPOS 1   /* a Schur complement v <= 0 was met; scored as 0 */
 #define LAGP_STATUS_NONFINITE 2 /* non-finite mean or scale */
@@ -84,6 +93,7 @@ typedef struct lagp_server lagp_server;
  *   d_len: 1 (isotropic) or p (separable); d[0..d_len-1] > 0;
  *   g: nugget >= 0;
  *   rescore_k: size of the FP64 re-scored shortlist in the mixed form (1..64);
+ *   scoring: LAGP_SCORING_* (exhaustive search only; 0 otherwise);
  *   brent_maxit, brent_tol: Brent line-search budget (<= 0: 100) and
  *     tolerance (<= 0: 2^-13). */
 typedef struct {
@@ -98,7 +108,7 @@ typedef struct {
   double d[LAGP_MAX_DIM];
   double g;
   int32_t brent_maxit;
-  int32_t reserved;
+  int32_t scoring;
   double brent_tol;
 } lagp_params;
 

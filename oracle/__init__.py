@@ -51,7 +51,7 @@ def lib():
         L.orc_knn.restype = ctypes.c_int
         common = [_dp, _dp, ctypes.c_int64, ctypes.c_int]
         par = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
-               ctypes.c_double, ctypes.c_int, ctypes.c_double]
+               ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int]
         L.orc_predict.argtypes = common + [_dp, ctypes.c_int64] + par + [_i32p, ctypes.c_int, _dp, _dp, _dp, _i32p,
                                                                           _dp, _i32p]
         L.orc_predict.restype = ctypes.c_int
@@ -109,7 +109,7 @@ def knn(X, XX, ncand: int, nthreads: int | None = None):
 def _par(params, p):
     d = _f64(np.atleast_1d(params.d))
     return d, [params.n0, params.n, params.ncand, params.search, params.numrays, _p(d), len(d), params.g,
-               params.brent_maxit, params.brent_tol]
+               params.brent_maxit, params.brent_tol, getattr(params, "scoring", 0)]
 
 
 def predict(X, y, XX, params, forced=None, nthreads: int | None = None):

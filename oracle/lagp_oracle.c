@@ -25,6 +25,11 @@
  *                  the quantities under Eq. alc, sign of g_j corrected)
  *   O6 predict     Student-t mean and scale with n degrees of freedom (Eqs.
  *                  predgp and preds2 with N -> n)                     (Sec. 2.1)
+ *   O7 Cholesky    the same exhaustive search and prediction through the
+ *      form        Cholesky factor of K_J grown one row per step (local_one_chol
+ *                  below): the criterion and prediction of O4-O6 in another
+ *                  rounding order, and the checker of the library's Cholesky
+ *                  scoring form
  *
  * Rounding is defined, not left to the compiler, so that another
  * implementation can reproduce every value here bit for bit: squared
@@ -251,6 +256,7 @@ typedef struct {
     int brent_maxit;
     double brent_tol;
     const double *lo, *hi; /* bounding box of the whole design */
+    int scoring;           /* exhaustive search: 0 partitioned inverse (O5), 1 Cholesky form (O7) */
 } ctx_t;
 
 typedef struct {
@@ -262,6 +268,7 @@ typedef struct {
     double *kxc;         /* ncand: K(x_c, x) */
     double *Ki;          /* n x n, leading dimension n */
     double *kx, *h, *w, *gv, *kz, *tmp;
+    double *cv, *cr;     /* ncand: Cholesky form, v_c and y_c - z^T u_c */
     int *J;              /* ranks of the selected candidates */
     char *inJ;           /* ncand flags */
     char *forbid;        /* ncand flags (ray starts) */
@@ -423,6 +430,126 @@ double orc_ray_segment(const double *a, const double *x, const double *lo, const
     return tau;
 }
 
+/*
+ * O7: exhaustive search through the Cholesky factor.  With K_J + g I = L L^T
+ * for the design J so far, free candidate q carries the column
+ * u_q = L^{-1} k_J(x_q) (entries U[k*ncand + q], k < |J|) and
+ *   v_q   = (1 + g) - u_q^T u_q        (v_j of Eq. alc at x_q)
+ *   cov_q = K(x_q, x) - w^T u_q        w = L^{-1} k_J(x)
+ *   r_q   = y_q - z^T u_q              z = L^{-1} y_J
+ * so that k_J(x_q)^T K_J^{-1} k_J(x) = u_q^T w and the integrand of Eq. alc
+ * at x is cov_q^2 / v_q.  Taking candidate t appends (u_t^T, l) to L with
+ * l = sqrt(v_t), w_j = cov_t / l, z_j = r_t / l, and every free q gets
+ *   u_q[j] = (K(x_t, x_q) - u_t^T u_q) / l
+ * after which v_q, cov_q and r_q drop u_q[j]^2, w_j u_q[j] and z_j u_q[j].
+ * The n0 nearest enter first, in rank order (that is the Cholesky
+ * factorisation of the starting K_J, Sec. 2.2).  Prediction: mean w^T z,
+ * psi = z^T z, k_x^T K^{-1} k_x = w^T w (Eqs. predgp, preds2, N -> n).
+ * Sums run in index order with one fused multiply-add per term; ties go to
+ * the smaller rank; v_q <= 0 scores 0 and raises the status flag, as in O4.
+ * trace_Ki (nullable) is filled with NaN: this form never forms K^{-1}.
+ */
+static int local_one_chol(const ctx_t *c, scratch_t *s, const double *x, const int32_t *forced,
+                          double *mean, double *s2, double *df, int32_t *sel, double *diag, double *trace_alc,
+                          double *trace_Ki)
+{
+    const int p = c->p, n = c->n, nc = c->ncand, n0 = c->n0;
+    const double *X = c->X;
+    double *U = s->Kc, *v = s->cv, *cov = s->kxc, *r = s->cr;
+    int status = 0;
+
+    knn_one(X, c->N, p, x, nc, s->cand, s->cand_d2, s->heap);
+    memset(s->inJ, 0, nc);
+    for (int q = 0; q < nc; q++) {
+        v[q] = 1.0 + c->g;
+        cov[q] = kern(X + s->cand[q] * p, x, p, c->d, c->d_len);
+        r[q] = c->y[s->cand[q]];
+    }
+    if (trace_Ki)
+        for (int i = 0; i < n * n; i++) trace_Ki[i] = NAN;
+    double mu = 0.0, psi = 0.0, qq = 0.0;
+    int done = 0;
+    for (int j = 0; j < n; j++) {
+        int take = j, best = -1;
+        double alc1 = -INFINITY, alc2 = -INFINITY, gap = INFINITY;
+        if (j >= n0) {
+            for (int q = 0; q < nc; q++) {
+                if (trace_alc) trace_alc[(size_t)(j - n0) * nc + q] = NAN;
+                if (s->inJ[q]) continue;
+                double a;
+                if (v[q] > 0.0) a = cov[q] * cov[q] / v[q];
+                else { a = 0.0; status |= ORC_STATUS_VNONPOS; }
+                if (trace_alc) trace_alc[(size_t)(j - n0) * nc + q] = a;
+                if (a > alc1) { alc2 = alc1; alc1 = a; best = q; }
+                else if (a > alc2) alc2 = a;
+            }
+            gap = (alc1 > 0.0) ? (alc1 - alc2) / alc1 : 0.0;
+            take = best;
+            if (forced) {
+                take = -1;
+                for (int q = 0; q < nc; q++)
+                    if (s->cand[q] == (int64_t)forced[j]) { take = q; break; }
+                if (take < 0 || s->inJ[take]) return -2;
+            }
+            if (take < 0) break; /* no finite criterion anywhere: no prediction */
+        }
+        if (j < n0 && !(v[take] > 0.0)) {
+            /* the starting covariance is not positive definite */
+            *mean = NAN;
+            *s2 = NAN;
+            *df = (double)n;
+            if (sel)
+                for (int i = 0; i < n; i++) sel[i] = (i < n0) ? (int32_t)s->cand[i] : -1;
+            return ORC_STATUS_NOTPD | ORC_STATUS_NONFINITE;
+        }
+        if (!(v[take] > 0.0)) status |= ORC_STATUS_VNONPOS;
+        const double l = sqrt(v[take]);
+        const double wj = cov[take] / l, zj = r[take] / l;
+        const double bj = (1.0 + c->g) - qq; /* (1+g) - k_x^T K_j^{-1} k_x before the step */
+        mu = fma(wj, zj, mu);
+        psi = fma(zj, zj, psi);
+        qq = fma(wj, wj, qq);
+        if (diag && j >= n0) {
+            double *dg = diag + (size_t)(j - n0) * ORC_NDIAG;
+            dg[0] = (best >= 0) ? (double)s->cand[best] : -1.0;
+            dg[1] = alc1;
+            dg[2] = alc2;
+            dg[3] = (v[take] > 0.0) ? cov[take] * cov[take] / v[take] : 0.0;
+            dg[4] = gap;
+            dg[5] = 0.0;
+            dg[6] = bj;
+            dg[7] = 0.0;
+        }
+        s->J[j] = take;
+        s->inJ[take] = 1;
+        done = j + 1;
+        if (j + 1 == n) break;
+        const double *xt = X + s->cand[take] * p;
+        for (int q = 0; q < nc; q++) {
+            if (s->inJ[q]) continue;
+            double d = 0.0;
+            for (int k = 0; k < j; k++) d = fma(U[(size_t)k * nc + take], U[(size_t)k * nc + q], d);
+            const double e = (kern(xt, X + s->cand[q] * p, p, c->d, c->d_len) - d) / l;
+            U[(size_t)j * nc + q] = e;
+            v[q] = fma(-e, e, v[q]);
+            cov[q] = fma(-wj, e, cov[q]);
+            r[q] = fma(-zj, e, r[q]);
+        }
+    }
+    if (done == n) {
+        *mean = mu;
+        *s2 = psi * ((1.0 + c->g) - qq) / (double)n;
+    } else {
+        *mean = NAN;
+        *s2 = NAN;
+    }
+    *df = (double)n;
+    if (!isfinite(*mean) || !isfinite(*s2)) status |= ORC_STATUS_NONFINITE;
+    if (sel)
+        for (int i = 0; i < n; i++) sel[i] = (i < done) ? (int32_t)s->cand[s->J[i]] : -1;
+    return status;
+}
+
 /* One location: local design, then prediction.  forced (nullable) gives a
  * selection sequence (design row ids, n entries) to follow instead of the
  * oracle's own choices; the oracle's own choice is still recorded per step.
@@ -439,6 +566,7 @@ static int local_one(const ctx_t *c, scratch_t *s, const double *x, const int32_
                      double *mean, double *s2, double *df, int32_t *sel, double *diag,
                      double *trace_alc, double *trace_Ki)
 {
+    if (c->scoring == 1) return local_one_chol(c, s, x, forced, mean, s2, df, sel, diag, trace_alc, trace_Ki);
     const int p = c->p, n = c->n, nc = c->ncand;
     const double *X = c->X;
     int status = 0;
@@ -644,23 +772,26 @@ static int scratch_alloc(scratch_t *s, int n, int ncand)
     s->gv = malloc(sizeof(double) * n);
     s->kz = malloc(sizeof(double) * n);
     s->tmp = malloc(sizeof(double) * (size_t)4 * n * n + 16);
+    s->cv = malloc(sizeof(double) * ncand);
+    s->cr = malloc(sizeof(double) * ncand);
     s->J = malloc(sizeof(int) * n);
     s->inJ = malloc(ncand);
     s->forbid = malloc(ncand);
     return (s->heap && s->cand && s->cand_d2 && s->Kc && s->kxc && s->Ki && s->kx && s->h && s->w &&
-            s->gv && s->kz && s->tmp && s->J && s->inJ && s->forbid) ? 0 : -1;
+            s->gv && s->kz && s->tmp && s->cv && s->cr && s->J && s->inJ && s->forbid) ? 0 : -1;
 }
 
 static void scratch_free(scratch_t *s)
 {
     free(s->heap); free(s->cand); free(s->cand_d2); free(s->Kc); free(s->kxc); free(s->Ki);
-    free(s->kx); free(s->h); free(s->w); free(s->gv); free(s->kz); free(s->tmp); free(s->J);
+    free(s->kx); free(s->h); free(s->w); free(s->gv); free(s->kz); free(s->tmp); free(s->cv); free(s->cr); free(s->J);
     free(s->inJ); free(s->forbid);
 }
 
 static int check_args(int64_t N, int p, int n0, int n, int ncand, int search, int numrays, const double *d,
-                      int d_len, double g)
+                      int d_len, double g, int scoring)
 {
+    if (scoring < 0 || scoring > 1 || (scoring == 1 && search != 0)) return -1;
     if (N < 1 || p < 1 || p > 16) return -1;
     if (n0 < 1 || n < n0 || ncand < n || (int64_t)ncand > N) return -1;
     if (search < 0 || search > 2) return -1;
@@ -714,15 +845,16 @@ int orc_knn(const double *X, int64_t N, int p, const double *XX, int64_t M, int 
  * -2 on allocation failure. */
 int orc_predict(const double *X, const double *y, int64_t N, int p, const double *XX, int64_t M, int n0,
                 int n, int ncand, int search, int numrays, const double *d, int d_len, double g,
-                int brent_maxit, double brent_tol, const int32_t *forced, int nthreads, double *mean,
-                double *s2, double *df, int32_t *sel, double *diag, int32_t *status)
+                int brent_maxit, double brent_tol, int scoring, const int32_t *forced, int nthreads,
+                double *mean, double *s2, double *df, int32_t *sel, double *diag, int32_t *status)
 {
-    if (check_args(N, p, n0, n, ncand, search, numrays, d, d_len, g) != 0 || M < 0) return -1;
+    if (check_args(N, p, n0, n, ncand, search, numrays, d, d_len, g, scoring) != 0 || M < 0) return -1;
     double lo[16], hi[16], w[16];
     bbox(X, N, p, lo, hi);
     for (int k = 0; k < d_len; k++) w[k] = 1.0 / d[k];
     ctx_t c = {X, y, N, p, n0, n, ncand, search, numrays, w, d_len, g,
-               brent_maxit > 0 ? brent_maxit : 100, brent_tol > 0.0 ? brent_tol : ldexp(1.0, -13), lo, hi};
+               brent_maxit > 0 ? brent_maxit : 100, brent_tol > 0.0 ? brent_tol : ldexp(1.0, -13), lo, hi,
+               scoring};
     int nd = (search == 2) ? 0 : n - n0;
     int err = 0;
 #pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
@@ -756,15 +888,16 @@ int orc_predict(const double *X, const double *y, int64_t N, int p, const double
  * the final inverse, the candidate list and the per-step diagnostics. */
 int orc_trace(const double *X, const double *y, int64_t N, int p, const double *x, int n0, int n, int ncand,
               int search, int numrays, const double *d, int d_len, double g, int brent_maxit,
-              double brent_tol, const int32_t *forced, double *mean, double *s2, double *df, int32_t *sel,
-              double *diag, double *trace_alc, double *trace_Ki, int64_t *cand)
+              double brent_tol, int scoring, const int32_t *forced, double *mean, double *s2, double *df,
+              int32_t *sel, double *diag, double *trace_alc, double *trace_Ki, int64_t *cand)
 {
-    if (check_args(N, p, n0, n, ncand, search, numrays, d, d_len, g) != 0) return -1;
+    if (check_args(N, p, n0, n, ncand, search, numrays, d, d_len, g, scoring) != 0) return -1;
     double lo[16], hi[16], w[16];
     bbox(X, N, p, lo, hi);
     for (int k = 0; k < d_len; k++) w[k] = 1.0 / d[k];
     ctx_t c = {X, y, N, p, n0, n, ncand, search, numrays, w, d_len, g,
-               brent_maxit > 0 ? brent_maxit : 100, brent_tol > 0.0 ? brent_tol : ldexp(1.0, -13), lo, hi};
+               brent_maxit > 0 ? brent_maxit : 100, brent_tol > 0.0 ? brent_tol : ldexp(1.0, -13), lo, hi,
+               scoring};
     scratch_t s;
     if (scratch_alloc(&s, n, ncand) != 0) return -2;
     int st = local_one(&c, &s, x, forced, mean, s2, df, sel, diag, trace_alc, trace_Ki);

@@ -30,6 +30,8 @@ LAGP_SEARCH_RAY = 1
 LAGP_SEARCH_NN = 2
 LAGP_PREC_FP64 = 0
 LAGP_PREC_MIXED = 1
+LAGP_SCORING_PARTINV = 0
+LAGP_SCORING_CHOL = 1
 LAGP_STATUS_VNONPOS = 1
 LAGP_STATUS_NONFINITE = 2
 LAGP_STATUS_NOTPD = 4
@@ -46,7 +48,7 @@ class lagp_params(ctypes.Structure):
         ("n0", ctypes.c_int32), ("n", ctypes.c_int32), ("ncand", ctypes.c_int32), ("numrays", ctypes.c_int32),
         ("search", ctypes.c_int32), ("precision", ctypes.c_int32), ("d_len", ctypes.c_int32),
         ("rescore_k", ctypes.c_int32), ("d", ctypes.c_double * LAGP_MAX_DIM), ("g", ctypes.c_double),
-        ("brent_maxit", ctypes.c_int32), ("reserved", ctypes.c_int32), ("brent_tol", ctypes.c_double),
+        ("brent_maxit", ctypes.c_int32), ("scoring", ctypes.c_int32), ("brent_tol", ctypes.c_double),
     ]
 
 
@@ -138,6 +140,7 @@ def make_params(params=None, **kw) -> lagp_params:
     P.rescore_k = src.rescore_k
     P.brent_maxit = src.brent_maxit
     P.brent_tol = float(src.brent_tol)
+    P.scoring = src.scoring
     return P
 
 

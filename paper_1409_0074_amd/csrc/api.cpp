@@ -63,6 +63,11 @@ int32_t check_params(const lagp_design* d, const lagp_params* P, int* rays) {
     return fail(LAGP_EINVAL, "the mixed precision form applies to exhaustive search only");
   if (P->precision == LAGP_PREC_MIXED && (P->rescore_k < 1 || P->rescore_k > 64))
     return fail(LAGP_EINVAL, "rescore_k must be in [1, 64]");
+  if (P->scoring != LAGP_SCORING_PARTINV && P->scoring != LAGP_SCORING_CHOL)
+    return fail(LAGP_EINVAL, "scoring must be LAGP_SCORING_PARTINV or LAGP_SCORING_CHOL");
+  if (P->scoring == LAGP_SCORING_CHOL &&
+      (P->search != LAGP_SEARCH_EXHAUSTIVE || P->precision != LAGP_PREC_FP64))
+    return fail(LAGP_EINVAL, "Cholesky scoring applies to exhaustive search in FP64 only");
   if (P->n < 1 || P->n > LAGP_MAX_N) return fail(LAGP_EINVAL, "n must be in [1, LAGP_MAX_N]");
   if (P->search != LAGP_SEARCH_NN && (P->n0 < 1 || P->n0 > P->n)) return fail(LAGP_EINVAL, "n0 must be in [1, n]");
   if (P->ncand < P->n) return fail(LAGP_EINVAL, "ncand must be >= n");
@@ -84,6 +89,8 @@ int32_t check_params(const lagp_design* d, const lagp_params* P, int* rays) {
     if (P->brent_tol < 0.0 || !std::isfinite(P->brent_tol)) return fail(LAGP_EINVAL, "brent_tol must be finite");
     *rays = R;
   }
+  if (P->scoring == LAGP_SCORING_CHOL && !lagp::chol_supported(P->n, P->ncand, p, (size_t)max_lds_per_block()))
+    return fail(LAGP_EINVAL, "Cholesky scoring needs n <= 50 and ncand <= 1024 (ncand <= 512 when p > 8)");
   return LAGP_OK;
 }
 
@@ -235,6 +242,8 @@ namespace lagp {
 // and a status word).
 size_t predict_per_location_bytes(const lagp_design* d, const lagp_params* P, bool have_cand) {
   const int n = P->n, nc = P->ncand;
+  if (P->scoring == LAGP_SCORING_CHOL)  // the search state stays on chip
+    return (have_cand ? 0 : knn2_bytes_per_location(nc) + 1024 + sizeof(int32_t) * (size_t)nc) + sizeof(int32_t);
   const int n0 = P->search == LAGP_SEARCH_NN ? n : P->n0;
   const int ncs = (nc + 15) & ~15;
   const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? (n + 3) / 4 * 4 : n0;  // exact tiles read whole chunks
@@ -276,7 +285,8 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const int S = lagp::knn_sort_size(nc);
   const int lds_max = max_lds_per_block();
   if (!cand_in && knn2_merge_lds_bytes(S) > (size_t)lds_max) return fail(LAGP_EINVAL, "ncand too large for LDS");
-  if (lagp::local_lds_bytes(n, ncs, p, rays, P->precision == LAGP_PREC_MIXED) > (size_t)lds_max)
+  const bool chol = P->scoring == LAGP_SCORING_CHOL;
+  if (!chol && lagp::local_lds_bytes(n, ncs, p, rays, P->precision == LAGP_PREC_MIXED) > (size_t)lds_max)
     return fail(LAGP_EINVAL, "local design too large for LDS (n, p, numrays)");
   const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? (n + 3) / 4 * 4 : n0;  // exact tiles read whole chunks
   // per-location workspace: kNN buffers and candidate list (unless given),
@@ -285,11 +295,12 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t b_knn = cand_in ? 0 : knn2_bytes_per_location(nc) + 1024;
   const size_t b_cand = cand_in ? 0 : sizeof(int32_t) * (size_t)nc;
-  const size_t b_kc = sizeof(double) * (size_t)kc_rows * ncs;
+  // (the Cholesky form keeps its search state on chip)
+  const size_t b_kc = chol ? 0 : sizeof(double) * (size_t)kc_rows * ncs;
   const size_t b_kc32 = P->precision == LAGP_PREC_MIXED ? sizeof(float) * (size_t)kc_rows * ncs : 0;
-  const size_t b_kxc = sizeof(double) * (size_t)ncs;
-  const size_t b_xc = sizeof(double) * (size_t)ncs * p;
-  const size_t b_chol = sizeof(double) * 2 * (size_t)n0 * n0;
+  const size_t b_kxc = chol ? 0 : sizeof(double) * (size_t)ncs;
+  const size_t b_xc = chol ? 0 : sizeof(double) * (size_t)ncs * p;
+  const size_t b_chol = chol ? 0 : sizeof(double) * 2 * (size_t)n0 * n0;
   const int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget);
   Workspace ws;
   ws.s = s;
@@ -342,7 +353,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.brent_tol = P->brent_tol > 0.0 ? P->brent_tol : std::ldexp(1.0, -13);
     a.g = P->g;
     for (int q = 0; q < P->d_len; ++q) a.w[q] = 1.0 / P->d[q];
-    LAGP_HIP(lagp::launch_local(a, s));
+    LAGP_HIP(chol ? lagp::launch_chol(a, s) : lagp::launch_local(a, s));
   }
   return LAGP_OK;
 }

@@ -21,11 +21,33 @@
 
 namespace lagp {
 
+// Taylor coefficients of exp in Horner order: 1/m! for m = 13 .. 2 (i = 0 ..
+// 11), each the correctly rounded quotient of exact integers.
+__host__ __device__ constexpr double gexp_coef(int i) {
+  switch (i) {
+    case 0: return 1.0 / 6227020800.0;
+    case 1: return 1.0 / 479001600.0;
+    case 2: return 1.0 / 39916800.0;
+    case 3: return 1.0 / 3628800.0;
+    case 4: return 1.0 / 362880.0;
+    case 5: return 1.0 / 40320.0;
+    case 6: return 1.0 / 5040.0;
+    case 7: return 1.0 / 720.0;
+    case 8: return 1.0 / 120.0;
+    case 9: return 1.0 / 24.0;
+    case 10: return 1.0 / 6.0;
+    default: return 0.5;
+  }
+}
+
 // exp(x) = 2^k exp(r), k = rint(x / ln2), r = x - k ln2 computed with ln2 as
 // the double nearest to it plus the remainder (two fused multiply-adds);
 // exp(r), |r| <= ln2/2, by its Taylor polynomial to degree 13 in Horner form
 // (truncation below 1e-17 relative).  Faithful (< 1 ulp) on [-708, 709].
-__device__ __forceinline__ double gexp(double x) {
+// coef(i) supplies gexp_coef(i); a kernel short of registers may read the
+// same values from LDS instead of holding them as constants.
+template <class Coef>
+__device__ __forceinline__ double gexp_with(double x, const Coef& coef) {
   if (x != x) return x;
   if (x < -708.0) return 0.0;
   if (x > 709.0) return __builtin_huge_val();
@@ -35,22 +57,16 @@ __device__ __forceinline__ double gexp(double x) {
   const double k = __builtin_rint(x * IL2);
   double r = __builtin_fma(-k, L2H, x);
   r = __builtin_fma(-k, L2L, r);
-  // 1/m! for m = 13 .. 2, each the correctly rounded quotient of exact ints
-  double t = 1.0 / 6227020800.0;
-  t = __builtin_fma(t, r, 1.0 / 479001600.0);
-  t = __builtin_fma(t, r, 1.0 / 39916800.0);
-  t = __builtin_fma(t, r, 1.0 / 3628800.0);
-  t = __builtin_fma(t, r, 1.0 / 362880.0);
-  t = __builtin_fma(t, r, 1.0 / 40320.0);
-  t = __builtin_fma(t, r, 1.0 / 5040.0);
-  t = __builtin_fma(t, r, 1.0 / 720.0);
-  t = __builtin_fma(t, r, 1.0 / 120.0);
-  t = __builtin_fma(t, r, 1.0 / 24.0);
-  t = __builtin_fma(t, r, 1.0 / 6.0);
-  t = __builtin_fma(t, r, 0.5);
+  double t = coef(0);
+#pragma unroll
+  for (int i = 1; i < 12; ++i) t = __builtin_fma(t, r, coef(i));
   t = __builtin_fma(t, r, 1.0);
   t = __builtin_fma(t, r, 1.0);
   return __builtin_ldexp(t, (int)k);
+}
+
+__device__ __forceinline__ double gexp(double x) {
+  return gexp_with(x, [](int i) { return gexp_coef(i); });
 }
 
 // Squared Euclidean distance with one fma per dimension, in order.

@@ -91,6 +91,11 @@ size_t knn2_merge_lds_bytes(int S);
 size_t local_lds_bytes(int n, int ncs, int p, int numrays, bool mixed);
 hipError_t launch_local(const LocalArgs& a, hipStream_t s);
 
+// Exhaustive search by incremental Cholesky columns (chol.hip): whether a
+// shape fits its kernels, and the launch (no workspace beyond the arguments).
+bool chol_supported(int n, int ncand, int p, size_t lds_max);
+hipError_t launch_chol(const LocalArgs& a, hipStream_t s);
+
 hipError_t launch_bbox(const double* X, int64_t N, int p, double* lo, double* hi, hipStream_t s);
 
 // Shared by the C ABI and the server (api.cpp).

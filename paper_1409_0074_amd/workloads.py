@@ -30,6 +30,9 @@ SEARCH_NN = 2
 PREC_FP64 = 0
 PREC_MIXED = 1
 
+SCORING_PARTINV = 0
+SCORING_CHOL = 1
+
 
 @dataclasses.dataclass
 class Params:
@@ -40,7 +43,9 @@ class Params:
     SEARCH_*; numrays: rays per greedy step (ray search); d: lengthscale(s),
     one value (isotropic) or p values (separable); g: nugget; precision:
     PREC_FP64 or PREC_MIXED; rescore_k: FP64 re-scored shortlist in the mixed
-    form; brent_maxit / brent_tol: the line-search budget and tolerance.
+    form; brent_maxit / brent_tol: the line-search budget and tolerance;
+    scoring: SCORING_PARTINV (partitioned-inverse updates) or SCORING_CHOL
+    (incremental Cholesky columns) for exhaustive search.
     """
 
     n0: int = 6
@@ -54,6 +59,7 @@ class Params:
     rescore_k: int = 16
     brent_maxit: int = 100
     brent_tol: float = 2.0 ** -13
+    scoring: int = SCORING_PARTINV
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

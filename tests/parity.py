@@ -63,3 +63,4 @@ def check_replay(w, params, g, XX=None, rtol=VALUE_RTOL, bit_exact_values=False)
         assert np.array_equal(g["mean"], o["mean"]) and np.array_equal(g["s2"], o["s2"])
     return dict(steps=int(gap.size), exempt=int(exempt.sum()), max_err_mu=float(e_mu.max()),
                 max_err_s2=float(e_s2.max()), min_gap=float(gap.min()))
+

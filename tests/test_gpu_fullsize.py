@@ -74,6 +74,20 @@ def test_uniform8d_full_size_sampled(lg, search):
     assert np.array_equal(g["mean"][idx], o["mean"]) and np.array_equal(g["s2"][idx], o["s2"])
 
 
+def test_uniform8d_full_size_sampled_chol(lg):
+    """The same full-size workload with Cholesky-column scoring, against the
+    oracle's Cholesky form on 24 sampled locations, bit for bit."""
+    w = W.uniform8d()
+    prm = w.params.replace(scoring=W.SCORING_CHOL)
+    g = _bench_calls(lg, w, prm)
+    assert np.all(g["status"] == 0)
+    assert np.all(g["df"] == prm.n)
+    idx = _sample(w.XX.shape[0], 24, 507)
+    o = oracle.predict(w.X, w.y, w.XX[idx], prm)
+    assert np.array_equal(g["sel"][idx], o["sel"])
+    assert np.array_equal(g["mean"][idx], o["mean"]) and np.array_equal(g["s2"][idx], o["s2"])
+
+
 def test_grid2d_full_size_sampled(lg):
     """1000 x 1000 grid design, n = 100, N' = 4000, the first 2000 locations
     through lagp_predict (as the benchmark's grid leg), 6 sampled locations

@@ -525,3 +525,165 @@ def test_singular_start_reports_nan(orc):
     out = orc.predict(X, y, X[:3] + 0.0, prm, nthreads=1)
     assert np.all(np.isnan(out["mean"])) and np.all(out["status"] & orc.STATUS_NOTPD)
     assert np.all(out["sel"][:, 4:] == -1)
+
+
+# ---------------------------------------------- Cholesky form of the search --
+
+def _mp_alc_all(X, x, J, cands, d, g):
+    """Integrand of Eq. alc at x for each candidate row, with 40-digit
+    arithmetic on the design J (Cholesky solves in mpmath)."""
+    mp.mp.dps = 40
+    P = {int(r): [mp.mpf(float(v)) for v in X[r]] for r in list(J) + list(cands)}
+    xm = [mp.mpf(float(v)) for v in x]
+
+    def kk(a, b):
+        return mp.exp(-sum((ai - bi) ** 2 for ai, bi in zip(a, b)) / mp.mpf(d))
+
+    n = len(J)
+    K = mp.matrix(n, n)
+    for i in range(n):
+        for k in range(n):
+            K[i, k] = kk(P[int(J[i])], P[int(J[k])]) + (mp.mpf(g) if i == k else 0)
+    L = mp.cholesky(K)
+
+    def fsolve(b):
+        z = []
+        for i in range(n):
+            s = b[i]
+            for k in range(i):
+                s -= L[i, k] * z[k]
+            z.append(s / L[i, i])
+        return z
+
+    w = fsolve([kk(P[int(J[i])], xm) for i in range(n)])
+    out = []
+    for r in cands:
+        u = fsolve([kk(P[int(J[i])], P[int(r)]) for i in range(n)])
+        v = 1 + mp.mpf(g) - sum(ui * ui for ui in u)
+        c = kk(P[int(r)], xm) - sum(ui * wi for ui, wi in zip(u, w))
+        out.append(float(c * c / v))
+    return np.array(out)
+
+
+def test_chol_form_equals_partitioned_form_when_well_conditioned(orc):
+    """With a large nugget both forms are accurate to ~1e-12, so they must
+    choose the same designs and agree in every criterion value and in the
+    prediction (O7 against O4-O6)."""
+    w = W.tiny_2d(M=8)
+    prm = w.params.replace(g=1e-2, n=30)
+    a = orc.predict(w.X, w.y, w.XX, prm, nthreads=2)
+    b = orc.predict(w.X, w.y, w.XX, prm.replace(scoring=W.SCORING_CHOL), nthreads=2)
+    assert np.array_equal(a["sel"], b["sel"])
+    assert np.allclose(b["mean"], a["mean"], rtol=1e-10, atol=1e-14)
+    assert np.allclose(b["s2"], a["s2"], rtol=1e-10, atol=0)
+    assert np.allclose(b["diag"][:, :, 1], a["diag"][:, :, 1], rtol=1e-9, atol=0)
+    assert np.all(b["status"] == 0)
+    ta = orc.trace(w.X, w.y, w.XX[0], prm)
+    tb = orc.trace(w.X, w.y, w.XX[0], prm.replace(scoring=W.SCORING_CHOL))
+    fin = np.isfinite(ta["alc"])
+    assert np.array_equal(fin, np.isfinite(tb["alc"]))
+    for step in range(ta["alc"].shape[0]):
+        f = fin[step]
+        top = np.max(ta["alc"][step][f])
+        assert np.allclose(tb["alc"][step][f], ta["alc"][step][f], rtol=1e-8, atol=1e-10 * top), step
+
+
+def test_chol_form_vs_high_precision_at_small_nugget(orc):
+    """g = 1e-6: v_c sits near g at late steps, so FP64 criterion values
+    lose digits in proportion to 1/v_c.  The Cholesky form's values stay
+    within 1e-6 of 40-digit arithmetic on every step, its choice is the
+    40-digit argmax wherever the top two differ by more than 1e-6, and its
+    prediction is within 1e-9 (mean) / 1e-7 (scale) of 40-digit values."""
+    rng = np.random.default_rng(21)
+    X = rng.random((300, 2))
+    y = W.f_bump2(X)
+    x = np.array([0.43, 0.55])
+    d, g = 0.1, 1e-6
+    prm = W.Params(n0=4, n=20, ncand=80, d=(d,), g=g, scoring=W.SCORING_CHOL)
+    tr = orc.trace(X, y, x, prm)
+    cand, sel = tr["cand"], list(tr["sel"])
+    worst = 0.0
+    for step in range(prm.n - prm.n0):
+        j = prm.n0 + step
+        free = [q for q in range(prm.ncand) if int(cand[q]) not in sel[:j]]
+        hp = _mp_alc_all(X, x, sel[:j], [cand[q] for q in free], d, g)
+        got = tr["alc"][step][free]
+        worst = max(worst, float(np.max(np.abs(got - hp) / hp)))
+        o = np.argsort(-hp)
+        if (hp[o[0]] - hp[o[1]]) / hp[o[0]] > 1e-6:
+            assert int(cand[free[o[0]]]) == sel[j], step
+    assert worst <= 1e-6, worst
+    mp.mp.dps = 40
+    J = sel
+    P = [[mp.mpf(float(v)) for v in X[r]] for r in J]
+    xm = [mp.mpf(float(v)) for v in x]
+    kk = lambda a, b: mp.exp(-sum((ai - bi) ** 2 for ai, bi in zip(a, b)) / mp.mpf(d))
+    n = len(J)
+    K = mp.matrix(n, n)
+    for i in range(n):
+        for k in range(n):
+            K[i, k] = kk(P[i], P[k]) + (mp.mpf(g) if i == k else 0)
+    kx = mp.matrix([kk(P[i], xm) for i in range(n)])
+    yJ = mp.matrix([mp.mpf(float(y[r])) for r in J])
+    a1, a2 = mp.lu_solve(K, kx), mp.lu_solve(K, yJ)
+    mu = float(sum(a1[i] * yJ[i] for i in range(n)))
+    s2 = float(sum(yJ[i] * a2[i] for i in range(n)) * (1 + mp.mpf(g) - sum(kx[i] * a1[i] for i in range(n))) / n)
+    assert abs(tr["mean"] - mu) <= 1e-9 * abs(mu)
+    assert abs(tr["s2"] - s2) <= 1e-7 * s2
+
+
+def test_chol_form_full_design_reproduces_full_gp(orc):
+    """n = N' = N: the Cholesky form's prediction is the full GP's."""
+    rng = np.random.default_rng(22)
+    N = 40
+    X = rng.random((N, 2))
+    y = W.f_bump2(X)
+    XX = rng.random((4, 2))
+    g, d = 1e-3, 0.1
+    prm = W.Params(n0=2, n=N, ncand=N, d=(d,), g=g, scoring=W.SCORING_CHOL)
+    out = orc.predict(X, y, XX, prm, nthreads=2)
+    K = _gauss(X, X, d) + g * np.eye(N)
+    psi = y @ np.linalg.solve(K, y)
+    for m in range(4):
+        k = _gauss(X, XX[m][None], d)[:, 0]
+        assert out["mean"][m] == pytest.approx(k @ np.linalg.solve(K, y), rel=1e-9, abs=1e-12)
+        assert out["s2"][m] == pytest.approx(psi * ((1.0 + g) - k @ np.linalg.solve(K, k)) / N, rel=1e-7)
+        assert sorted(out["sel"][m]) == list(range(N))
+
+
+def test_chol_form_start_only_is_nearest_neighbour_kriging(orc):
+    """n0 = n: no greedy step; the factor of the n nearest gives their kriging
+    prediction (Sec. 2.2)."""
+    rng = np.random.default_rng(23)
+    X = rng.random((500, 3))
+    y = W.f_sines8(np.pad(X, ((0, 0), (0, 0))))
+    XX = rng.random((4, 3))
+    g, d, n = 1e-4, 0.3, 18
+    prm = W.Params(n0=n, n=n, ncand=40, d=(d,), g=g, scoring=W.SCORING_CHOL)
+    out = orc.predict(X, y, XX, prm, nthreads=2)
+    for m in range(4):
+        J = np.argsort(((X - XX[m]) ** 2).sum(1), kind="stable")[:n]
+        K = _gauss(X[J], X[J], d) + g * np.eye(n)
+        k = _gauss(X[J], XX[m][None], d)[:, 0]
+        assert out["mean"][m] == pytest.approx(k @ np.linalg.solve(K, y[J]), rel=1e-9, abs=1e-12)
+        assert list(out["sel"][m]) == list(J)
+
+
+def test_chol_form_choice_is_argmax_of_its_scores(orc):
+    """Every step takes the largest criterion among free candidates, lowest
+    rank on ties, and records it."""
+    w = W.tiny_2d(M=1)
+    prm = w.params.replace(n=30, scoring=W.SCORING_CHOL)
+    tr = orc.trace(w.X, w.y, w.XX[0], prm)
+    for step in range(prm.n - prm.n0):
+        a = np.where(np.isnan(tr["alc"][step]), -np.inf, tr["alc"][step])
+        q = int(np.argmax(a))
+        assert tr["sel"][prm.n0 + step] == tr["cand"][q]
+        assert tr["diag"][step][1] == a[q]
+
+
+def test_chol_form_singular_start(orc):
+    X = np.repeat(np.random.default_rng(107).random((300, 2)), 2, axis=0)
+    prm = W.Params(n0=4, n=10, ncand=40, d=(0.1,), g=0.0, scoring=W.SCORING_CHOL)
+    out = orc.predict(X, W.f_bump2(X), X[:3].copy(), prm, nthreads=1)
+    assert np.all(np.isnan(out["mean"])) and np.all(out["status"] & orc.STATUS_NOTPD)
