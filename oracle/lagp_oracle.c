@@ -439,8 +439,9 @@ double orc_ray_segment(const double *a, const double *x, const double *lo, const
  *   r_q   = y_q - z^T u_q              z = L^{-1} y_J
  * so that k_J(x_q)^T K_J^{-1} k_J(x) = u_q^T w and the integrand of Eq. alc
  * at x is cov_q^2 / v_q.  Taking candidate t appends (u_t^T, l) to L with
- * l = sqrt(v_t), w_j = cov_t / l, z_j = r_t / l, and every free q gets
- *   u_q[j] = (K(x_t, x_q) - u_t^T u_q) / l
+ * l = sqrt(v_t); with li = 1/l (one IEEE division), w_j = cov_t li,
+ * z_j = r_t li, and every free q gets
+ *   u_q[j] = (K(x_t, x_q) - u_t^T u_q) li
  * after which v_q, cov_q and r_q drop u_q[j]^2, w_j u_q[j] and z_j u_q[j].
  * The n0 nearest enter first, in rank order (that is the Cholesky
  * factorisation of the starting K_J, Sec. 2.2).  Prediction: mean w^T z,
@@ -503,8 +504,8 @@ static int local_one_chol(const ctx_t *c, scratch_t *s, const double *x, const i
             return ORC_STATUS_NOTPD | ORC_STATUS_NONFINITE;
         }
         if (!(v[take] > 0.0)) status |= ORC_STATUS_VNONPOS;
-        const double l = sqrt(v[take]);
-        const double wj = cov[take] / l, zj = r[take] / l;
+        const double l = sqrt(v[take]), li = 1.0 / l;
+        const double wj = cov[take] * li, zj = r[take] * li;
         const double bj = (1.0 + c->g) - qq; /* (1+g) - k_x^T K_j^{-1} k_x before the step */
         mu = fma(wj, zj, mu);
         psi = fma(zj, zj, psi);
@@ -529,7 +530,7 @@ static int local_one_chol(const ctx_t *c, scratch_t *s, const double *x, const i
             if (s->inJ[q]) continue;
             double d = 0.0;
             for (int k = 0; k < j; k++) d = fma(U[(size_t)k * nc + take], U[(size_t)k * nc + q], d);
-            const double e = (kern(xt, X + s->cand[q] * p, p, c->d, c->d_len) - d) / l;
+            const double e = (kern(xt, X + s->cand[q] * p, p, c->d, c->d_len) - d) * li;
             U[(size_t)j * nc + q] = e;
             v[q] = fma(-e, e, v[q]);
             cov[q] = fma(-wj, e, cov[q]);

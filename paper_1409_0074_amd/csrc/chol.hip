@@ -10,9 +10,9 @@
 // (the integrand of Eq. (alc) at the location itself) is cov_c^2 / v_c.
 // Adding candidate w appends the row (u_w^T, l) to L with l = sqrt(v_w).
 // Every other candidate gains the entry
-//   e_c = (K(x_w, x_c) - u_w^T u_c) / l
+//   e_c = (K(x_w, x_c) - u_w^T u_c) (1 / l)
 // and v_c -= e_c^2, cov_c -= (cov_w / l) e_c, q_c -= (q_w / l) e_c; the new
-// entries of w_x and z are cov_w / l and q_w / l.  After n points
+// entries of w_x and z are cov_w (1 / l) and q_w (1 / l).  After n points
 //   mean = w_x^T z,  psi = z^T z,  k_x^T K^{-1} k_x = w_x^T w_x
 // give Eqs. (predgp), (preds2) with n local points.  The starting design
 // (the n0 nearest, Sec. 2.2) is the same recursion with the choice forced.
@@ -20,7 +20,11 @@
 // A step costs one length-j inner product per candidate instead of the
 // j x j contraction of the partitioned-inverse form, and a location's whole
 // state (u_c in registers, candidate coordinates in LDS) stays on chip, so
-// the search reads nothing from memory after its prologue.  It computes the
+// the search reads nothing from memory after its prologue.  Each thread
+// holds two neighbouring candidates (2t, 2t+1): the per-step work that does
+// not depend on the candidate (the winner's column read from LDS, the
+// reductions, the barrier) is shared by two, and the two inner products
+// are independent chains.  It computes the
 // same criterion and prediction in a different rounding order: results agree
 // with the partitioned-inverse definition to rounding, not bit for bit.
 #include "dev_math.h"
@@ -33,22 +37,23 @@ namespace {
 constexpr int CH_CHUNK = 8;  // u entries per statically indexed block
 
 // NU: u entries kept per candidate (designs up to NU + 1 points); PM:
-// coordinate rows (p <= PM, rows p .. PM-1 zero); TS: LDS row stride and
-// largest workgroup (N' <= TS).
-template <int NU, int PM, int TS>
+// coordinate rows (p <= PM, rows p .. PM-1 zero); CS: candidate slots, the
+// LDS row stride (N' <= CS), two per thread.
+template <int NU, int PM, int CS>
 struct ChCfg {
-  // the first UL entries of every u_c live in LDS (ul[k * TS + c]), the rest
+  // the first UL entries of every u_c live in LDS (ul[k * CS + c]), the rest
   // in registers
   static constexpr int UL = NU > 32 ? CH_CHUNK : 0;
   static constexpr int NUP = (NU + CH_CHUNK - 1) / CH_CHUNK * CH_CHUNK;
   static constexpr int SS = NUP + 4;  // slot: u (zero padded), v, cov, q, pad
   static constexpr int NCH = NU / CH_CHUNK + 1;  // step blocks: j = 0 .. NU
-  static constexpr int NWV = TS / 64;
+  static constexpr int NT = CS / 2;              // largest workgroup
+  static constexpr int NWV = NT / 64;
 };
 
-// LDS: coordinates by dimension (PM x TS), the leading u entries (UL x TS),
-// two parities of per-wave slots and reduction words, the location, the
-// design ranks.
+// LDS: coordinates by dimension (PM x CS), the leading u entries (UL x CS),
+// two parities of per-wave slots and reduction words, the location, the exp
+// coefficients, the design ranks.
 struct ChLds {
   double* xs;
   double* ul;
@@ -56,24 +61,24 @@ struct ChLds {
   double* redv;  // 2 x NWV: best criterion of each wave
   double* red2;  // 2 x NWV: runner-up of each wave
   double* x;     // LAGP_MAX_DIM
-  double* ec;    // 12: the Taylor coefficients of exp (read per use, not held in registers)
+  double* ec;    // 12: Taylor coefficients of exp (read per use, not held in registers)
   int* redi;     // 2 x NWV: rank of each wave's best
   int* J;        // n
 };
 
-__host__ __device__ constexpr size_t ch_lds_bytes(int PM, int TS, int UL, int SS, int n) {
-  return sizeof(double) * ((size_t)(PM + UL) * TS + 2 * (size_t)(TS / 64) * SS + 4 * (size_t)(TS / 64) +
+__host__ __device__ constexpr size_t ch_lds_bytes(int PM, int CS, int UL, int SS, int n) {
+  return sizeof(double) * ((size_t)(PM + UL) * CS + 2 * (size_t)(CS / 128) * SS + 4 * (size_t)(CS / 128) +
                            LAGP_MAX_DIM + 12) +
-         sizeof(int) * (2 * (size_t)(TS / 64) + (size_t)n);
+         sizeof(int) * (2 * (size_t)(CS / 128) + (size_t)n);
 }
 
-template <int NU, int PM, int TS>
+template <int NU, int PM, int CS>
 __device__ inline ChLds ch_carve(unsigned char* s) {
-  using C = ChCfg<NU, PM, TS>;
+  using C = ChCfg<NU, PM, CS>;
   ChLds L;
   L.xs = reinterpret_cast<double*>(s);
-  L.ul = L.xs + PM * TS;
-  L.slot = L.ul + C::UL * TS;
+  L.ul = L.xs + PM * CS;
+  L.slot = L.ul + C::UL * CS;
   L.redv = L.slot + 2 * C::NWV * C::SS;
   L.red2 = L.redv + 2 * C::NWV;
   L.x = L.red2 + 2 * C::NWV;
@@ -83,35 +88,42 @@ __device__ inline ChLds ch_carve(unsigned char* s) {
   return L;
 }
 
-// Gaussian correlation between candidates ca and cb (columns of xs) in the
-// rounding of corr(): dimension order, one fused multiply-add per term (the
-// zero rows past p add exact zeros).
-template <int PM, int TS>
-__device__ __forceinline__ double ch_corr(const double* xs, const double* ec, int ca, int cb, const LocalArgs& A) {
-  const auto coef = [ec](int i) { return ec[i]; };
-  double s = 0.0;
-  if (A.dlen == 1) {
-#pragma unroll
-    for (int k = 0; k < PM; ++k) {
-      const double t = xs[k * TS + ca] - xs[k * TS + cb];
-      s = __builtin_fma(t, t, s);
-    }
-    return gexp_with(-(s * A.w[0]), coef);
-  }
-#pragma unroll
-  for (int k = 0; k < PM; ++k) {
-    const double t = xs[k * TS + ca] - xs[k * TS + cb];
-    s = __builtin_fma(t * t, A.w[k], s);
-  }
-  return gexp_with(-s, coef);
+// DPP lane move of a double (both halves), rows outside ROWMASK keep v.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double ch_dpp(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = (int)(uint32_t)b, hi = (int)(uint32_t)(b >> 32);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi2 << 32) | (uint64_t)(uint32_t)lo2);
 }
 
-// Per-thread state of one candidate (u entries below UL are in LDS).
+__device__ __forceinline__ double ch_readlane(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Maximum over the wave (a value in every lane): quad swaps, half-row and
+// row mirrors, then the row broadcasts; lane 63 ends with the maximum.
+__device__ __forceinline__ double ch_wave_max(double v) {
+  v = fmax(v, ch_dpp<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
+  v = fmax(v, ch_dpp<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
+  v = fmax(v, ch_dpp<0x141, 0xF>(v));  // row_half_mirror
+  v = fmax(v, ch_dpp<0x140, 0xF>(v));  // row_mirror
+  v = fmax(v, ch_dpp<0x142, 0xA>(v));  // row_bcast:15 into rows 1 and 3
+  v = fmax(v, ch_dpp<0x143, 0xC>(v));  // row_bcast:31 into rows 2 and 3
+  return ch_readlane(v, 63);
+}
+
+// Per-thread state of the candidate pair (2t, 2t+1); u entries below UL are
+// in LDS.
 template <int NU>
-struct ChState {
-  double u[NU];
-  double v, cov, q;
-  bool act;
+struct ChPair {
+  double u0[NU], u1[NU];
+  double v[2], cov[2], q[2];
+  bool act[2];
   int vflag;
 };
 
@@ -122,27 +134,76 @@ struct ChRun {
   bool pd, stop;
 };
 
-template <int NU, int PM, int TS, int B>
-__device__ __forceinline__ void ch_write_slot(double* sl, const ChState<NU>& S, const ChLds& L) {
-  using C = ChCfg<NU, PM, TS>;
-  constexpr int KE = (B + 1) * CH_CHUNK < NU ? (B + 1) * CH_CHUNK : NU;
+// Gaussian correlation between the winner w and candidate c in the rounding
+// of corr(): dimension order, one fused multiply-add per term (the zero rows
+// past p add exact zeros).  The coordinates of c come in a (c, c+1) pair.
+template <int PM>
+__device__ __forceinline__ void ch_corr2(const double* xs, int CS, int w, int c0, const double* ec, const LocalArgs& A,
+                                         double& k0, double& k1) {
+  const auto coef = [ec](int i) { return ec[i]; };
+  double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-  for (int k = 0; k < KE; ++k) sl[k] = k < C::UL ? L.ul[k * TS + threadIdx.x] : S.u[k];
-  sl[C::NUP] = S.v;
-  sl[C::NUP + 1] = S.cov;
-  sl[C::NUP + 2] = S.q;
+  for (int k = 0; k < PM; ++k) {
+    const double xw = xs[k * CS + w];
+    const double2 xc = *reinterpret_cast<const double2*>(xs + k * CS + c0);
+    const double t0 = xw - xc.x, t1 = xw - xc.y;
+    if (A.dlen == 1) {
+      s0 = __builtin_fma(t0, t0, s0);
+      s1 = __builtin_fma(t1, t1, s1);
+    } else {
+      s0 = __builtin_fma(t0 * t0, A.w[k], s0);
+      s1 = __builtin_fma(t1 * t1, A.w[k], s1);
+    }
+  }
+  if (A.dlen == 1) {
+    s0 = s0 * A.w[0];
+    s1 = s1 * A.w[0];
+  }
+  k0 = gexp_with(-s0, coef);
+  k1 = gexp_with(-s1, coef);
+}
+
+// Publish candidate 2t + which: its u (zero padded to the block), v, cov, q.
+template <int NU, int PM, int CS, int B>
+__device__ __forceinline__ void ch_write_slot(double* sl, const ChPair<NU>& S, int which, const ChLds& L) {
+  using C = ChCfg<NU, PM, CS>;
+  constexpr int KE = (B + 1) * CH_CHUNK < NU ? (B + 1) * CH_CHUNK : NU;
+  const int c = 2 * threadIdx.x + which;
+  if (which == 0) {
+#pragma unroll
+    for (int k = 0; k < KE; ++k) sl[k] = k < C::UL ? L.ul[k * CS + c] : S.u0[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < KE; ++k) sl[k] = k < C::UL ? L.ul[k * CS + c] : S.u1[k];
+  }
+  sl[C::NUP] = which ? S.v[1] : S.v[0];  // (no run-time index into the state: it must stay in registers)
+  sl[C::NUP + 1] = which ? S.cov[1] : S.cov[0];
+  sl[C::NUP + 2] = which ? S.q[1] : S.q[0];
+}
+
+__device__ __forceinline__ double ch_score(const double v, const double cov, bool act, int& vflag) {
+  if (!act) return -1.0;
+  double sc;
+  if (v > 0.0) {
+    sc = cov * cov / v;
+  } else {
+    sc = 0.0;
+    vflag = 1;
+  }
+  return sc >= 0.0 ? sc : -1.0;  // NaN: never chosen
 }
 
 // Steps j = B*CH_CHUNK .. B*CH_CHUNK + CH_CHUNK - 1: choose design point j
 // (forced to rank j while j < n0, else the largest criterion, lowest rank on
 // ties), publish its column, extend every other candidate's.
-template <int NU, int PM, int TS, bool DIAG, int B>
-__device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChState<NU>& S, ChRun& R, int64_t m) {
-  using C = ChCfg<NU, PM, TS>;
+template <int NU, int PM, int CS, bool DIAG, int B>
+__device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChPair<NU>& S, ChRun& R, int64_t m) {
+  using C = ChCfg<NU, PM, CS>;
   constexpr int NUP = C::NUP, SS = C::SS, UL = C::UL, NWV = C::NWV;
   constexpr int KE = (B + 1) * CH_CHUNK < NU ? (B + 1) * CH_CHUNK : NU;  // u entries in use up to this block
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nwv = blockDim.x >> 6;
+  const int c0 = 2 * tid;
   const int n = a.n, n0 = a.n0;
   for (int jj = 0; jj < CH_CHUNK; ++jj) {
     const int j = B * CH_CHUNK + jj;
@@ -150,64 +211,49 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChS
     const int par = j & 1;
     double* sl = L.slot + par * NWV * SS;
     if (j < n0) {
-      if (tid == j) ch_write_slot<NU, PM, TS, B>(sl + wv * SS, S, L);
+      if ((j >> 1) == tid) ch_write_slot<NU, PM, CS, B>(sl + wv * SS, S, j & 1, L);
     } else {
-      double sc = -1.0;
-      if (S.act) {
-        if (S.v > 0.0) {
-          sc = S.cov * S.cov / S.v;
-        } else {
-          sc = 0.0;
-          S.vflag = 1;
-        }
-        if (!(sc >= 0.0)) sc = -1.0;  // NaN: never chosen
-      }
-      // wave maximum, then its lowest lane
-      double wmax = sc;
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) wmax = fmax(wmax, __shfl_xor(wmax, o, 64));
-      const uint64_t hit = __ballot(sc == wmax && wmax >= 0.0);
+      const double s0 = ch_score(S.v[0], S.cov[0], S.act[0], S.vflag);
+      const double s1 = ch_score(S.v[1], S.cov[1], S.act[1], S.vflag);
+      const int pick = s1 > s0 ? 1 : 0;  // the lower rank on ties
+      const double pb = pick ? s1 : s0;
+      const double wmax = ch_wave_max(pb);
+      const uint64_t hit = __ballot(pb == wmax && wmax >= 0.0);
       const int wl = hit ? __builtin_ctzll(hit) : -1;
-      if (lane == wl) ch_write_slot<NU, PM, TS, B>(sl + wv * SS, S, L);
-      if constexpr (DIAG) {
-        double s2 = lane == wl ? -1.0 : sc;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) s2 = fmax(s2, __shfl_xor(s2, o, 64));
-        if (lane == 0) L.red2[par * NWV + wv] = s2;
-      }
-      if (lane == 0) {
+      if (lane == wl) ch_write_slot<NU, PM, CS, B>(sl + wv * SS, S, pick, L);
+      if (lane == (wl >= 0 ? wl : 0)) {
         L.redv[par * NWV + wv] = wl >= 0 ? wmax : -1.0;
-        L.redi[par * NWV + wv] = wl >= 0 ? (wv << 6) + wl : -1;
+        L.redi[par * NWV + wv] = wl >= 0 ? c0 + pick : -1;
+      }
+      if constexpr (DIAG) {
+        const double s2 = ch_wave_max(lane == wl ? (pick ? s0 : s1) : fmax(s0, s1));
+        if (lane == 0) L.red2[par * NWV + wv] = s2;
       }
     }
     __syncthreads();
     int w = j;
     double b1 = 0.0, b2 = 0.0;
     if (j >= n0) {
-      // earliest wave wins ties: rank order
-      b1 = -1.0;
-      b2 = -1.0;
-      w = -1;
-      for (int qw = 0; qw < nwv; ++qw) {
-        const double cv = L.redv[par * NWV + qw];
-        const int ci = L.redi[par * NWV + qw];
-        const double c2 = DIAG ? L.red2[par * NWV + qw] : -1.0;
-        if (ci >= 0 && cv > b1) {
-          b2 = fmax(b1, c2);
-          b1 = cv;
-          w = ci;
-        } else {
-          b2 = fmax(b2, ci >= 0 ? cv : -1.0);
-          if (DIAG) b2 = fmax(b2, c2);
-        }
+      // the best over waves; the earliest wave (lowest ranks) wins ties
+      double cv = -1.0, c2 = -1.0;
+      int ci = -1;
+      if (lane < nwv) {
+        ci = L.redi[par * NWV + lane];
+        cv = ci >= 0 ? L.redv[par * NWV + lane] : -1.0;
+        if constexpr (DIAG) c2 = L.red2[par * NWV + lane];
       }
-      if (w < 0) {  // no finite criterion anywhere: give up on x
+      const double gmax = ch_wave_max(cv);
+      const uint64_t gh = __ballot(cv == gmax && gmax >= 0.0);
+      if (!gh) {  // no finite criterion anywhere: give up on x
         R.stop = true;
         return;
       }
+      const int ql = __builtin_ctzll(gh);
+      w = __builtin_amdgcn_readlane(ci, ql);
+      b1 = gmax;
+      if constexpr (DIAG) b2 = ch_wave_max(lane == ql ? c2 : fmax(cv, c2));
     }
-    w = __builtin_amdgcn_readfirstlane(w);
-    const double* ws = sl + (w >> 6) * SS;
+    const double* ws = sl + (w >> 7) * SS;
     const double vw = ws[NUP], covw = ws[NUP + 1], qw = ws[NUP + 2];
     if (j < n0 && !(vw > 0.0)) {  // the starting covariance is not positive definite
       R.pd = false;
@@ -216,7 +262,8 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChS
     }
     if (!(vw > 0.0)) S.vflag = 1;
     const double l = __builtin_sqrt(vw);
-    const double wxj = covw / l, zj = qw / l;
+    const double li = 1.0 / l;
+    const double wxj = covw * li, zj = qw * li;
     if (tid == 0) {
       L.J[j] = w;
       R.mu = __builtin_fma(wxj, zj, R.mu);
@@ -228,96 +275,126 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChS
         dg[1] = b2 < 0.0 ? -__builtin_huge_val() : b2;
       }
     }
-    if (tid == w) S.act = false;
+    if (w == c0) S.act[0] = false;
+    if (w == c0 + 1) S.act[1] = false;
     R.done = j + 1;
-    if (j + 1 < n && S.act) {
-      const double kv = ch_corr<PM, TS>(L.xs, L.ec, w, tid, a);
-      double dot = 0.0;
+    if (j + 1 < n) {
+      // both candidates of the pair, taken or not (a taken one is never read again)
+      double kv0, kv1;
+      ch_corr2<PM>(L.xs, CS, w, c0, L.ec, a, kv0, kv1);
+      double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-      for (int k = 0; k < KE; ++k) dot = __builtin_fma(ws[k], k < UL ? L.ul[k * TS + tid] : S.u[k], dot);
-      const double e = (kv - dot) / l;
+      for (int k = 0; k < KE; ++k) {
+        const double wk = ws[k];
+        if (k < UL) {
+          const double2 uu = *reinterpret_cast<const double2*>(L.ul + k * CS + c0);
+          d0 = __builtin_fma(wk, uu.x, d0);
+          d1 = __builtin_fma(wk, uu.y, d1);
+        } else {
+          d0 = __builtin_fma(wk, S.u0[k], d0);
+          d1 = __builtin_fma(wk, S.u1[k], d1);
+        }
+      }
+      const double e0 = (kv0 - d0) * li, e1 = (kv1 - d1) * li;
 #pragma unroll
       for (int kk = 0; kk < CH_CHUNK; ++kk) {
         constexpr int K0 = B * CH_CHUNK;
         if (K0 + kk < NU && kk == jj) {
-          if (K0 + kk < UL)
-            L.ul[(K0 + kk) * TS + tid] = e;
-          else
-            S.u[K0 + kk < NU ? K0 + kk : 0] = e;
+          if (K0 + kk < UL) {
+            *reinterpret_cast<double2*>(L.ul + (K0 + kk) * CS + c0) = make_double2(e0, e1);
+          } else {
+            S.u0[K0 + kk < NU ? K0 + kk : 0] = e0;
+            S.u1[K0 + kk < NU ? K0 + kk : 0] = e1;
+          }
         }
       }
-      S.v = __builtin_fma(-e, e, S.v);
-      S.cov = __builtin_fma(-wxj, e, S.cov);
-      S.q = __builtin_fma(-zj, e, S.q);
+      S.v[0] = __builtin_fma(-e0, e0, S.v[0]);
+      S.v[1] = __builtin_fma(-e1, e1, S.v[1]);
+      S.cov[0] = __builtin_fma(-wxj, e0, S.cov[0]);
+      S.cov[1] = __builtin_fma(-wxj, e1, S.cov[1]);
+      S.q[0] = __builtin_fma(-zj, e0, S.q[0]);
+      S.q[1] = __builtin_fma(-zj, e1, S.q[1]);
     }
   }
 }
 
-template <int NU, int PM, int TS, bool DIAG, int B>
-__device__ __forceinline__ void ch_blocks(const LocalArgs& a, const ChLds& L, ChState<NU>& S, ChRun& R, int64_t m) {
-  if constexpr (B < ChCfg<NU, PM, TS>::NCH) {
-    ch_block<NU, PM, TS, DIAG, B>(a, L, S, R, m);
-    if (!R.stop && (B + 1) * CH_CHUNK < a.n) ch_blocks<NU, PM, TS, DIAG, B + 1>(a, L, S, R, m);
+template <int NU, int PM, int CS, bool DIAG, int B>
+__device__ __forceinline__ void ch_blocks(const LocalArgs& a, const ChLds& L, ChPair<NU>& S, ChRun& R, int64_t m) {
+  if constexpr (B < ChCfg<NU, PM, CS>::NCH) {
+    ch_block<NU, PM, CS, DIAG, B>(a, L, S, R, m);
+    if (!R.stop && (B + 1) * CH_CHUNK < a.n) ch_blocks<NU, PM, CS, DIAG, B + 1>(a, L, S, R, m);
   }
 }
 
-// One workgroup of 64 ceil(N'/64) <= TS threads per location, thread c for
-// the candidate of rank c.
-template <int NU, int PM, int TS, bool DIAG>
-__global__ __launch_bounds__(TS) __attribute__((amdgpu_waves_per_eu(4))) void k_chol(LocalArgs a) {
+// One workgroup of 64 ceil(N'/128) threads per location; thread t holds the
+// candidates of ranks 2t and 2t+1.
+template <int NU, int PM, int CS, bool DIAG>
+__global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) void k_chol(LocalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  using Cf = ChCfg<NU, PM, TS>;
-  const ChLds L = ch_carve<NU, PM, TS>(smem);
+  using Cf = ChCfg<NU, PM, CS>;
+  const ChLds L = ch_carve<NU, PM, CS>(smem);
   const int tid = threadIdx.x;
   const int64_t m = blockIdx.x;
   const int p = a.p, n = a.n, nc = a.ncand;
   const int32_t* C = a.cand + m * nc;
+  const int c0 = 2 * tid;
 
   if (tid < LAGP_MAX_DIM) L.x[tid] = tid < p ? a.XX[m * p + tid] : 0.0;
   if (tid < 12) L.ec[tid] = gexp_coef(tid);
-  ChState<NU> S;
+  ChPair<NU> S;
 #pragma unroll
-  for (int k = 0; k < NU; ++k) S.u[k] = 0.0;
-#pragma unroll
-  for (int k = 0; k < Cf::UL; ++k) L.ul[k * TS + tid] = 0.0;
-  S.act = tid < nc;
-  S.vflag = 0;
-  double yc = 0.0;
-  if (S.act) {
-    const int64_t row = C[tid];
-#pragma unroll
-    for (int k = 0; k < PM; ++k) L.xs[k * TS + tid] = k < p ? a.X[row * p + k] : 0.0;
-    yc = a.y[row];
-  } else {
-#pragma unroll
-    for (int k = 0; k < PM; ++k) L.xs[k * TS + tid] = 0.0;
+  for (int k = 0; k < NU; ++k) {
+    S.u0[k] = 0.0;
+    S.u1[k] = 0.0;
   }
-  __syncthreads();
-  double kx = 0.0;
-  if (S.act) {
-    double s = 0.0;
-    if (a.dlen == 1) {
 #pragma unroll
-      for (int k = 0; k < PM; ++k) {
-        const double t = L.xs[k * TS + tid] - L.x[k];
-        s = __builtin_fma(t, t, s);
-      }
-      kx = gexp(-(s * a.w[0]));
+  for (int k = 0; k < Cf::UL; ++k) *reinterpret_cast<double2*>(L.ul + k * CS + c0) = make_double2(0.0, 0.0);
+  S.vflag = 0;
+  double yc[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int c = c0 + i;
+    S.act[i] = c < nc;
+    yc[i] = 0.0;
+    if (S.act[i]) {
+      const int64_t row = C[c];
+#pragma unroll
+      for (int k = 0; k < PM; ++k) L.xs[k * CS + c] = k < p ? a.X[row * p + k] : 0.0;
+      yc[i] = a.y[row];
     } else {
 #pragma unroll
-      for (int k = 0; k < PM; ++k) {
-        const double t = L.xs[k * TS + tid] - L.x[k];
-        s = __builtin_fma(t * t, a.w[k], s);
-      }
-      kx = gexp(-s);
+      for (int k = 0; k < PM; ++k) L.xs[k * CS + c] = 0.0;
     }
   }
-  S.v = 1.0 + a.g;
-  S.cov = kx;
-  S.q = yc;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    double kx = 0.0;
+    if (S.act[i]) {
+      double s = 0.0;
+      if (a.dlen == 1) {
+#pragma unroll
+        for (int k = 0; k < PM; ++k) {
+          const double t = L.xs[k * CS + c0 + i] - L.x[k];
+          s = __builtin_fma(t, t, s);
+        }
+        kx = gexp(-(s * a.w[0]));
+      } else {
+#pragma unroll
+        for (int k = 0; k < PM; ++k) {
+          const double t = L.xs[k * CS + c0 + i] - L.x[k];
+          s = __builtin_fma(t * t, a.w[k], s);
+        }
+        kx = gexp(-s);
+      }
+    }
+    S.v[i] = 1.0 + a.g;
+    S.cov[i] = kx;
+    S.q[i] = yc[i];
+  }
 
   ChRun R{0.0, 0.0, 0.0, 0, true, false};
-  ch_blocks<NU, PM, TS, DIAG, 0>(a, L, S, R, m);
+  ch_blocks<NU, PM, CS, DIAG, 0>(a, L, S, R, m);
 
   const int vf = __syncthreads_or(S.vflag);
   const bool ok = R.pd && R.done == n;
@@ -345,14 +422,14 @@ __global__ __launch_bounds__(TS) __attribute__((amdgpu_waves_per_eu(4))) void k_
 constexpr int CH_NU_SMALL = 31;  // n <= 32
 constexpr int CH_NU_LARGE = 49;  // n <= 50
 
-template <int NU, int PM, int TS>
+template <int NU, int PM, int CS>
 constexpr size_t ch_bytes(int n) {
-  using C = ChCfg<NU, PM, TS>;
-  return ch_lds_bytes(PM, TS, C::UL, C::SS, n);
+  using C = ChCfg<NU, PM, CS>;
+  return ch_lds_bytes(PM, CS, C::UL, C::SS, n);
 }
 
 struct ChPick {
-  int nu, pm, ts;
+  int nu, pm, cs;
   size_t lds;
 };
 
@@ -360,40 +437,40 @@ ChPick ch_pick(int n, int ncand, int p) {
   ChPick k;
   k.nu = n <= CH_NU_SMALL + 1 ? CH_NU_SMALL : CH_NU_LARGE;
   k.pm = p <= 8 ? 8 : LAGP_MAX_DIM;
-  k.ts = ncand <= 512 ? 512 : 1024;
-  const bool small = k.nu == CH_NU_SMALL, p8 = k.pm == 8, t5 = k.ts == 512;
+  k.cs = ncand <= 512 ? 512 : 1024;
+  const bool small = k.nu == CH_NU_SMALL, p8 = k.pm == 8, c5 = k.cs == 512;
   if (small)
-    k.lds = p8 ? (t5 ? ch_bytes<CH_NU_SMALL, 8, 512>(n) : ch_bytes<CH_NU_SMALL, 8, 1024>(n))
-               : (t5 ? ch_bytes<CH_NU_SMALL, LAGP_MAX_DIM, 512>(n) : ch_bytes<CH_NU_SMALL, LAGP_MAX_DIM, 1024>(n));
+    k.lds = p8 ? (c5 ? ch_bytes<CH_NU_SMALL, 8, 512>(n) : ch_bytes<CH_NU_SMALL, 8, 1024>(n))
+               : (c5 ? ch_bytes<CH_NU_SMALL, LAGP_MAX_DIM, 512>(n) : ch_bytes<CH_NU_SMALL, LAGP_MAX_DIM, 1024>(n));
   else
-    k.lds = p8 ? (t5 ? ch_bytes<CH_NU_LARGE, 8, 512>(n) : ch_bytes<CH_NU_LARGE, 8, 1024>(n))
-               : (t5 ? ch_bytes<CH_NU_LARGE, LAGP_MAX_DIM, 512>(n) : ch_bytes<CH_NU_LARGE, LAGP_MAX_DIM, 1024>(n));
+    k.lds = p8 ? (c5 ? ch_bytes<CH_NU_LARGE, 8, 512>(n) : ch_bytes<CH_NU_LARGE, 8, 1024>(n))
+               : (c5 ? ch_bytes<CH_NU_LARGE, LAGP_MAX_DIM, 512>(n) : ch_bytes<CH_NU_LARGE, LAGP_MAX_DIM, 1024>(n));
   return k;
 }
 
-template <int NU, int PM, int TS, bool DIAG>
+template <int NU, int PM, int CS, bool DIAG>
 hipError_t launch_chol_t(const LocalArgs& a, size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol<NU, PM, TS, DIAG>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol<NU, PM, CS, DIAG>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int T = (a.ncand + 63) / 64 * 64;
-  hipLaunchKernelGGL((k_chol<NU, PM, TS, DIAG>), dim3(a.M), dim3(T), lds, s, a);
+  const int T = (a.ncand + 127) / 128 * 64;
+  hipLaunchKernelGGL((k_chol<NU, PM, CS, DIAG>), dim3(a.M), dim3(T), lds, s, a);
   return hipGetLastError();
 }
 
-template <int NU, int PM, int TS>
+template <int NU, int PM, int CS>
 hipError_t launch_chol_d(const LocalArgs& a, size_t lds, hipStream_t s) {
-  return a.diag ? launch_chol_t<NU, PM, TS, true>(a, lds, s) : launch_chol_t<NU, PM, TS, false>(a, lds, s);
+  return a.diag ? launch_chol_t<NU, PM, CS, true>(a, lds, s) : launch_chol_t<NU, PM, CS, false>(a, lds, s);
 }
 
 template <int NU, int PM>
-hipError_t launch_chol_ts(const LocalArgs& a, int ts, size_t lds, hipStream_t s) {
-  return ts == 512 ? launch_chol_d<NU, PM, 512>(a, lds, s) : launch_chol_d<NU, PM, 1024>(a, lds, s);
+hipError_t launch_chol_cs(const LocalArgs& a, int cs, size_t lds, hipStream_t s) {
+  return cs == 512 ? launch_chol_d<NU, PM, 512>(a, lds, s) : launch_chol_d<NU, PM, 1024>(a, lds, s);
 }
 
 template <int NU>
 hipError_t launch_chol_pm(const LocalArgs& a, const ChPick& k, hipStream_t s) {
-  return k.pm == 8 ? launch_chol_ts<NU, 8>(a, k.ts, k.lds, s) : launch_chol_ts<NU, LAGP_MAX_DIM>(a, k.ts, k.lds, s);
+  return k.pm == 8 ? launch_chol_cs<NU, 8>(a, k.cs, k.lds, s) : launch_chol_cs<NU, LAGP_MAX_DIM>(a, k.cs, k.lds, s);
 }
 
 }  // namespace
