@@ -4,9 +4,10 @@
 One step = the whole hot path over the predictive set of the uniform 8-d
 workload (N = 1e6 design points, M = 1e4 locations, n = 50, 1000 nearest
 candidates, exhaustive greedy ALC search): candidate kNN, then the local
-design search, partitioned-inverse updates and prediction.  Inputs are
-resident in HBM before timing starts.  The ray-search form (10 rays) runs on
-the same inputs and is reported beside it, as is the CPU oracle on a bounded
+design search (criterion scored through incremental Cholesky columns) and
+prediction.  Inputs are resident in HBM before timing starts.  The
+partitioned-inverse scoring form and the ray-search form (10 rays) run on the
+same inputs and are reported beside it, as is the CPU oracle on a bounded
 sample of locations.
 
     python bench.py [--steps K] [--warmup W]
@@ -24,27 +25,40 @@ import numpy as np
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of one exhaustive k_local launch over the uniform 8-d workload
-# (M = 1e4), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
-# `bench.py --steps 1 --warmup 0 --no-ray --no-cpu --no-serving
+# HBM traffic of one launch of each local-design kernel over the uniform 8-d
+# workload (M = 1e4), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)
+# of `bench.py --steps 1 --warmup 0 --no-ray --no-cpu --no-serving
 # --copy-calibration-mb 1024`, each scaled by what the counter read for a
 # 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the
-# kernel sources it was taken on (sha256 below); otherwise reported as null.
-KERNEL_SOURCES = ("paper_1409_0074_amd/csrc/local.hip", "paper_1409_0074_amd/csrc/dev_math.h",
-                  "paper_1409_0074_amd/csrc/lagp_internal.h", "paper_1409_0074_amd/csrc/api.cpp")
-MEASURED_TRAFFIC = {"sha256": "c56df06dca77fa4d5272ad81c4d49a476c0b5b00623a4bfbf52b1422e66826c4",
-                    "bytes": 1.40473e+11, "fetch_kib": 66303884.4, "write_kib": 4576782.4}
+# kernel sources it was taken on (sha256); otherwise reported as null.
+COMMON_SOURCES = ("paper_1409_0074_amd/csrc/dev_math.h", "paper_1409_0074_amd/csrc/lagp_internal.h",
+                  "paper_1409_0074_amd/csrc/api.cpp")
+KERNEL_SOURCES = {"k_chol": ("paper_1409_0074_amd/csrc/chol.hip",) + COMMON_SOURCES,
+                  "k_local": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES}
+MEASURED_TRAFFIC = {
+    "k_chol": {"sha256": "d5fbf2bffceb3be05e4173eb6f60f32e2a56b8bf43827eeafd0ac823cbb8bb1a",
+               "bytes": 2.295e9, "fetch_kib": 1119846.4, "write_kib": 1255.5},
+    "k_local": {"sha256": "df70cb53e2ae6201c135595ccf412d0a691cc8d41eb92d0b5ea156ceecfc23a4",
+                "bytes": 1.405e11, "fetch_kib": 66323586.4, "write_kib": 4578536.8},
+}
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources_sha256(kernel: str) -> str:
     import hashlib
 
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[kernel]:
         with open(os.path.join(here, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def measured_traffic(kernel: str, M: int):
+    t = MEASURED_TRAFFIC.get(kernel)
+    if t is None or M != 10000 or t["sha256"] != kernel_sources_sha256(kernel):
+        return None
+    return t["bytes"]
 
 
 def scoring_bytes(n0: int, n: int, ncand: int) -> float:
@@ -59,6 +73,19 @@ def scoring_flops(n0: int, n: int, ncand: int) -> float:
     the contraction K_j^{-1} [k_c] over the ncand - j remaining candidates,
     2 j^2 (ncand - j)."""
     return float(sum(2.0 * j * j * (ncand - j) for j in range(n0, n)))
+
+
+def chol_flops(n0: int, n: int, ncand: int, p: int) -> float:
+    """FLOPs of the Cholesky-column search per location, counting the
+    arithmetic each candidate does: after design point j is taken, the
+    ncand - j - 1 free candidates each run the length-j inner product
+    (2 j), the kernel value (4 p for the weighted squared distance, 34 for
+    exp: the reduction and the degree-13 Horner polynomial), the new entry
+    (2) and the updates of v, cov and q (6); every search step scores the
+    ncand - j free candidates (2: a square and a division)."""
+    upd = sum((ncand - j - 1) * (2.0 * j + 4 * p + 34 + 2 + 6) for j in range(n - 1))
+    score = sum(2.0 * (ncand - j) for j in range(n0, n))
+    return float(upd + score)
 
 
 def time_steps(fn, steps: int, events_per_step: int):
@@ -209,7 +236,7 @@ def main() -> int:
     y = torch.from_numpy(w.y).to(dev)
     XX = torch.from_numpy(w.XX).to(dev)
     design = lg.lagp_design_create(X, y)
-    P = lg.make_params(prm)
+    P = lg.make_params(prm, scoring=W.SCORING_CHOL)
     cand = torch.empty((M, nc), dtype=torch.int32, device=dev)
     f64 = dict(dtype=torch.float64, device=dev)
     mean, s2, df = torch.empty(M, **f64), torch.empty(M, **f64), torch.empty(M, **f64)
@@ -234,13 +261,9 @@ def main() -> int:
     value = M / (ms_step / 1e3)
     st = status.cpu().numpy()
 
-    flops = scoring_flops(prm.n0, prm.n, nc) * M
-    achieved = flops / (t_local / 1e3) / 1e12
-    nbytes = scoring_bytes(prm.n0, prm.n, nc) * M
-    achieved_gbs = nbytes / (t_local / 1e3) / 1e9
-    traffic = None
-    if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC["sha256"] == kernel_sources_sha256() and M == 10000:
-        traffic = MEASURED_TRAFFIC["bytes"]
+    p = int(w.X.shape[1])
+    cflops = chol_flops(prm.n0, prm.n, nc, p)
+    achieved = cflops * M / (t_local / 1e3) / 1e12
     result = {
         "metric": "local-GP predictions/sec at N=1e6, n=50 (exhaustive vs ray); p99 latency",
         "value": round(value, 2),
@@ -255,24 +278,59 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "N": int(w.X.shape[0]), "p": 8, "M": M, "n0": prm.n0, "n": prm.n,
-                   "ncand": nc, "search": "exhaustive", "kernel": "separable gaussian, d=0.5, g=1e-6",
+                   "ncand": nc, "search": "exhaustive", "scoring": "incremental cholesky columns",
+                   "kernel": "separable gaussian, d=0.5, g=1e-6",
                    "parallelism": "one GPU, data parallel over locations"},
         "phases_ms": {"knn": round(float(t_knn), 3), "local_design": round(float(t_local), 3)},
-        # the candidate rows stream from HBM once per step: 8.3 FLOP/B, under
-        # the FP64 ridge (78.6 TF/s / 8 TB/s = 9.8), so HBM is the bound
-        "roofline": {"bound": "hbm", "kernel": "k_local (exhaustive)", "achieved": round(achieved_gbs, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "work": f"sum_j 8 j (ncand - j), j = n0..n-1: {scoring_bytes(prm.n0, prm.n, nc):.4g} "
-                             f"B/location x {M} locations per launch",
-                     "mfma": {"achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                              "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                              "work": f"sum_j 2 j^2 (ncand - j): {scoring_flops(prm.n0, prm.n, nc):.4g} "
-                                      f"FLOP/location"}},
+        # the search state stays in registers and LDS (nothing streams from
+        # HBM after the candidate gather), so the bound is the FP64 vector
+        # rate: 256 CUs x 4 SIMDs x 16 FMA lanes x 2 x 2.4 GHz = 78.6 TF/s
+        "roofline": {"bound": "alu", "kernel": "k_chol (exhaustive search, Cholesky scoring)",
+                     "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic("k_chol", M),
+                     "work": f"{cflops:.4g} FLOP/location (inner products, kernel values, updates, scores) "
+                             f"x {M} locations per launch"},
         "status_nonzero": int((st != 0).sum()),
     }
     if calib is not None:
         result["copy_calibration"] = calib
+
+    # the partitioned-inverse scoring form (the paper's update; FP64 MFMA
+    # contraction over kernel rows streamed from HBM)
+    Pp = lg.make_params(prm)
+
+    def pstep(ev, sel_out=None):
+        step(ev, P=Pp, sel_out=sel_out)
+
+    pstep(dummy, sel_out=sel)
+    torch.cuda.synchronize()
+    pi_sel = sel.cpu().numpy().copy()
+    pi_mean = mean.cpu().numpy().copy()
+    (pk, pl), pwall = time_steps(pstep, args.ray_steps, 2)
+    pms = pwall / args.ray_steps
+    pflops = scoring_flops(prm.n0, prm.n, nc) * M
+    pbytes = scoring_bytes(prm.n0, prm.n, nc) * M
+    p_gbs = pbytes / (pl / 1e3) / 1e9
+    p_tf = pflops / (pl / 1e3) / 1e12
+    same = np.all(pi_sel == ex_sel, axis=1)
+    result["partitioned_inverse"] = {
+        "value": round(M / (pms / 1e3), 2), "unit": "predictions/s", "ms_per_step": round(pms, 3),
+        "phases_ms": {"knn": round(float(pk), 3), "local_design": round(float(pl), 3)},
+        # the candidate rows stream from HBM once per step: 8.3 FLOP/B, under
+        # the FP64 ridge (78.6 TF/s / 8 TB/s = 9.8), so HBM is the bound
+        "roofline": {"bound": "hbm", "kernel": "k_local (exhaustive, partitioned inverse)",
+                     "achieved": round(p_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(p_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_local", M),
+                     "work": f"sum_j 8 j (ncand - j), j = n0..n-1: {scoring_bytes(prm.n0, prm.n, nc):.4g} "
+                             f"B/location x {M} locations per launch",
+                     "mfma": {"achieved": round(p_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(p_tf / FP64_PEAK_TFLOPS, 4),
+                              "work": f"sum_j 2 j^2 (ncand - j): {scoring_flops(prm.n0, prm.n, nc):.4g} "
+                                      f"FLOP/location"}},
+        "identical_designs_vs_cholesky": float(np.mean(same)),
+        "mean_relerr_max_vs_cholesky": float(np.max(np.abs(pi_mean[same] - ex_mean[same]) /
+                                                    np.maximum(np.abs(ex_mean[same]), 1e-12), initial=0.0)),
+    }
 
     if not args.no_ray:
         Pr = lg.make_params(prm, search=W.SEARCH_RAY, numrays=10)
@@ -297,7 +355,7 @@ def main() -> int:
     if args.grid:
         result["grid"] = grid(args.grid_M)
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(w, prm)
+        result["cpu_baseline"] = cpu_baseline(w, prm.replace(scoring=W.SCORING_CHOL))
     print(json.dumps(result), flush=True)
     return 0
 

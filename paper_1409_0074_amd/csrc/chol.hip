@@ -36,18 +36,24 @@ namespace {
 
 constexpr int CH_CHUNK = 8;  // u entries per statically indexed block
 
-// NU: u entries kept per candidate (designs up to NU + 1 points); PM:
-// coordinate rows (p <= PM, rows p .. PM-1 zero); CS: candidate slots, the
-// LDS row stride (N' <= CS), two per thread.
-template <int NU, int PM, int CS>
+typedef double v8d __attribute__((ext_vector_type(8)));
+
+// NB: blocks of CH_CHUNK u entries kept per candidate.  The entry a step
+// appends is read by later steps only, so designs of up to 8 NB + 2 points
+// fit.  PM: coordinate rows (p <= PM, rows p .. PM-1 zero); CS: candidate
+// slots, the LDS row stride (N' <= CS), two per thread.
+template <int NB, int PM, int CS>
 struct ChCfg {
-  // the first UL entries of every u_c live in LDS (ul[k * CS + c]), the rest
-  // in registers
-  static constexpr int UL = NU > 32 ? CH_CHUNK : 0;
-  static constexpr int NUP = (NU + CH_CHUNK - 1) / CH_CHUNK * CH_CHUNK;
-  static constexpr int SS = NUP + 4;  // slot: u (zero padded), v, cov, q, pad
-  static constexpr int NCH = NU / CH_CHUNK + 1;  // step blocks: j = 0 .. NU
-  static constexpr int NT = CS / 2;              // largest workgroup
+  // the first BL blocks of every u_c live in LDS (ul[k * CS + c]), the other
+  // NR in registers, one 8-vector each (an entry is appended at a run-time
+  // position with one indexed register move)
+  static constexpr int BL = NB > 4 ? 1 : 0;
+  static constexpr int UL = BL * CH_CHUNK;
+  static constexpr int NR = NB - BL;
+  static constexpr int NUP = NB * CH_CHUNK;
+  static constexpr int SS = NUP + 4;  // slot: u, then v, 1/sqrt(v), cov/sqrt(v), q/sqrt(v)
+  static constexpr int NCH = NB + 1;  // step blocks: j = 0 .. 8 NB + 1
+  static constexpr int NT = CS / 2;   // largest workgroup
   static constexpr int NWV = NT / 64;
 };
 
@@ -72,9 +78,9 @@ __host__ __device__ constexpr size_t ch_lds_bytes(int PM, int CS, int UL, int SS
          sizeof(int) * (2 * (size_t)(CS / 128) + (size_t)n);
 }
 
-template <int NU, int PM, int CS>
+template <int NB, int PM, int CS>
 __device__ inline ChLds ch_carve(unsigned char* s) {
-  using C = ChCfg<NU, PM, CS>;
+  using C = ChCfg<NB, PM, CS>;
   ChLds L;
   L.xs = reinterpret_cast<double*>(s);
   L.ul = L.xs + PM * CS;
@@ -117,11 +123,44 @@ __device__ __forceinline__ double ch_wave_max(double v) {
   return ch_readlane(v, 63);
 }
 
-// Per-thread state of the candidate pair (2t, 2t+1); u entries below UL are
-// in LDS.
-template <int NU>
+// Wave maximum of a 32-bit unsigned key (every lane): the same DPP pattern
+// with the moves fused into the maximum (0 is the identity).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t ch_dpp_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t ch_wave_max_u(uint32_t v) {
+  v = max(v, ch_dpp_u<0xB1, 0xF>(v));
+  v = max(v, ch_dpp_u<0x4E, 0xF>(v));
+  v = max(v, ch_dpp_u<0x141, 0xF>(v));
+  v = max(v, ch_dpp_u<0x140, 0xF>(v));
+  v = max(v, ch_dpp_u<0x142, 0xA>(v));
+  v = max(v, ch_dpp_u<0x143, 0xC>(v));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Lanes holding the largest criterion of the wave.  A criterion is >= 0
+// (or -1: nothing to offer); for non-negative doubles the bit patterns order
+// like the values, so the maximum is found on the high words, then on the
+// low words of the lanes that tie there: two 32-bit reductions instead of a
+// 64-bit one.  Returns the ballot of the lanes equal to the maximum (0 if
+// no lane offers anything).
+__device__ __forceinline__ uint64_t ch_wave_argmax(double sc) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, sc);
+  const bool ok = sc >= 0.0;
+  const uint32_t hi = ok ? (uint32_t)(b >> 32) | 0x80000000u : 0u;
+  const uint32_t lo = (uint32_t)b;
+  const uint32_t mhi = ch_wave_max_u(hi);
+  const uint32_t mlo = ch_wave_max_u(hi == mhi ? lo : 0u);
+  return __ballot(ok && hi == mhi && lo == mlo);
+}
+
+// Per-thread state of the candidate pair (2t, 2t+1); u blocks below BL are
+// in LDS, block BL + i in r0[i] / r1[i].
+template <int NR>
 struct ChPair {
-  double u0[NU], u1[NU];
+  v8d r0[NR > 0 ? NR : 1], r1[NR > 0 ? NR : 1];
   double v[2], cov[2], q[2];
   bool act[2];
   int vflag;
@@ -163,22 +202,35 @@ __device__ __forceinline__ void ch_corr2(const double* xs, int CS, int w, int c0
   k1 = gexp_with(-s1, coef);
 }
 
-// Publish candidate 2t + which: its u (zero padded to the block), v, cov, q.
-template <int NU, int PM, int CS, int B>
-__device__ __forceinline__ void ch_write_slot(double* sl, const ChPair<NU>& S, int which, const ChLds& L) {
-  using C = ChCfg<NU, PM, CS>;
-  constexpr int KE = (B + 1) * CH_CHUNK < NU ? (B + 1) * CH_CHUNK : NU;
-  const int c = 2 * threadIdx.x + which;
-  if (which == 0) {
+// u entries in use during step block B (whole blocks; entries not yet
+// appended are zero)
+template <int NB, int B>
+constexpr int ch_ke() { return (B + 1 < NB ? B + 1 : NB) * CH_CHUNK; }
+
+// Publish candidate 2t + W: its u (whole blocks), v, cov, q.  (W is a
+// template argument: a run-time choice between the two register sets would
+// turn them into memory.)
+template <int NB, int PM, int CS, int B, int W>
+__device__ __forceinline__ void ch_write_slot(double* sl, const ChPair<ChCfg<NB, PM, CS>::NR>& S, const ChLds& L) {
+  using C = ChCfg<NB, PM, CS>;
+  constexpr int KE = ch_ke<NB, B>();
+  const int c = 2 * threadIdx.x + W;
 #pragma unroll
-    for (int k = 0; k < KE; ++k) sl[k] = k < C::UL ? L.ul[k * CS + c] : S.u0[k];
-  } else {
-#pragma unroll
-    for (int k = 0; k < KE; ++k) sl[k] = k < C::UL ? L.ul[k * CS + c] : S.u1[k];
+  for (int k = 0; k < KE; ++k) {
+    if (k < C::UL) {
+      sl[k] = L.ul[k * CS + c];
+    } else {
+      const int b = k / CH_CHUNK - C::BL < 0 ? 0 : k / CH_CHUNK - C::BL;
+      sl[k] = W == 0 ? S.r0[b][k % CH_CHUNK] : S.r1[b][k % CH_CHUNK];
+    }
   }
-  sl[C::NUP] = which ? S.v[1] : S.v[0];  // (no run-time index into the state: it must stay in registers)
-  sl[C::NUP + 1] = which ? S.cov[1] : S.cov[0];
-  sl[C::NUP + 2] = which ? S.q[1] : S.q[0];
+  // the quantities every candidate needs from the winner, computed here by
+  // the candidate's own lane, before the barrier
+  const double v = S.v[W], li = 1.0 / __builtin_sqrt(v);
+  sl[C::NUP] = v;
+  sl[C::NUP + 1] = li;
+  sl[C::NUP + 2] = S.cov[W] * li;
+  sl[C::NUP + 3] = S.q[W] * li;
 }
 
 __device__ __forceinline__ double ch_score(const double v, const double cov, bool act, int& vflag) {
@@ -196,11 +248,12 @@ __device__ __forceinline__ double ch_score(const double v, const double cov, boo
 // Steps j = B*CH_CHUNK .. B*CH_CHUNK + CH_CHUNK - 1: choose design point j
 // (forced to rank j while j < n0, else the largest criterion, lowest rank on
 // ties), publish its column, extend every other candidate's.
-template <int NU, int PM, int CS, bool DIAG, int B>
-__device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChPair<NU>& S, ChRun& R, int64_t m) {
-  using C = ChCfg<NU, PM, CS>;
-  constexpr int NUP = C::NUP, SS = C::SS, UL = C::UL, NWV = C::NWV;
-  constexpr int KE = (B + 1) * CH_CHUNK < NU ? (B + 1) * CH_CHUNK : NU;  // u entries in use up to this block
+template <int NB, int PM, int CS, bool DIAG, int B>
+__device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChPair<ChCfg<NB, PM, CS>::NR>& S,
+                                         ChRun& R, int64_t m) {
+  using C = ChCfg<NB, PM, CS>;
+  constexpr int NUP = C::NUP, SS = C::SS, UL = C::UL, NWV = C::NWV, BL = C::BL;
+  constexpr int KE = ch_ke<NB, B>();
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nwv = blockDim.x >> 6;
   const int c0 = 2 * tid;
@@ -211,16 +264,20 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
     const int par = j & 1;
     double* sl = L.slot + par * NWV * SS;
     if (j < n0) {
-      if ((j >> 1) == tid) ch_write_slot<NU, PM, CS, B>(sl + wv * SS, S, j & 1, L);
+      if ((j >> 1) == tid) {
+        if ((j & 1) == 0) ch_write_slot<NB, PM, CS, B, 0>(sl + wv * SS, S, L);
+        if ((j & 1) == 1) ch_write_slot<NB, PM, CS, B, 1>(sl + wv * SS, S, L);
+      }
     } else {
       const double s0 = ch_score(S.v[0], S.cov[0], S.act[0], S.vflag);
       const double s1 = ch_score(S.v[1], S.cov[1], S.act[1], S.vflag);
       const int pick = s1 > s0 ? 1 : 0;  // the lower rank on ties
       const double pb = pick ? s1 : s0;
-      const double wmax = ch_wave_max(pb);
-      const uint64_t hit = __ballot(pb == wmax && wmax >= 0.0);
+      const uint64_t hit = ch_wave_argmax(pb);
       const int wl = hit ? __builtin_ctzll(hit) : -1;
-      if (lane == wl) ch_write_slot<NU, PM, CS, B>(sl + wv * SS, S, pick, L);
+      const double wmax = wl >= 0 ? ch_readlane(pb, wl) : -1.0;
+      if (lane == wl && pick == 0) ch_write_slot<NB, PM, CS, B, 0>(sl + wv * SS, S, L);
+      if (lane == wl && pick == 1) ch_write_slot<NB, PM, CS, B, 1>(sl + wv * SS, S, L);
       if (lane == (wl >= 0 ? wl : 0)) {
         L.redv[par * NWV + wv] = wl >= 0 ? wmax : -1.0;
         L.redi[par * NWV + wv] = wl >= 0 ? c0 + pick : -1;
@@ -242,28 +299,24 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
         cv = ci >= 0 ? L.redv[par * NWV + lane] : -1.0;
         if constexpr (DIAG) c2 = L.red2[par * NWV + lane];
       }
-      const double gmax = ch_wave_max(cv);
-      const uint64_t gh = __ballot(cv == gmax && gmax >= 0.0);
+      const uint64_t gh = ch_wave_argmax(cv);
       if (!gh) {  // no finite criterion anywhere: give up on x
         R.stop = true;
         return;
       }
       const int ql = __builtin_ctzll(gh);
       w = __builtin_amdgcn_readlane(ci, ql);
-      b1 = gmax;
+      b1 = ch_readlane(cv, ql);
       if constexpr (DIAG) b2 = ch_wave_max(lane == ql ? c2 : fmax(cv, c2));
     }
     const double* ws = sl + (w >> 7) * SS;
-    const double vw = ws[NUP], covw = ws[NUP + 1], qw = ws[NUP + 2];
+    const double vw = ws[NUP], li = ws[NUP + 1], wxj = ws[NUP + 2], zj = ws[NUP + 3];
     if (j < n0 && !(vw > 0.0)) {  // the starting covariance is not positive definite
       R.pd = false;
       R.stop = true;
       return;
     }
     if (!(vw > 0.0)) S.vflag = 1;
-    const double l = __builtin_sqrt(vw);
-    const double li = 1.0 / l;
-    const double wxj = covw * li, zj = qw * li;
     if (tid == 0) {
       L.J[j] = w;
       R.mu = __builtin_fma(wxj, zj, R.mu);
@@ -291,22 +344,17 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
           d0 = __builtin_fma(wk, uu.x, d0);
           d1 = __builtin_fma(wk, uu.y, d1);
         } else {
-          d0 = __builtin_fma(wk, S.u0[k], d0);
-          d1 = __builtin_fma(wk, S.u1[k], d1);
+          d0 = __builtin_fma(wk, S.r0[k / CH_CHUNK - BL < 0 ? 0 : k / CH_CHUNK - BL][k % CH_CHUNK], d0);
+          d1 = __builtin_fma(wk, S.r1[k / CH_CHUNK - BL < 0 ? 0 : k / CH_CHUNK - BL][k % CH_CHUNK], d1);
         }
       }
       const double e0 = (kv0 - d0) * li, e1 = (kv1 - d1) * li;
-#pragma unroll
-      for (int kk = 0; kk < CH_CHUNK; ++kk) {
-        constexpr int K0 = B * CH_CHUNK;
-        if (K0 + kk < NU && kk == jj) {
-          if (K0 + kk < UL) {
-            *reinterpret_cast<double2*>(L.ul + (K0 + kk) * CS + c0) = make_double2(e0, e1);
-          } else {
-            S.u0[K0 + kk < NU ? K0 + kk : 0] = e0;
-            S.u1[K0 + kk < NU ? K0 + kk : 0] = e1;
-          }
-        }
+      // append u[j] (the entry of the last update, j = 8 NB, is never read)
+      if constexpr (B < BL) {
+        *reinterpret_cast<double2*>(L.ul + j * CS + c0) = make_double2(e0, e1);
+      } else if constexpr (B < NB) {
+        S.r0[B - BL][jj] = e0;
+        S.r1[B - BL][jj] = e1;
       }
       S.v[0] = __builtin_fma(-e0, e0, S.v[0]);
       S.v[1] = __builtin_fma(-e1, e1, S.v[1]);
@@ -318,21 +366,22 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
   }
 }
 
-template <int NU, int PM, int CS, bool DIAG, int B>
-__device__ __forceinline__ void ch_blocks(const LocalArgs& a, const ChLds& L, ChPair<NU>& S, ChRun& R, int64_t m) {
-  if constexpr (B < ChCfg<NU, PM, CS>::NCH) {
-    ch_block<NU, PM, CS, DIAG, B>(a, L, S, R, m);
-    if (!R.stop && (B + 1) * CH_CHUNK < a.n) ch_blocks<NU, PM, CS, DIAG, B + 1>(a, L, S, R, m);
+template <int NB, int PM, int CS, bool DIAG, int B>
+__device__ __forceinline__ void ch_blocks(const LocalArgs& a, const ChLds& L, ChPair<ChCfg<NB, PM, CS>::NR>& S,
+                                          ChRun& R, int64_t m) {
+  if constexpr (B < ChCfg<NB, PM, CS>::NCH) {
+    ch_block<NB, PM, CS, DIAG, B>(a, L, S, R, m);
+    if (!R.stop && (B + 1) * CH_CHUNK < a.n) ch_blocks<NB, PM, CS, DIAG, B + 1>(a, L, S, R, m);
   }
 }
 
 // One workgroup of 64 ceil(N'/128) threads per location; thread t holds the
 // candidates of ranks 2t and 2t+1.
-template <int NU, int PM, int CS, bool DIAG>
+template <int NB, int PM, int CS, bool DIAG>
 __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) void k_chol(LocalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  using Cf = ChCfg<NU, PM, CS>;
-  const ChLds L = ch_carve<NU, PM, CS>(smem);
+  using Cf = ChCfg<NB, PM, CS>;
+  const ChLds L = ch_carve<NB, PM, CS>(smem);
   const int tid = threadIdx.x;
   const int64_t m = blockIdx.x;
   const int p = a.p, n = a.n, nc = a.ncand;
@@ -341,11 +390,11 @@ __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) voi
 
   if (tid < LAGP_MAX_DIM) L.x[tid] = tid < p ? a.XX[m * p + tid] : 0.0;
   if (tid < 12) L.ec[tid] = gexp_coef(tid);
-  ChPair<NU> S;
+  ChPair<Cf::NR> S;
 #pragma unroll
-  for (int k = 0; k < NU; ++k) {
-    S.u0[k] = 0.0;
-    S.u1[k] = 0.0;
+  for (int b = 0; b < (Cf::NR > 0 ? Cf::NR : 1); ++b) {
+    S.r0[b] = v8d{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    S.r1[b] = S.r0[b];
   }
 #pragma unroll
   for (int k = 0; k < Cf::UL; ++k) *reinterpret_cast<double2*>(L.ul + k * CS + c0) = make_double2(0.0, 0.0);
@@ -394,7 +443,7 @@ __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
 
   ChRun R{0.0, 0.0, 0.0, 0, true, false};
-  ch_blocks<NU, PM, CS, DIAG, 0>(a, L, S, R, m);
+  ch_blocks<NB, PM, CS, DIAG, 0>(a, L, S, R, m);
 
   const int vf = __syncthreads_or(S.vflag);
   const bool ok = R.pd && R.done == n;
@@ -419,70 +468,71 @@ __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
 }
 
-constexpr int CH_NU_SMALL = 31;  // n <= 32
-constexpr int CH_NU_LARGE = 49;  // n <= 50
+constexpr int CH_NB_SMALL = 4;  // n <= 34
+constexpr int CH_NB_LARGE = 6;  // n <= 50
+constexpr int CH_N_MAX = 8 * CH_NB_LARGE + 2;
 
-template <int NU, int PM, int CS>
+template <int NB, int PM, int CS>
 constexpr size_t ch_bytes(int n) {
-  using C = ChCfg<NU, PM, CS>;
+  using C = ChCfg<NB, PM, CS>;
   return ch_lds_bytes(PM, CS, C::UL, C::SS, n);
 }
 
 struct ChPick {
-  int nu, pm, cs;
+  int nb, pm, cs;
   size_t lds;
 };
 
 ChPick ch_pick(int n, int ncand, int p) {
   ChPick k;
-  k.nu = n <= CH_NU_SMALL + 1 ? CH_NU_SMALL : CH_NU_LARGE;
+  k.nb = n <= 8 * CH_NB_SMALL + 2 ? CH_NB_SMALL : CH_NB_LARGE;
   k.pm = p <= 8 ? 8 : LAGP_MAX_DIM;
   k.cs = ncand <= 512 ? 512 : 1024;
-  const bool small = k.nu == CH_NU_SMALL, p8 = k.pm == 8, c5 = k.cs == 512;
+  const bool small = k.nb == CH_NB_SMALL, p8 = k.pm == 8, c5 = k.cs == 512;
   if (small)
-    k.lds = p8 ? (c5 ? ch_bytes<CH_NU_SMALL, 8, 512>(n) : ch_bytes<CH_NU_SMALL, 8, 1024>(n))
-               : (c5 ? ch_bytes<CH_NU_SMALL, LAGP_MAX_DIM, 512>(n) : ch_bytes<CH_NU_SMALL, LAGP_MAX_DIM, 1024>(n));
+    k.lds = p8 ? (c5 ? ch_bytes<CH_NB_SMALL, 8, 512>(n) : ch_bytes<CH_NB_SMALL, 8, 1024>(n))
+               : (c5 ? ch_bytes<CH_NB_SMALL, LAGP_MAX_DIM, 512>(n) : ch_bytes<CH_NB_SMALL, LAGP_MAX_DIM, 1024>(n));
   else
-    k.lds = p8 ? (c5 ? ch_bytes<CH_NU_LARGE, 8, 512>(n) : ch_bytes<CH_NU_LARGE, 8, 1024>(n))
-               : (c5 ? ch_bytes<CH_NU_LARGE, LAGP_MAX_DIM, 512>(n) : ch_bytes<CH_NU_LARGE, LAGP_MAX_DIM, 1024>(n));
+    k.lds = p8 ? (c5 ? ch_bytes<CH_NB_LARGE, 8, 512>(n) : ch_bytes<CH_NB_LARGE, 8, 1024>(n))
+               : (c5 ? ch_bytes<CH_NB_LARGE, LAGP_MAX_DIM, 512>(n) : ch_bytes<CH_NB_LARGE, LAGP_MAX_DIM, 1024>(n));
   return k;
 }
 
-template <int NU, int PM, int CS, bool DIAG>
+template <int NB, int PM, int CS, bool DIAG>
 hipError_t launch_chol_t(const LocalArgs& a, size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol<NU, PM, CS, DIAG>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol<NB, PM, CS, DIAG>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int T = (a.ncand + 127) / 128 * 64;
-  hipLaunchKernelGGL((k_chol<NU, PM, CS, DIAG>), dim3(a.M), dim3(T), lds, s, a);
+  hipLaunchKernelGGL((k_chol<NB, PM, CS, DIAG>), dim3(a.M), dim3(T), lds, s, a);
   return hipGetLastError();
 }
 
-template <int NU, int PM, int CS>
+template <int NB, int PM, int CS>
 hipError_t launch_chol_d(const LocalArgs& a, size_t lds, hipStream_t s) {
-  return a.diag ? launch_chol_t<NU, PM, CS, true>(a, lds, s) : launch_chol_t<NU, PM, CS, false>(a, lds, s);
+  return a.diag ? launch_chol_t<NB, PM, CS, true>(a, lds, s) : launch_chol_t<NB, PM, CS, false>(a, lds, s);
 }
 
-template <int NU, int PM>
+template <int NB, int PM>
 hipError_t launch_chol_cs(const LocalArgs& a, int cs, size_t lds, hipStream_t s) {
-  return cs == 512 ? launch_chol_d<NU, PM, 512>(a, lds, s) : launch_chol_d<NU, PM, 1024>(a, lds, s);
+  return cs == 512 ? launch_chol_d<NB, PM, 512>(a, lds, s) : launch_chol_d<NB, PM, 1024>(a, lds, s);
 }
 
-template <int NU>
+template <int NB>
 hipError_t launch_chol_pm(const LocalArgs& a, const ChPick& k, hipStream_t s) {
-  return k.pm == 8 ? launch_chol_cs<NU, 8>(a, k.cs, k.lds, s) : launch_chol_cs<NU, LAGP_MAX_DIM>(a, k.cs, k.lds, s);
+  return k.pm == 8 ? launch_chol_cs<NB, 8>(a, k.cs, k.lds, s) : launch_chol_cs<NB, LAGP_MAX_DIM>(a, k.cs, k.lds, s);
 }
 
 }  // namespace
 
 bool chol_supported(int n, int ncand, int p, size_t lds_max) {
-  return n <= CH_NU_LARGE + 1 && ncand <= 1024 && p <= LAGP_MAX_DIM && ch_pick(n, ncand, p).lds <= lds_max;
+  return n <= CH_N_MAX && ncand <= 1024 && p <= LAGP_MAX_DIM && ch_pick(n, ncand, p).lds <= lds_max;
 }
 
 hipError_t launch_chol(const LocalArgs& a, hipStream_t s) {
   if (a.M <= 0) return hipSuccess;
   const ChPick k = ch_pick(a.n, a.ncand, a.p);
-  return k.nu == CH_NU_SMALL ? launch_chol_pm<CH_NU_SMALL>(a, k, s) : launch_chol_pm<CH_NU_LARGE>(a, k, s);
+  return k.nb == CH_NB_SMALL ? launch_chol_pm<CH_NB_SMALL>(a, k, s) : launch_chol_pm<CH_NB_LARGE>(a, k, s);
 }
 
 }  // namespace lagp

@@ -48,25 +48,44 @@ __host__ __device__ constexpr double gexp_coef(int i) {
 // same values from LDS instead of holding them as constants.
 template <class Coef>
 __device__ __forceinline__ double gexp_with(double x, const Coef& coef) {
-  if (x != x) return x;
-  if (x < -708.0) return 0.0;
-  if (x > 709.0) return __builtin_huge_val();
+  // straight-line: the out-of-range cases are selected at the end (no
+  // divergent branches around the polynomial)
+  const double xc = x < -708.0 ? -708.0 : (x > 709.0 ? 709.0 : (x == x ? x : 0.0));
   const double L2H = 0x1.62e42fefa39efp-1;   // double nearest ln 2
   const double L2L = 0x1.abc9e3b39803fp-56;  // ln 2 - L2H
   const double IL2 = 0x1.71547652b82fep+0;   // double nearest 1/ln 2
-  const double k = __builtin_rint(x * IL2);
-  double r = __builtin_fma(-k, L2H, x);
+  const double k = __builtin_rint(xc * IL2);
+  double r = __builtin_fma(-k, L2H, xc);
   r = __builtin_fma(-k, L2L, r);
   double t = coef(0);
 #pragma unroll
   for (int i = 1; i < 12; ++i) t = __builtin_fma(t, r, coef(i));
   t = __builtin_fma(t, r, 1.0);
   t = __builtin_fma(t, r, 1.0);
-  return __builtin_ldexp(t, (int)k);
+  const double e = __builtin_ldexp(t, (int)k);
+  if (x != x) return x;
+  return x < -708.0 ? 0.0 : (x > 709.0 ? __builtin_huge_val() : e);
 }
 
+// The same function with the out-of-range cases as early returns and the
+// coefficients as constants (the form the partitioned-inverse kernels were
+// tuned with; identical values).
 __device__ __forceinline__ double gexp(double x) {
-  return gexp_with(x, [](int i) { return gexp_coef(i); });
+  if (x != x) return x;
+  if (x < -708.0) return 0.0;
+  if (x > 709.0) return __builtin_huge_val();
+  const double L2H = 0x1.62e42fefa39efp-1;
+  const double L2L = 0x1.abc9e3b39803fp-56;
+  const double IL2 = 0x1.71547652b82fep+0;
+  const double k = __builtin_rint(x * IL2);
+  double r = __builtin_fma(-k, L2H, x);
+  r = __builtin_fma(-k, L2L, r);
+  double t = gexp_coef(0);
+#pragma unroll
+  for (int i = 1; i < 12; ++i) t = __builtin_fma(t, r, gexp_coef(i));
+  t = __builtin_fma(t, r, 1.0);
+  t = __builtin_fma(t, r, 1.0);
+  return __builtin_ldexp(t, (int)k);
 }
 
 // Squared Euclidean distance with one fma per dimension, in order.

@@ -1,20 +1,17 @@
 """GPU-vs-oracle comparison helpers (test infrastructure).
 
-Replay protocol: the oracle follows the GPU's selection sequence step by step
-and records its own choice, the two best criterion values and the value of
-the GPU's pick.  A step where the oracle's relative top-two gap exceeds
-GAP_TOL must have the same pick; a closer step is exempt but the GPU's pick
-must still score within GAP_TOL of the best.  Mean and scale are then the
-oracle's on the GPU's design.
+The oracle always runs on its own inputs (it never receives a GPU result).
+The FP64 forms of the library sum in the oracle's defined order, so their
+designs and predictions are compared for bit equality; the mixed form is
+compared run against run, and where its design departs from the FP64 one the
+oracle's criterion value of the GPU's pick at that step is looked up in the
+oracle's own trace of the location.
 """
 from __future__ import annotations
 
 import numpy as np
 
 import oracle
-
-GAP_TOL = 1e-9        # selection must match where the top-two gap exceeds this (relative)
-VALUE_RTOL = 1e-8     # mean and scale, FP64 form
 
 
 def run_gpu(w, params, XX=None, sel=True, diag=True):
@@ -31,36 +28,38 @@ def run_gpu(w, params, XX=None, sel=True, diag=True):
         d.close()
 
 
-def rel_err(a, b, floor):
-    return np.abs(a - b) / np.maximum(np.abs(b), floor)
-
-
-def check_replay(w, params, g, XX=None, rtol=VALUE_RTOL, bit_exact_values=False):
-    """Replay the GPU's selections in the oracle; returns a stats dict and
-    asserts the protocol."""
+def check_exact(w, params, g, XX=None, diag=True):
+    """The GPU's run against the oracle's independent run of the same
+    locations (the oracle never sees a GPU result): designs, means, scales
+    and status words equal bit for bit, and the per-step best and runner-up
+    criterion values too when the GPU reported them."""
     XX = w.XX if XX is None else XX
-    o = oracle.predict(w.X, w.y, XX, params, forced=g["sel"])
-    assert np.all(o["status"] < 0x100), "oracle could not replay the GPU sequence"
-    n0 = params.n0
-    dg = o["diag"]                      # M x steps x NDIAG
-    gpu_pick = g["sel"][:, n0:].astype(float)
-    own = dg[:, :, 0]
-    alc1, alc2, alc_take = dg[:, :, 1], dg[:, :, 2], dg[:, :, 3]
-    gap = dg[:, :, 4]
-    decisive = gap > GAP_TOL
-    mism = decisive & (own != gpu_pick)
-    assert not mism.any(), f"{mism.sum()} decisive steps differ; first at {np.argwhere(mism)[0]}"
-    exempt = ~decisive
-    if exempt.any():
-        ok = alc_take[exempt] >= alc1[exempt] * (1.0 - GAP_TOL)
-        assert ok.all(), "an exempt step took a clearly worse candidate"
-    floor_mu = 1e-6 * np.sqrt(np.mean(w.y ** 2))
-    e_mu = rel_err(g["mean"], o["mean"], floor_mu)
-    e_s2 = rel_err(g["s2"], o["s2"], 1e-300)
-    assert np.all(e_mu <= rtol), f"mean rel err {e_mu.max()}"
-    assert np.all(e_s2 <= rtol), f"s2 rel err {e_s2.max()}"
-    if bit_exact_values:
-        assert np.array_equal(g["mean"], o["mean"]) and np.array_equal(g["s2"], o["s2"])
-    return dict(steps=int(gap.size), exempt=int(exempt.sum()), max_err_mu=float(e_mu.max()),
-                max_err_s2=float(e_s2.max()), min_gap=float(gap.min()))
+    o = oracle.predict(w.X, w.y, XX, params)
+    assert np.array_equal(g["sel"], o["sel"]), f"designs differ at {np.argwhere(g['sel'] != o['sel'])[:3]}"
+    assert np.array_equal(g["mean"], o["mean"], equal_nan=True)
+    assert np.array_equal(g["s2"], o["s2"], equal_nan=True)
+    assert np.array_equal(g["status"], o["status"])
+    if diag and g.get("diag") is not None and params.search != 2 and params.n > params.n0:
+        assert np.array_equal(g["diag"][:, :, 0], o["diag"][:, :, 1])
+        assert np.array_equal(g["diag"][:, :, 1], o["diag"][:, :, 2])
+    return o
 
+
+def first_divergence(g_sel, o_sel):
+    """Per location, the first design position where two selection
+    sequences differ (-1 where they agree throughout)."""
+    out = np.full(g_sel.shape[0], -1)
+    for m in range(g_sel.shape[0]):
+        d = np.nonzero(g_sel[m] != o_sel[m])[0]
+        if d.size:
+            out[m] = d[0]
+    return out
+
+
+def oracle_pick_value(w, params, m, step, row, XX=None):
+    """The oracle's criterion value of design row `row` at greedy step
+    `step` of its own run at location m (from its full trace)."""
+    XX = w.XX if XX is None else XX
+    tr = oracle.trace(w.X, w.y, XX[m], params)
+    q = int(np.nonzero(tr["cand"] == row)[0][0])
+    return tr["alc"][step - params.n0][q], tr["diag"][step - params.n0]

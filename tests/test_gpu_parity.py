@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from paper_1409_0074_amd import workloads as W
-from tests.parity import check_replay, run_gpu
+from tests.parity import check_exact, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -95,16 +95,11 @@ def test_candidates_edge_sizes(lg):
 
 # ------------------------------------------------------- local designs ---
 
-def test_exhaustive_uniform2d_replay(lg):
+def test_exhaustive_uniform2d(lg):
     w = W.tiny_2d()
     g = run_gpu(w, w.params)
     assert np.all(g["status"] == 0)
-    st = check_replay(w, w.params, g, bit_exact_values=True)
-    print("uniform2d exhaustive:", st)
-    free = oracle.predict(w.X, w.y, w.XX, w.params)
-    match = np.mean(np.all(free["sel"] == g["sel"], axis=1))
-    print("free-run identical sequences:", match)
-    assert st["exempt"] <= 0.01 * st["steps"]
+    check_exact(w, w.params, g)
 
 
 @pytest.mark.parametrize("case", ["uniform2d", "uniform8d", "grid"])
@@ -131,14 +126,13 @@ def test_exhaustive_free_run_bit_exact(lg, case):
 
 
 @pytest.mark.parametrize("sep", [True, False])
-def test_exhaustive_uniform8d_replay(lg, sep):
+def test_exhaustive_uniform8d(lg, sep):
     rng = np.random.default_rng(103)
     X = rng.random((60000, 8))
     w = W.Workload("u8", X, W.f_sines8(X), rng.random((20, 8)),
                    W.Params(n0=6, n=50, ncand=1000, d=(0.5,) * 8 if sep else (0.5,), g=1e-6))
     g = run_gpu(w, w.params)
-    st = check_replay(w, w.params, g, bit_exact_values=True)
-    print("uniform8d exhaustive:", st)
+    check_exact(w, w.params, g)
 
 
 @pytest.mark.parametrize("n,ncand,g_nug", [(64, 200, 1e-6), (100, 900, 1e-6), (70, 333, 1e-3)])
@@ -148,8 +142,7 @@ def test_exhaustive_large_n(lg, n, ncand, g_nug):
     X = rng.random((20000, 2))
     w = W.Workload("u2", X, W.f_bump2(X), rng.random((6, 2)), W.Params(n0=6, n=n, ncand=ncand, d=(0.05,), g=g_nug))
     g = run_gpu(w, w.params)
-    st = check_replay(w, w.params, g)
-    print(f"n={n} ncand={ncand}:", st)
+    check_exact(w, w.params, g)
 
 
 def test_exhaustive_grid_design(lg):
@@ -158,8 +151,7 @@ def test_exhaustive_grid_design(lg):
     rng = np.random.default_rng(105)
     w = W.Workload("grid", X, W.f_bump2(X), rng.random((8, 2)), W.Params(n0=6, n=60, ncand=800, d=(0.05,), g=1e-6))
     g = run_gpu(w, w.params)
-    st = check_replay(w, w.params, g)
-    print("grid:", st)
+    check_exact(w, w.params, g)
 
 
 @pytest.mark.parametrize("R", [2, 10])
@@ -195,7 +187,7 @@ def test_nn_mode_bit_exact(lg):
 def test_ragged_location_counts(lg, M):
     w = W.tiny_2d(M=M)
     g = run_gpu(w, w.params)
-    check_replay(w, w.params, g, bit_exact_values=True)
+    check_exact(w, w.params, g)
 
 
 def test_no_greedy_steps(lg):
