@@ -21,6 +21,9 @@ STATUS_VNONPOS = 1
 STATUS_NONFINITE = 2
 STATUS_NOTPD = 4
 STATUS_BADRAY = 8
+STATUS_MLE_BOUND = 16
+STATUS_MLE_NOTPD = 32
+STATUS_MLE_MAXIT = 64
 
 _lib = None
 
@@ -72,6 +75,16 @@ def lib():
         L.orc_sqdist.restype = ctypes.c_double
         L.orc_spd_inverse.argtypes = [_dp, ctypes.c_int, _dp]
         L.orc_spd_inverse.restype = ctypes.c_int
+        i32 = ctypes.c_int
+        L.orc_predict_mle.argtypes = common + [_dp, ctypes.c_int64, i32, i32, i32, ctypes.c_double, ctypes.c_double,
+                                               i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32, i32,
+                                               _dp, _dp, _dp, _i32p, _dp, _i32p, _i32p]
+        L.orc_predict_mle.restype = ctypes.c_int
+        L.orc_mle_eval.argtypes = [i32, i32, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.orc_mle_eval.restype = ctypes.c_int
+        L.orc_mle_fit.argtypes = [i32, i32, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.orc_mle_fit.restype = ctypes.c_double
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
@@ -152,6 +165,46 @@ def trace(X, y, x, params, forced=None):
         raise ValueError(f"orc_trace failed: {st}")
     out.update(mean=mean.value, s2=s2.value, df=df.value, status=st)
     return out
+
+
+def predict_mle(X, y, XX, params, mode: int, dmin: float = 0.0, dmax: float = 0.0, tol: float = 0.0,
+                maxit: int = 0, nthreads: int | None = None):
+    """Local MLE of an isotropic lengthscale (mode 1: on the design searched
+    under params.d; mode 2: two-stage re-design) and the prediction under the
+    estimate, at every row of XX (exhaustive search, params.scoring)."""
+    X, y, XX = _f64(X), _f64(y), _f64(np.atleast_2d(XX))
+    N, p = X.shape
+    M = XX.shape[0]
+    n = params.n
+    d0 = float(np.atleast_1d(params.d)[0])
+    out = dict(mean=np.empty(M), s2=np.empty(M), df=np.empty(M), sel=np.empty((M, n), np.int32),
+               dhat=np.empty(M), iters=np.empty(M, np.int32), status=np.empty(M, np.int32))
+    rc = lib().orc_predict_mle(_p(X), _p(y), N, p, _p(XX), M, params.n0, n, params.ncand, d0, params.g,
+                               getattr(params, "scoring", 0), mode, dmin, dmax, tol, maxit,
+                               nthreads or default_threads(), _p(out["mean"]), _p(out["s2"]), _p(out["df"]),
+                               _p(out["sel"], _i32p), _p(out["dhat"]), _p(out["iters"], _i32p),
+                               _p(out["status"], _i32p))
+    if rc != 0:
+        raise ValueError(f"orc_predict_mle failed: {rc}")
+    return out
+
+
+def mle_eval(XJ, yJ, g: float, theta: float):
+    """(l, l', l'') of the local likelihood at theta, or None if K is not
+    positive definite."""
+    XJ, yJ = _f64(XJ), _f64(yJ)
+    out = np.empty(3)
+    rc = lib().orc_mle_eval(XJ.shape[0], XJ.shape[1], _p(XJ), _p(yJ), g, theta, _p(out))
+    return None if rc != 0 else tuple(out)
+
+
+def mle_fit(XJ, yJ, g: float, theta0: float, dmin: float, dmax: float, tol: float = 1e-8, maxit: int = 100):
+    """(theta_hat, evaluations, flags) of the safeguarded Newton maximisation."""
+    XJ, yJ = _f64(XJ), _f64(yJ)
+    it, fl = ctypes.c_int(), ctypes.c_int()
+    t = lib().orc_mle_fit(XJ.shape[0], XJ.shape[1], _p(XJ), _p(yJ), g, theta0, dmin, dmax, tol, maxit,
+                          ctypes.byref(it), ctypes.byref(fl))
+    return t, it.value, fl.value
 
 
 def brent_min(f, lo: float, hi: float, tol: float = 2.0 ** -13, maxit: int = 100):

@@ -30,6 +30,12 @@
  *                  below): the criterion and prediction of O4-O6 in another
  *                  rounding order, and the checker of the library's Cholesky
  *                  scoring form
+ *   O8 local MLE   the isotropic lengthscale maximising the local marginal
+ *                  likelihood (Eq. gpk with the n local points) by a
+ *                  safeguarded Newton iteration on its analytic derivatives,
+ *                  and the two-stage re-design: search under d0, estimate,
+ *                  search again under the estimate, estimate again, predict
+ *                  (Sec. 5)
  *
  * Rounding is defined, not left to the compiler, so that another
  * implementation can reproduce every value here bit for bit: squared
@@ -62,6 +68,9 @@
 #define ORC_STATUS_NONFINITE 2 /* non-finite prediction */
 #define ORC_STATUS_NOTPD 4     /* starting K_J not positive definite */
 #define ORC_STATUS_BADRAY 8    /* too few remaining candidates for the rays */
+#define ORC_STATUS_MLE_BOUND 16 /* the lengthscale estimate sits at a bound of its range */
+#define ORC_STATUS_MLE_NOTPD 32 /* K was not positive definite at some Newton iterate */
+#define ORC_STATUS_MLE_MAXIT 64 /* the Newton iteration ran out of iterations */
 
 /* ---------------------------------------------------------------- O1 ---- */
 
@@ -816,6 +825,235 @@ static void bbox(const double *X, int64_t N, int p, double *lo, double *hi)
         }
 }
 
+/* ---------------------------------------------------------------- O8 ---- */
+
+/*
+ * Local marginal likelihood of an isotropic lengthscale theta on a fixed
+ * local design (Eq. gpk with N -> n and the nugget g fixed):
+ *   l(theta) = -1/2 log|K| - n/2 log psi,  psi = y^T K^{-1} y,
+ *   K = E + g I,  E_ik = exp(-a_ik),  a_ik = D_ik w,  w = 1/theta,
+ * D_ik the squared distances of the design points (O1 rounding).  With
+ * Kd = dK/dtheta = E a w and Kdd = d2K/dtheta2 = E (a^2 - 2a) w^2,
+ * alpha = K^{-1} y, beta = Kd alpha:
+ *   l'  = -1/2 tr(K^{-1} Kd) + n/2 (alpha^T beta) / psi
+ *   l'' = -1/2 [tr(K^{-1} Kdd) - tr(K^{-1} Kd K^{-1} Kd)]
+ *         + n/2 [(alpha^T Kdd alpha - 2 beta^T K^{-1} beta) / psi + ((alpha^T beta) / psi)^2]
+ * (differentiating log|K| and psi).  Every sum runs in index order with one
+ * fused multiply-add per term; a trace is the in-order sum of its row sums.
+ * ws: 8 n^2 + 4 n doubles.  Returns 0, or -1 if K is not positive definite.
+ */
+static int mle_eval(int n, const double *D, const double *y, double g, double theta, double *ws, double *l,
+                    double *d1, double *d2)
+{
+    const double w = 1.0 / theta;
+    double *E = ws, *K = E + n * n, *Kd = K + n * n, *Kdd = Kd + n * n, *Ki = Kdd + n * n, *P = Ki + n * n;
+    double *work = P + n * n; /* 2 n^2: L, then L^{-1} */
+    double *al = work + 2 * n * n, *be = al + n, *ga = be + n, *de = ga + n;
+    for (int i = 0; i < n; i++)
+        for (int k = 0; k < n; k++) {
+            const double a = D[i * n + k] * w;
+            const double e = oexp(-a);
+            E[i * n + k] = e;
+            K[i * n + k] = e + (i == k ? g : 0.0);
+            Kd[i * n + k] = (e * a) * w;
+            Kdd[i * n + k] = (e * (a * a - 2.0 * a)) * (w * w);
+        }
+    if (spd_inverse(K, n, Ki, work) != 0) return -1;
+    double logdet = 0.0; /* log|K| / 2 = sum_i log L_ii */
+    for (int i = 0; i < n; i++) logdet += log(work[i * n + i]);
+    matvec(Ki, n, n, y, al);
+    const double psi = dot(y, al, n);
+    matvec(Kd, n, n, al, be);
+    const double ab = dot(al, be, n);
+    matvec(Ki, n, n, be, ga);
+    const double bgb = dot(be, ga, n);
+    matvec(Kdd, n, n, al, de);
+    const double add = dot(al, de, n);
+    for (int i = 0; i < n; i++) /* P = K^{-1} Kd */
+        for (int k = 0; k < n; k++) {
+            double t = 0.0;
+            for (int m = 0; m < n; m++) t = fma(Ki[i * n + m], Kd[m * n + k], t);
+            P[i * n + k] = t;
+        }
+    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    for (int i = 0; i < n; i++) {
+        double r1 = 0.0, r2 = 0.0, r3 = 0.0;
+        for (int k = 0; k < n; k++) {
+            r1 = fma(Ki[i * n + k], Kd[k * n + i], r1);
+            r2 = fma(Ki[i * n + k], Kdd[k * n + i], r2);
+            r3 = fma(P[i * n + k], P[k * n + i], r3);
+        }
+        t1 = t1 + r1;
+        t2 = t2 + r2;
+        t3 = t3 + r3;
+    }
+    const double hn = 0.5 * (double)n;
+    const double q = ab / psi;
+    *l = -logdet - hn * log(psi);
+    *d1 = -0.5 * t1 + hn * q;
+    *d2 = -0.5 * (t2 - t3) + hn * ((add - 2.0 * bgb) / psi + q * q);
+    return 0;
+}
+
+/*
+ * The maximiser of l on [dmin, dmax] by Newton's method on l' = 0, kept
+ * inside a bracket: lo and hi start at the bounds; every iterate theta moves
+ * lo up (l'(theta) > 0: the maximum lies above) or hi down; the Newton step
+ * theta - l'/l'' is taken when l'' < 0 and it lands strictly inside the
+ * bracket, else the geometric midpoint sqrt(lo hi); a K that is not positive
+ * definite counts as l' < 0.  Stops when a step moves theta by at most
+ * tol theta (or l' = 0), or after maxit evaluations.  The paper names the
+ * method only as Newton-like maximisation of the local posterior; reading:
+ * a flat prior on theta (the likelihood itself).
+ */
+static double mle_fit(int n, const double *D, const double *y, double g, double theta0, double dmin, double dmax,
+                      double tol, int maxit, double *ws, int *iters, int *flags)
+{
+    double lo = dmin, hi = dmax;
+    double theta = theta0 < lo ? lo : (theta0 > hi ? hi : theta0);
+    int it = 0, conv = 0;
+    *flags = 0;
+    while (it < maxit) {
+        double l, d1, d2;
+        const int bad = mle_eval(n, D, y, g, theta, ws, &l, &d1, &d2) != 0;
+        it++;
+        if (bad) {
+            *flags |= ORC_STATUS_MLE_NOTPD;
+            d1 = -1.0;
+            d2 = 0.0;
+        }
+        if (d1 == 0.0) {
+            conv = 1;
+            break;
+        }
+        if (d1 > 0.0) lo = theta;
+        else hi = theta;
+        double tn = (d2 < 0.0) ? theta - d1 / d2 : lo;
+        if (!(tn > lo && tn < hi)) tn = sqrt(lo * hi);
+        const int done = fabs(tn - theta) <= tol * theta;
+        theta = tn;
+        if (done) {
+            conv = 1;
+            break;
+        }
+    }
+    if (!conv) *flags |= ORC_STATUS_MLE_MAXIT;
+    if (theta <= dmin * (1.0 + tol) || theta >= dmax * (1.0 - tol)) *flags |= ORC_STATUS_MLE_BOUND;
+    *iters = it;
+    return theta;
+}
+
+/* Squared distances of the n design points (coordinates XJ, n x p). */
+static void design_sqdist(int n, int p, const double *XJ, double *D)
+{
+    for (int i = 0; i < n; i++)
+        for (int k = 0; k < n; k++) D[i * n + k] = sqdist(XJ + i * p, XJ + k * p, p);
+}
+
+/* The prediction of O6 at lengthscale theta on a given design, through the
+ * Cholesky factor K = L L^T (O7's form, accurate where K is ill
+ * conditioned): w = L^{-1} k_x, z = L^{-1} y by forward substitution
+ * (x_i = (b_i - sum_{m<i} L_im x_m) / L_ii, the sum in m order with fused
+ * multiply-adds), mean = w^T z, psi = z^T z, k_x^T K^{-1} k_x = w^T w. */
+static int predict_theta(int n, int p, const double *XJ, const double *yJ, const double *x, double g, double theta,
+                         double *mean, double *s2, double *ws)
+{
+    const double w = 1.0 / theta;
+    double *K = ws, *L = K + n * n, *kx = L + n * n, *wv = kx + n, *z = wv + n;
+    for (int i = 0; i < n; i++)
+        for (int k = 0; k < n; k++)
+            K[i * n + k] = kern(XJ + i * p, XJ + k * p, p, &w, 1) + (i == k ? g : 0.0);
+    memset(L, 0, sizeof(double) * n * n);
+    for (int i = 0; i < n; i++)
+        for (int k = 0; k <= i; k++) {
+            double t = K[i * n + k];
+            for (int m = 0; m < k; m++) t = fma(-L[i * n + m], L[k * n + m], t);
+            if (i == k) {
+                if (!(t > 0.0)) {
+                    *mean = NAN;
+                    *s2 = NAN;
+                    return -1;
+                }
+                L[i * n + i] = sqrt(t);
+            } else {
+                L[i * n + k] = t / L[k * n + k];
+            }
+        }
+    for (int i = 0; i < n; i++) kx[i] = kern(XJ + i * p, x, p, &w, 1);
+    for (int i = 0; i < n; i++) {
+        double a = kx[i], b = yJ[i];
+        for (int m = 0; m < i; m++) {
+            a = fma(-L[i * n + m], wv[m], a);
+            b = fma(-L[i * n + m], z[m], b);
+        }
+        wv[i] = a / L[i * n + i];
+        z[i] = b / L[i * n + i];
+    }
+    *mean = dot(wv, z, n);
+    const double psi = dot(z, z, n);
+    *s2 = psi * ((1.0 + g) - dot(wv, wv, n)) / (double)n;
+    return 0;
+}
+
+/* One location, local MLE (mode 1: estimate on the design searched under
+ * d0 and predict there; mode 2: then search again under the estimate,
+ * estimate again from it, and predict on the second design). */
+static int local_mle(const ctx_t *c, scratch_t *s, const double *x, int mode, double dmin, double dmax, double tol,
+                     int maxit, double *mean, double *s2, double *df, int32_t *sel, double *dhat, int32_t *iters)
+{
+    const int n = c->n, p = c->p;
+    int32_t *J = malloc(sizeof(int32_t) * n);
+    double *XJ = malloc(sizeof(double) * n * p), *yJ = malloc(sizeof(double) * n);
+    double *D = malloc(sizeof(double) * n * n), *ws = malloc(sizeof(double) * (8 * n * n + 8 * n));
+    int status = -2;
+    if (!J || !XJ || !yJ || !D || !ws) goto out;
+    const double d0 = 1.0 / c->d[0];
+    double theta = d0;
+    int total = 0;
+    ctx_t cs = *c;
+    double wstage;
+    for (int stage = 1; stage <= mode; stage++) {
+        if (stage == 2) {
+            wstage = 1.0 / theta;
+            cs.d = &wstage;
+        }
+        double m0, s0, f0;
+        status = local_one(&cs, s, x, NULL, &m0, &s0, &f0, J, NULL, NULL, NULL);
+        if (status < 0) goto out;
+        if (status & (ORC_STATUS_NOTPD | ORC_STATUS_NONFINITE)) {
+            *mean = NAN;
+            *s2 = NAN;
+            *df = (double)n;
+            *dhat = theta;
+            *iters = total;
+            if (sel) memcpy(sel, J, sizeof(int32_t) * n);
+            goto out;
+        }
+        for (int i = 0; i < n; i++) {
+            memcpy(XJ + i * p, c->X + (int64_t)J[i] * p, sizeof(double) * p);
+            yJ[i] = c->y[J[i]];
+        }
+        design_sqdist(n, p, XJ, D);
+        int it, flags;
+        theta = mle_fit(n, D, yJ, c->g, theta, dmin, dmax, tol, maxit, ws, &it, &flags);
+        total += it;
+        status |= flags;
+    }
+    if (predict_theta(n, p, XJ, yJ, x, c->g, theta, mean, s2, ws) != 0) status |= ORC_STATUS_NOTPD;
+    if (!isfinite(*mean) || !isfinite(*s2)) status |= ORC_STATUS_NONFINITE;
+    *df = (double)n;
+    *dhat = theta;
+    *iters = total;
+    if (sel) memcpy(sel, J, sizeof(int32_t) * n);
+out:
+    free(J);
+    free(XJ);
+    free(yJ);
+    free(D);
+    free(ws);
+    return status;
+}
+
 /* ------------------------------------------------------------ exports --- */
 
 /* Nearest candidates for M locations: idx (M x ncand row ids), d2 (M x ncand). */
@@ -905,6 +1143,82 @@ int orc_trace(const double *X, const double *y, int64_t N, int p, const double *
     if (cand) memcpy(cand, s.cand, sizeof(int64_t) * ncand);
     scratch_free(&s);
     return st;
+}
+
+/* Local MLE prediction for M locations (mode 1: one stage, 2: two stages;
+ * exhaustive search, isotropic d0 = d[0]; dmin, dmax, tol, maxit as mle_fit,
+ * <= 0 for the defaults d0/1000, 100 d0, 1e-8, 100).  Outputs mean, s2, df,
+ * dhat (the estimate used), iters (Newton evaluations), sel (M x n), status. */
+int orc_predict_mle(const double *X, const double *y, int64_t N, int p, const double *XX, int64_t M, int n0, int n,
+                    int ncand, double d0, double g, int scoring, int mode, double dmin, double dmax, double tol,
+                    int maxit, int nthreads, double *mean, double *s2, double *df, int32_t *sel, double *dhat,
+                    int32_t *iters, int32_t *status)
+{
+    if (check_args(N, p, n0, n, ncand, 0, 0, &d0, 1, g, scoring) != 0 || M < 0) return -1;
+    if (mode < 1 || mode > 2) return -1;
+    if (!(dmin > 0.0)) dmin = d0 / 1000.0;
+    if (!(dmax > 0.0)) dmax = 100.0 * d0;
+    if (!(tol > 0.0)) tol = 1e-8;
+    if (maxit <= 0) maxit = 100;
+    if (!(dmin < dmax)) return -1;
+    double lo[16], hi[16], w0 = 1.0 / d0;
+    bbox(X, N, p, lo, hi);
+    ctx_t c = {X, y, N, p, n0, n, ncand, 0, 0, &w0, 1, g, 100, ldexp(1.0, -13), lo, hi, scoring};
+    int err = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        scratch_t s;
+        int ok = scratch_alloc(&s, n, ncand) == 0;
+        if (!ok) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(dynamic)
+        for (int64_t m = 0; m < M; m++) {
+            if (!ok) continue;
+            int st = local_mle(&c, &s, XX + m * p, mode, dmin, dmax, tol, maxit, mean + m, s2 + m, df + m,
+                               sel ? sel + m * n : NULL, dhat + m, iters + m);
+            if (st < 0) {
+#pragma omp atomic write
+                err = st;
+                st = 0x100;
+            }
+            status[m] = st;
+        }
+        scratch_free(&s);
+    }
+    return err;
+}
+
+/* The local log-likelihood and its first two derivatives at theta on the
+ * design XJ (n x p), yJ (for direct checks).  Returns 0, or -1 if K is not
+ * positive definite. */
+int orc_mle_eval(int n, int p, const double *XJ, const double *yJ, double g, double theta, double *out3)
+{
+    double *D = malloc(sizeof(double) * n * n), *ws = malloc(sizeof(double) * (8 * n * n + 8 * n));
+    int rc = -2;
+    if (D && ws) {
+        design_sqdist(n, p, XJ, D);
+        rc = mle_eval(n, D, yJ, g, theta, ws, out3, out3 + 1, out3 + 2);
+    }
+    free(D);
+    free(ws);
+    return rc;
+}
+
+/* mle_fit on the design XJ, yJ. */
+double orc_mle_fit(int n, int p, const double *XJ, const double *yJ, double g, double theta0, double dmin,
+                   double dmax, double tol, int maxit, int *iters, int *flags)
+{
+    double *D = malloc(sizeof(double) * n * n), *ws = malloc(sizeof(double) * (8 * n * n + 8 * n));
+    double t = NAN;
+    if (D && ws) {
+        design_sqdist(n, p, XJ, D);
+        t = mle_fit(n, D, yJ, g, theta0, dmin, dmax, tol, maxit, ws, iters, flags);
+    }
+    free(D);
+    free(ws);
+    return t;
 }
 
 /* Exported for direct checks of the pieces. */

@@ -687,3 +687,115 @@ def test_chol_form_singular_start(orc):
     prm = W.Params(n0=4, n=10, ncand=40, d=(0.1,), g=0.0, scoring=W.SCORING_CHOL)
     out = orc.predict(X, W.f_bump2(X), X[:3].copy(), prm, nthreads=1)
     assert np.all(np.isnan(out["mean"])) and np.all(out["status"] & orc.STATUS_NOTPD)
+
+
+# ------------------------------------------------- local MLE, two stages --
+
+def _np_loglik(XJ, yJ, g, theta):
+    """-1/2 log|K| - n/2 log(y^T K^{-1} y) written with numpy's determinant
+    and solver (an implementation independent of the oracle's)."""
+    n = len(yJ)
+    K = _gauss(XJ, XJ, theta) + g * np.eye(n)
+    sign, logdet = np.linalg.slogdet(K)
+    assert sign > 0
+    return -0.5 * logdet - 0.5 * n * np.log(yJ @ np.linalg.solve(K, yJ))
+
+
+def _mle_case(seed, n=24, p=2):
+    rng = np.random.default_rng(seed)
+    XJ = rng.random((n, p)) * 0.4
+    yJ = W.f_bump2(XJ) if p == 2 else W.f_sines8(np.pad(XJ, ((0, 0), (0, 8 - p))))
+    return XJ, yJ
+
+
+@pytest.mark.parametrize("seed", [41, 42, 43])
+def test_mle_loglik_matches_numpy(orc, seed):
+    XJ, yJ = _mle_case(seed)
+    for theta in (0.01, 0.05, 0.3):
+        l, _, _ = orc.mle_eval(XJ, yJ, 1e-4, theta)
+        assert l == pytest.approx(_np_loglik(XJ, yJ, 1e-4, theta), rel=1e-9, abs=1e-9)
+
+
+@pytest.mark.parametrize("seed", [41, 44])
+def test_mle_derivatives_match_finite_differences(orc, seed):
+    """l' and l'' (Eq. gpk differentiated) against central differences of
+    numpy's log-likelihood and of the oracle's own l'."""
+    XJ, yJ = _mle_case(seed)
+    g = 1e-4
+    for theta in (0.02, 0.08, 0.4):
+        h = 1e-5 * theta
+        l, d1, d2 = orc.mle_eval(XJ, yJ, g, theta)
+        fd1 = (_np_loglik(XJ, yJ, g, theta + h) - _np_loglik(XJ, yJ, g, theta - h)) / (2 * h)
+        assert d1 == pytest.approx(fd1, rel=1e-5, abs=1e-6 * abs(l) / theta)
+        fd2 = (orc.mle_eval(XJ, yJ, g, theta + h)[1] - orc.mle_eval(XJ, yJ, g, theta - h)[1]) / (2 * h)
+        assert d2 == pytest.approx(fd2, rel=1e-5, abs=1e-6 * abs(d1) / theta + 1e-3)
+
+
+@pytest.mark.parametrize("seed", [41, 45, 46, 47])
+def test_mle_fit_is_the_bruteforce_maximiser(orc, seed):
+    """The safeguarded Newton estimate equals the maximiser of numpy's
+    log-likelihood found by a log-spaced scan refined with scipy's bounded
+    scalar search, to 1e-6 relative."""
+    from scipy.optimize import minimize_scalar
+
+    XJ, yJ = _mle_case(seed)
+    g, lo, hi = 1e-4, 1e-3, 10.0
+    t, it, flags = orc.mle_fit(XJ, yJ, g, 0.1, lo, hi, 1e-10, 200)
+    grid = np.exp(np.linspace(np.log(lo), np.log(hi), 400))
+    vals = [_np_loglik(XJ, yJ, g, th) for th in grid]
+    i = int(np.argmax(vals))
+    a, b = grid[max(i - 1, 0)], grid[min(i + 1, len(grid) - 1)]
+    r = minimize_scalar(lambda u: -_np_loglik(XJ, yJ, g, np.exp(u)), bounds=(np.log(a), np.log(b)),
+                        method="bounded", options={"xatol": 1e-12})
+    tstar = float(np.exp(r.x))
+    assert flags == 0 and it < 60
+    assert t == pytest.approx(tstar, rel=1e-6)
+
+
+def test_mle_fit_reports_a_bound(orc):
+    """A response that is nearly linear across the design prefers the
+    longest lengthscale: the estimate sits at dmax and says so."""
+    rng = np.random.default_rng(48)
+    XJ = rng.random((20, 2)) * 0.1
+    yJ = 0.3 * XJ[:, 0] - 0.2 * XJ[:, 1] + 1.0
+    t, it, flags = orc.mle_fit(XJ, yJ, 1e-4, 0.05, 1e-3, 0.5, 1e-8, 100)
+    assert flags & orc.STATUS_MLE_BOUND
+    assert t == pytest.approx(0.5, rel=1e-6)
+
+
+def test_two_stage_is_search_estimate_search_estimate(orc):
+    """Mode 2 = the design searched under the mode-1 estimate (the oracle's
+    ordinary search with d = that estimate), the estimate refitted from it,
+    and the GP prediction at the final estimate on the second design."""
+    w = W.tiny_2d(M=3)
+    prm = w.params.replace(scoring=W.SCORING_CHOL)
+    o1 = orc.predict_mle(w.X, w.y, w.XX, prm, 1, nthreads=1)
+    o2 = orc.predict_mle(w.X, w.y, w.XX, prm, 2, nthreads=1)
+    g = prm.g
+    for m in range(3):
+        s2 = orc.predict(w.X, w.y, w.XX[m:m + 1], prm.replace(d=(float(o1["dhat"][m]),)), nthreads=1)
+        assert np.array_equal(s2["sel"][0], o2["sel"][m])
+        J = o2["sel"][m]
+        t, _, _ = orc.mle_fit(w.X[J], w.y[J], g, float(o1["dhat"][m]), prm.d[0] / 1000, 100 * prm.d[0])
+        assert t == o2["dhat"][m]
+        # the prediction at the final estimate, against 40-digit arithmetic
+        mp.mp.dps = 40
+        th = mp.mpf(float(o2["dhat"][m]))
+        P = [[mp.mpf(float(v)) for v in w.X[r]] for r in J]
+        xm = [mp.mpf(float(v)) for v in w.XX[m]]
+        kk = lambda a, b: mp.exp(-sum((ai - bi) ** 2 for ai, bi in zip(a, b)) / th)  # noqa: E731
+        n = len(J)
+        K = mp.matrix(n, n)
+        for i in range(n):
+            for k in range(n):
+                K[i, k] = kk(P[i], P[k]) + (mp.mpf(g) if i == k else 0)
+        kx = mp.matrix([kk(P[i], xm) for i in range(n)])
+        yJ = mp.matrix([mp.mpf(float(w.y[r])) for r in J])
+        a1, a2 = mp.lu_solve(K, kx), mp.lu_solve(K, yJ)
+        mu = float(sum(a1[i] * yJ[i] for i in range(n)))
+        s2 = float(sum(yJ[i] * a2[i] for i in range(n)) * (1 + mp.mpf(g) - sum(kx[i] * a1[i] for i in range(n))) / n)
+        assert abs(o2["mean"][m] - mu) <= 1e-9 * abs(mu)
+        assert abs(o2["s2"][m] - s2) <= 1e-7 * s2
+    # the mode-1 design is the ordinary search under d0
+    base = orc.predict(w.X, w.y, w.XX, prm, nthreads=1)
+    assert np.array_equal(base["sel"], o1["sel"])
