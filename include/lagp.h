@@ -78,6 +78,9 @@ extern "C" {
 #define LAGP_STATUS_VNONPOS 1   /* a Schur complement v <= 0 was met; scored as 0 */
 #define LAGP_STATUS_NONFINITE 2 /* non-finite mean or scale */
 #define LAGP_STATUS_NOTPD 4     /* the starting n0 x n0 covariance is not positive definite */
+#define LAGP_STATUS_MLE_BOUND 16 /* local MLE: the lengthscale estimate sits at a bound of its range */
+#define LAGP_STATUS_MLE_NOTPD 32 /* local MLE: K was not positive definite at some Newton iterate */
+#define LAGP_STATUS_MLE_MAXIT 64 /* local MLE: the Newton iteration ran out of iterations */
 
 typedef struct lagp_design lagp_design;
 typedef struct lagp_server lagp_server;
@@ -111,6 +114,25 @@ typedef struct {
   int32_t scoring;
   double brent_tol;
 } lagp_params;
+
+/* Local maximum likelihood of an isotropic lengthscale (Sec. 5: every
+ * local design is coupled with a Newton-like estimate of the lengthscale
+ * from the local likelihood, Eq. gpk with the n local points; optionally a
+ * second-stage re-design under that estimate).
+ *   mode: 1 = estimate on the design searched under params->d[0], predict
+ *         under the estimate on that design; 2 = two stages: search under
+ *         d0, estimate, search again under the estimate, estimate again
+ *         from it, predict on the second design;
+ *   dmin, dmax: the range of the estimate (<= 0: d0/1000 and 100 d0);
+ *   tol: stop when a Newton step moves the estimate by at most tol times it
+ *        (<= 0: 1e-8); maxit: likelihood evaluations per stage (<= 0: 100). */
+typedef struct {
+  int32_t mode;
+  int32_t maxit;
+  double dmin;
+  double dmax;
+  double tol;
+} lagp_mle_params;
 
 /* Library version, major*10000 + minor*100 + patch. */
 int32_t lagp_version(void);
@@ -170,6 +192,28 @@ int32_t lagp_predict(const lagp_design* design, const double* XX, int64_t M, con
 int32_t lagp_predict_candidates(const lagp_design* design, const double* XX, int64_t M, const int32_t* cand_idx,
                                 const lagp_params* params, double* mean, double* s2, double* df, int32_t* sel_idx,
                                 double* diag, int32_t* status, void* stream);
+
+/* Local GP prediction with local maximum likelihood of the lengthscale
+ * (lagp_mle_params).  The estimate maximises the local likelihood
+ * l(d) = -1/2 log|K| - n/2 log(y^T K^-1 y) of the n local points (Eq. gpk,
+ * nugget fixed) by Newton's method on l'(d) = 0 from analytic first and
+ * second derivatives, kept inside a bracket that shrinks from [dmin, dmax]
+ * (geometric bisection when a Newton step would leave it); the prediction
+ * (Eqs. predgp, preds2 with n local points) is taken under the estimate
+ * through the Cholesky factor of K.  Needs exhaustive search with
+ * LAGP_SCORING_CHOL (so n <= 50), an isotropic lengthscale (d_len = 1) and
+ * precision FP64.  cand_idx (nullable, device, M x ncand int32) gives the
+ * candidate lists as lagp_candidates writes them; NULL searches them here.
+ * Outputs (device): mean, s2, df (M); dhat (M) the estimate used; sel_idx
+ * (nullable, M x n) the final local design; iters (nullable, M) likelihood
+ * evaluations over all stages; status (nullable, M) LAGP_STATUS_* bits of
+ * every stage or'ed.  A location whose design search fails reports NaN mean
+ * and scale and the lengthscale it was searched under.  Otherwise as
+ * lagp_predict (asynchronous on the stream, workspace stream-ordered). */
+int32_t lagp_predict_mle(const lagp_design* design, const double* XX, int64_t M, const int32_t* cand_idx,
+                         const lagp_params* params, const lagp_mle_params* mle, double* mean, double* s2,
+                         double* df, double* dhat, int32_t* sel_idx, int32_t* iters, int32_t* status,
+                         void* stream);
 
 /* ---- serving: continuous batching over a resident design ---------------
  *

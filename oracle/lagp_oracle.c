@@ -1007,6 +1007,7 @@ static int local_mle(const ctx_t *c, scratch_t *s, const double *x, int mode, do
     double *D = malloc(sizeof(double) * n * n), *ws = malloc(sizeof(double) * (8 * n * n + 8 * n));
     int status = -2;
     if (!J || !XJ || !yJ || !D || !ws) goto out;
+    status = 0; /* the flags of every stage, or'ed */
     const double d0 = 1.0 / c->d[0];
     double theta = d0;
     int total = 0;
@@ -1018,9 +1019,13 @@ static int local_mle(const ctx_t *c, scratch_t *s, const double *x, int mode, do
             cs.d = &wstage;
         }
         double m0, s0, f0;
-        status = local_one(&cs, s, x, NULL, &m0, &s0, &f0, J, NULL, NULL, NULL);
-        if (status < 0) goto out;
-        if (status & (ORC_STATUS_NOTPD | ORC_STATUS_NONFINITE)) {
+        const int st = local_one(&cs, s, x, NULL, &m0, &s0, &f0, J, NULL, NULL, NULL);
+        if (st < 0) {
+            status = st;
+            goto out;
+        }
+        status |= st;
+        if (st & (ORC_STATUS_NOTPD | ORC_STATUS_NONFINITE)) {
             *mean = NAN;
             *s2 = NAN;
             *df = (double)n;

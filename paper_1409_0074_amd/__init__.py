@@ -35,10 +35,13 @@ LAGP_SCORING_CHOL = 1
 LAGP_STATUS_VNONPOS = 1
 LAGP_STATUS_NONFINITE = 2
 LAGP_STATUS_NOTPD = 4
+LAGP_STATUS_MLE_BOUND = 16
+LAGP_STATUS_MLE_NOTPD = 32
+LAGP_STATUS_MLE_MAXIT = 64
 
 EXPORTED = [
     "lagp_version", "lagp_last_error", "lagp_design_create", "lagp_design_destroy", "lagp_design_info",
-    "lagp_candidates", "lagp_predict", "lagp_predict_candidates", "lagp_server_create", "lagp_server_submit", "lagp_server_poll",
+    "lagp_candidates", "lagp_predict", "lagp_predict_candidates", "lagp_predict_mle", "lagp_server_create", "lagp_server_submit", "lagp_server_poll",
     "lagp_server_fetch", "lagp_server_stats", "lagp_server_destroy",
 ]
 
@@ -50,6 +53,11 @@ class lagp_params(ctypes.Structure):
         ("rescore_k", ctypes.c_int32), ("d", ctypes.c_double * LAGP_MAX_DIM), ("g", ctypes.c_double),
         ("brent_maxit", ctypes.c_int32), ("scoring", ctypes.c_int32), ("brent_tol", ctypes.c_double),
     ]
+
+
+class lagp_mle_params(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("maxit", ctypes.c_int32), ("dmin", ctypes.c_double),
+                ("dmax", ctypes.c_double), ("tol", ctypes.c_double)]
 
 
 class LagpError(RuntimeError):
@@ -85,6 +93,9 @@ def lib():
         L.lagp_predict.restype = i32
         L.lagp_predict_candidates.argtypes = [_vp, _vp, i64, _vp, pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.lagp_predict_candidates.restype = i32
+        L.lagp_predict_mle.argtypes = [_vp, _vp, i64, _vp, pp, ctypes.POINTER(lagp_mle_params), _vp, _vp, _vp, _vp,
+                                       _vp, _vp, _vp, _vp]
+        L.lagp_predict_mle.restype = i32
         L.lagp_server_create.argtypes = [_vp, sz, i32, ctypes.POINTER(_vp)]
         L.lagp_server_create.restype = i32
         L.lagp_server_submit.argtypes = [_vp, _vp, i64, pp, ctypes.POINTER(ctypes.c_uint64)]
@@ -189,6 +200,20 @@ def lagp_predict_candidates(design, XX, cand_idx, params: lagp_params, mean, s2,
                                                 _ptr(status), _stream(stream)))
 
 
+def make_mle_params(mode: int, dmin: float = 0.0, dmax: float = 0.0, tol: float = 0.0,
+                    maxit: int = 0) -> lagp_mle_params:
+    M = lagp_mle_params()
+    M.mode, M.maxit, M.dmin, M.dmax, M.tol = int(mode), int(maxit), float(dmin), float(dmax), float(tol)
+    return M
+
+
+def lagp_predict_mle(design, XX, cand_idx, params: lagp_params, mle: lagp_mle_params, mean, s2, df, dhat,
+                     sel_idx=None, iters=None, status=None, stream=None) -> int:
+    return _check(lib().lagp_predict_mle(design, _ptr(XX), XX.shape[0], _ptr(cand_idx), ctypes.byref(params),
+                                         ctypes.byref(mle), _ptr(mean), _ptr(s2), _ptr(df), _ptr(dhat),
+                                         _ptr(sel_idx), _ptr(iters), _ptr(status), _stream(stream)))
+
+
 def lagp_server_create(design, hbm_budget_bytes: int, max_inflight: int):
     h = _vp()
     _check(lib().lagp_server_create(design, int(hbm_budget_bytes), int(max_inflight), ctypes.byref(h)))
@@ -282,4 +307,23 @@ class Design:
         out["diag"] = torch.empty((M, P.n - n0, 2), **dev) if diag else None
         lagp_predict(self.handle, XX, P, out["mean"], out["s2"], out["df"], out["sel"], out["diag"], out["status"],
                      stream)
+        return out
+
+    def predict_mle(self, XX, params, mode: int, dmin: float = 0.0, dmax: float = 0.0, tol: float = 0.0,
+                    maxit: int = 0, stream=None):
+        """Local MLE prediction: a dict of device tensors mean, s2, df, dhat,
+        sel, iters, status."""
+        import torch
+
+        XX = torch.as_tensor(XX, dtype=torch.float64, device="cuda").contiguous()
+        P = params if isinstance(params, lagp_params) else make_params(params)
+        Q = make_mle_params(mode, dmin, dmax, tol, maxit)
+        M = XX.shape[0]
+        dev = dict(dtype=torch.float64, device="cuda")
+        i32 = dict(dtype=torch.int32, device="cuda")
+        out = dict(mean=torch.empty(M, **dev), s2=torch.empty(M, **dev), df=torch.empty(M, **dev),
+                   dhat=torch.empty(M, **dev), sel=torch.empty((M, P.n), **i32), iters=torch.empty(M, **i32),
+                   status=torch.empty(M, **i32))
+        lagp_predict_mle(self.handle, XX, None, P, Q, out["mean"], out["s2"], out["df"], out["dhat"], out["sel"],
+                         out["iters"], out["status"], stream)
         return out

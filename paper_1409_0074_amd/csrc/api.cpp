@@ -384,4 +384,135 @@ int32_t lagp_predict_candidates(const lagp_design* d, const double* XX, int64_t 
   return lagp::run_predict(d, XX, M, cand_idx, P, mean, s2, df, sel_idx, diag, status, stream, workspace_budget());
 }
 
+// Local MLE (mle.hip) around the Cholesky-form search (chol.hip): search
+// under d0, estimate, [search under the estimate, estimate again], predict.
+int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
+                         const lagp_params* P, const lagp_mle_params* mle, double* mean, double* s2, double* df,
+                         double* dhat, int32_t* sel_idx, int32_t* iters, int32_t* status, void* stream) {
+  if (!d) return fail(LAGP_EINVAL, "design is NULL");
+  if (M < 0) return fail(LAGP_EINVAL, "M must be >= 0");
+  int rays = 0;
+  int32_t rc = check_params(d, P, &rays);
+  if (rc != LAGP_OK) return rc;
+  if (!mle) return fail(LAGP_EINVAL, "mle is NULL");
+  if (mle->mode != 1 && mle->mode != 2) return fail(LAGP_EINVAL, "mle->mode must be 1 or 2");
+  if (P->search != LAGP_SEARCH_EXHAUSTIVE || P->scoring != LAGP_SCORING_CHOL || P->precision != LAGP_PREC_FP64)
+    return fail(LAGP_EINVAL, "local MLE needs exhaustive search with LAGP_SCORING_CHOL in FP64");
+  if (P->d_len != 1) return fail(LAGP_EINVAL, "local MLE estimates one isotropic lengthscale: d_len must be 1");
+  const int p = d->p, n = P->n, nc = P->ncand;
+  const double d0 = P->d[0];
+  const double dmin = mle->dmin > 0.0 ? mle->dmin : d0 / 1000.0;
+  const double dmax = mle->dmax > 0.0 ? mle->dmax : 100.0 * d0;
+  const double tol = mle->tol > 0.0 ? mle->tol : 1e-8;
+  const int maxit = mle->maxit > 0 ? mle->maxit : 100;
+  if (!(dmin < dmax) || !std::isfinite(dmax)) return fail(LAGP_EINVAL, "need 0 < dmin < dmax (finite)");
+  const int lds_max = max_lds_per_block();
+  if (!lagp::mle_supported(n, p, (size_t)lds_max)) return fail(LAGP_EINVAL, "local MLE needs n <= 50");
+  if (M == 0) return LAGP_OK;
+  if (!XX || !mean || !s2 || !df || !dhat) return fail(LAGP_EINVAL, "XX, mean, s2, df and dhat must not be NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int S = lagp::knn_sort_size(nc);
+  if (!cand_in && lagp::knn2_merge_lds_bytes(S) > (size_t)lds_max) return fail(LAGP_EINVAL, "ncand too large for LDS");
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t b_knn = cand_in ? 0 : lagp::knn2_bytes_per_location(nc) + 1024;
+  const size_t b_cand = cand_in ? 0 : sizeof(int32_t) * (size_t)nc;
+  const size_t b_sel = sel_idx ? 0 : sizeof(int32_t) * (size_t)n;
+  // stage scratch: status of each search, the stage-one estimate, flags and evaluations
+  const size_t b_st = sizeof(int32_t) * 6, b_th = sizeof(double);
+  const size_t per = b_knn + b_cand + b_sel + b_st + b_th;
+  const int64_t chunk = std::min<int64_t>(M, std::max<int64_t>(lagp::KNN_QB, (int64_t)(workspace_budget() / per)));
+  Workspace ws;
+  ws.s = s;
+  const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_sel = o_cand + al(b_cand * chunk),
+               o_st = o_sel + al(b_sel * chunk), o_th = o_st + al(b_st * chunk), o_sub = o_th + al(b_th * chunk),
+               total = o_sub + (cand_in ? 0 : lagp::knn2_shared_bytes(d->N, p, nc));
+  LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
+  char* base = reinterpret_cast<char*>(ws.ptr);
+  for (int64_t m0 = 0; m0 < M; m0 += chunk) {
+    const int32_t mc = (int32_t)std::min<int64_t>(chunk, M - m0);
+    const int32_t* cand = cand_in ? cand_in + m0 * nc : reinterpret_cast<const int32_t*>(base + o_cand);
+    if (!cand_in)
+      LAGP_HIP(lagp::launch_knn2(knn_args(d, XX + m0 * p, mc, nc, base + o_knn, chunk, base + o_sub,
+                                          reinterpret_cast<int32_t*>(base + o_cand), nullptr),
+                                 s));
+    int32_t* sel = sel_idx ? sel_idx + m0 * n : reinterpret_cast<int32_t*>(base + o_sel);
+    int32_t* stw = reinterpret_cast<int32_t*>(base + o_st);
+    int32_t *st1 = stw, *fl1 = stw + chunk, *it1 = stw + 2 * chunk, *st2 = stw + 3 * chunk;
+    int32_t* st_out = status ? status + m0 : stw + 4 * chunk;
+    int32_t* it_out = iters ? iters + m0 : stw + 5 * chunk;
+    double* th1 = reinterpret_cast<double*>(base + o_th);
+    lagp::LocalArgs a{};
+    a.X = d->X;
+    a.y = d->y;
+    a.lo = d->lo;
+    a.hi = d->hi;
+    a.XX = XX + m0 * p;
+    a.cand = cand;
+    a.mean = mean + m0;  // (overwritten by the prediction under the estimate)
+    a.s2 = s2 + m0;
+    a.df = df + m0;
+    a.sel = sel;
+    a.status = st1;
+    a.N = d->N;
+    a.M = mc;
+    a.p = p;
+    a.n0 = P->n0;
+    a.n = n;
+    a.ncand = nc;
+    a.ncs = (nc + 15) & ~15;
+    a.search = P->search;
+    a.precision = P->precision;
+    a.dlen = 1;
+    a.g = P->g;
+    a.w[0] = 1.0 / d0;
+    LAGP_HIP(lagp::launch_chol(a, s));
+    lagp::MleArgs e{};
+    e.X = d->X;
+    e.y = d->y;
+    e.XX = XX + m0 * p;
+    e.sel = sel;
+    e.d0 = d0;
+    e.dmin = dmin;
+    e.dmax = dmax;
+    e.tol = tol;
+    e.g = P->g;
+    e.maxit = maxit;
+    e.n = n;
+    e.p = p;
+    e.M = mc;
+    e.status_in = st1;
+    if (mle->mode == 1) {
+      e.theta_out = dhat + m0;
+      e.status_out = st_out;
+      e.iters_out = it_out;
+      e.mean = mean + m0;
+      e.s2 = s2 + m0;
+      e.df = df + m0;
+      LAGP_HIP(lagp::launch_mle(e, s));
+      continue;
+    }
+    e.theta_out = th1;
+    e.status_out = fl1;
+    e.iters_out = it1;
+    e.nan_on_skip = 1;
+    LAGP_HIP(lagp::launch_mle(e, s));
+    a.dloc = th1;  // second stage: search under the estimate
+    a.status = st2;
+    LAGP_HIP(lagp::launch_chol(a, s));
+    e.theta0 = th1;
+    e.status_in = st2;
+    e.flags_prev = fl1;
+    e.iters_prev = it1;
+    e.theta_out = dhat + m0;
+    e.status_out = st_out;
+    e.iters_out = it_out;
+    e.mean = mean + m0;
+    e.s2 = s2 + m0;
+    e.df = df + m0;
+    e.nan_on_skip = 0;
+    LAGP_HIP(lagp::launch_mle(e, s));
+  }
+  return LAGP_OK;
+}
+
 }  // extern "C"

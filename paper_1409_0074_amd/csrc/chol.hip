@@ -178,7 +178,7 @@ struct ChRun {
 // past p add exact zeros).  The coordinates of c come in a (c, c+1) pair.
 template <int PM>
 __device__ __forceinline__ void ch_corr2(const double* xs, int CS, int w, int c0, const double* ec, const LocalArgs& A,
-                                         double& k0, double& k1) {
+                                         double w0, double& k0, double& k1) {
   const auto coef = [ec](int i) { return ec[i]; };
   double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -195,8 +195,8 @@ __device__ __forceinline__ void ch_corr2(const double* xs, int CS, int w, int c0
     }
   }
   if (A.dlen == 1) {
-    s0 = s0 * A.w[0];
-    s1 = s1 * A.w[0];
+    s0 = s0 * w0;
+    s1 = s1 * w0;
   }
   k0 = gexp_with(-s0, coef);
   k1 = gexp_with(-s1, coef);
@@ -250,7 +250,7 @@ __device__ __forceinline__ double ch_score(const double v, const double cov, boo
 // ties), publish its column, extend every other candidate's.
 template <int NB, int PM, int CS, bool DIAG, int B>
 __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChPair<ChCfg<NB, PM, CS>::NR>& S,
-                                         ChRun& R, int64_t m) {
+                                         ChRun& R, int64_t m, double w0) {
   using C = ChCfg<NB, PM, CS>;
   constexpr int NUP = C::NUP, SS = C::SS, UL = C::UL, NWV = C::NWV, BL = C::BL;
   constexpr int KE = ch_ke<NB, B>();
@@ -334,7 +334,7 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
     if (j + 1 < n) {
       // both candidates of the pair, taken or not (a taken one is never read again)
       double kv0, kv1;
-      ch_corr2<PM>(L.xs, CS, w, c0, L.ec, a, kv0, kv1);
+      ch_corr2<PM>(L.xs, CS, w, c0, L.ec, a, w0, kv0, kv1);
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
       for (int k = 0; k < KE; ++k) {
@@ -368,10 +368,10 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
 
 template <int NB, int PM, int CS, bool DIAG, int B>
 __device__ __forceinline__ void ch_blocks(const LocalArgs& a, const ChLds& L, ChPair<ChCfg<NB, PM, CS>::NR>& S,
-                                          ChRun& R, int64_t m) {
+                                          ChRun& R, int64_t m, double w0) {
   if constexpr (B < ChCfg<NB, PM, CS>::NCH) {
-    ch_block<NB, PM, CS, DIAG, B>(a, L, S, R, m);
-    if (!R.stop && (B + 1) * CH_CHUNK < a.n) ch_blocks<NB, PM, CS, DIAG, B + 1>(a, L, S, R, m);
+    ch_block<NB, PM, CS, DIAG, B>(a, L, S, R, m, w0);
+    if (!R.stop && (B + 1) * CH_CHUNK < a.n) ch_blocks<NB, PM, CS, DIAG, B + 1>(a, L, S, R, m, w0);
   }
 }
 
@@ -387,6 +387,17 @@ __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int p = a.p, n = a.n, nc = a.ncand;
   const int32_t* C = a.cand + m * nc;
   const int c0 = 2 * tid;
+  // isotropic reciprocal lengthscale: per location when given (a location
+  // without one is skipped), else the call's
+  double w0 = a.w[0];
+  if (a.dloc) {
+    const double dl = a.dloc[m];
+    if (!(dl > 0.0)) {
+      if (tid == 0) a.status[m] = 0;
+      return;
+    }
+    w0 = 1.0 / dl;
+  }
 
   if (tid < LAGP_MAX_DIM) L.x[tid] = tid < p ? a.XX[m * p + tid] : 0.0;
   if (tid < 12) L.ec[tid] = gexp_coef(tid);
@@ -427,7 +438,7 @@ __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) voi
           const double t = L.xs[k * CS + c0 + i] - L.x[k];
           s = __builtin_fma(t, t, s);
         }
-        kx = gexp(-(s * a.w[0]));
+        kx = gexp(-(s * w0));
       } else {
 #pragma unroll
         for (int k = 0; k < PM; ++k) {
@@ -443,7 +454,7 @@ __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
 
   ChRun R{0.0, 0.0, 0.0, 0, true, false};
-  ch_blocks<NB, PM, CS, DIAG, 0>(a, L, S, R, m);
+  ch_blocks<NB, PM, CS, DIAG, 0>(a, L, S, R, m, w0);
 
   const int vf = __syncthreads_or(S.vflag);
   const bool ok = R.pd && R.done == n;

@@ -49,6 +49,30 @@ struct LocalArgs {
   double brent_tol;
   double g;
   double w[LAGP_MAX_DIM];  // reciprocal lengthscales 1/d_k
+  const double* dloc;      // nullable, M: per-location isotropic lengthscale (Cholesky form;
+                           // a location whose entry is not > 0 is skipped, its status set to 0)
+};
+
+// Arguments of the local MLE kernel (mle.hip) for one chunk of locations.
+struct MleArgs {
+  const double* X;
+  const double* y;
+  const double* XX;            // M x p
+  const int32_t* sel;          // M x n design rows
+  const double* theta0;        // nullable, M: starting lengthscales (else d0)
+  double d0;
+  const int32_t* status_in;    // nullable, M: status of the design stage
+  const int32_t* flags_prev;   // nullable, M: status carried from an earlier stage
+  const int32_t* iters_prev;   // nullable, M: evaluations carried from an earlier stage
+  double* theta_out;           // M
+  int32_t* status_out;         // M: status_in | flags_prev | this stage's flags
+  int32_t* iters_out;          // M
+  double* mean;                // nullable (then no prediction), M
+  double* s2;
+  double* df;
+  double dmin, dmax, tol, g;
+  int32_t maxit, n, p, M;
+  int32_t nan_on_skip;         // a skipped location's theta_out: NaN (1) or its starting value (0)
 };
 
 // Arguments of the threshold-first kNN (knn.hip).
@@ -95,6 +119,11 @@ hipError_t launch_local(const LocalArgs& a, hipStream_t s);
 // shape fits its kernels, and the launch (no workspace beyond the arguments).
 bool chol_supported(int n, int ncand, int p, size_t lds_max);
 hipError_t launch_chol(const LocalArgs& a, hipStream_t s);
+
+// Local MLE of the lengthscale and the prediction under it (mle.hip).
+size_t mle_lds_bytes(int n, int p);
+bool mle_supported(int n, int p, size_t lds_max);
+hipError_t launch_mle(const MleArgs& a, hipStream_t s);
 
 hipError_t launch_bbox(const double* X, int64_t N, int p, double* lo, double* hi, hipStream_t s);
 

@@ -1,0 +1,336 @@
+// Local maximum likelihood of an isotropic lengthscale on each location's
+// local design, and the prediction under the estimate (one workgroup per
+// location).
+//
+// The local log-likelihood (Eq. gpk with the n local points, nugget g fixed)
+//   l(theta) = -1/2 log|K| - n/2 log psi,  psi = y^T K^{-1} y,
+//   K = E + g I,  E_ik = exp(-a_ik),  a_ik = D_ik w,  w = 1/theta,
+// has, with Kd = dK/dtheta = E a w, Kdd = d2K/dtheta2 = E (a^2 - 2a) w^2,
+// alpha = K^{-1} y and beta = Kd alpha,
+//   l'  = -1/2 tr(K^{-1} Kd) + n/2 (alpha^T beta) / psi
+//   l'' = -1/2 [tr(K^{-1} Kdd) - tr(K^{-1} Kd K^{-1} Kd)]
+//         + n/2 [(alpha^T Kdd alpha - 2 beta^T K^{-1} beta) / psi + ((alpha^T beta) / psi)^2].
+// Newton's method on l' = 0 runs inside a bracket [lo, hi] that starts at
+// [dmin, dmax]: an iterate with l' > 0 raises lo, otherwise it lowers hi; the
+// Newton step is taken when l'' < 0 and it lands strictly inside the
+// bracket, else the geometric midpoint sqrt(lo hi); a K that is not positive
+// definite counts as l' < 0.  The iteration stops when a step moves theta by
+// at most tol theta (or l' = 0) or after maxit evaluations.  The prediction at
+// the estimate goes through the Cholesky factor: w = L^{-1} k_x,
+// z = L^{-1} y, mean = w^T z, scale psi ((1+g) - w^T w) / n with psi = z^T z.
+//
+// Every sum runs in index order from 0.0 with one fused multiply-add per
+// term, a trace is the in-order sum of its row sums, and K^{-1} comes from
+// the Cholesky factor as L^{-T} L^{-1}, so the estimates and predictions are
+// reproducible bit for bit by any IEEE implementation of the same steps.
+#include "dev_math.h"
+#include "lagp_internal.h"
+
+namespace lagp {
+
+namespace {
+
+constexpr int MLE_THREADS = 256;
+constexpr int MLE_NMAX = 50;
+
+struct MleLds {
+  double* XJ;   // n x p
+  double* D;    // n x LD: squared distances
+  double* E;    // n x LD: exp(-a)
+  double* Kd;   // n x LD
+  double* Lm;   // n x LD: K, then its Cholesky factor (lower triangle)
+  double* Li;   // n x LD: L^{-1} (lower), then K^{-1} Kd
+  double* Ki;   // n x LD
+  double* y;    // n
+  double* al;   // n: K^{-1} y
+  double* be;   // n: Kd alpha
+  double* ga;   // n: K^{-1} beta
+  double* de;   // n: Kdd alpha
+  double* r;    // 3 n: row sums of the three traces
+  double* x;    // LAGP_MAX_DIM
+  double* sc;   // 8 scalars
+  int* flag;    // 4 ints
+};
+
+__host__ __device__ inline size_t mle_lds_bytes_n(int n, int p) {
+  const int LD = n + 1;
+  return sizeof(double) * ((size_t)n * p + 6 * (size_t)n * LD + 8 * (size_t)n + LAGP_MAX_DIM + 8) +
+         4 * sizeof(int);
+}
+
+__device__ inline MleLds mle_carve(unsigned char* s, int n, int p) {
+  const int LD = n + 1;
+  MleLds L;
+  double* d = reinterpret_cast<double*>(s);
+  L.XJ = d; d += n * p;
+  L.D = d; d += n * LD;
+  L.E = d; d += n * LD;
+  L.Kd = d; d += n * LD;
+  L.Lm = d; d += n * LD;
+  L.Li = d; d += n * LD;
+  L.Ki = d; d += n * LD;
+  L.y = d; d += n;
+  L.al = d; d += n;
+  L.be = d; d += n;
+  L.ga = d; d += n;
+  L.de = d; d += n;
+  L.r = d; d += 3 * n;
+  L.x = d; d += LAGP_MAX_DIM;
+  L.sc = d; d += 8;
+  L.flag = reinterpret_cast<int*>(d);
+  return L;
+}
+
+// In-place Cholesky factor of the n x n matrix in Lm (column by column: the
+// pivot, then the rows below it), the arithmetic of every element as
+// L_ik = (K_ik - sum_{m<k} L_im L_km) / L_kk, L_kk = sqrt(K_kk - sum_{m<k} L_km^2).
+// Returns false if a pivot is not positive.
+__device__ bool mle_cholesky(double* Lm, int n, int LD, int* flag) {
+  const int tid = threadIdx.x;
+  if (tid == 0) flag[0] = 1;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      double s = Lm[k * LD + k];
+      for (int m = 0; m < k; ++m) s = __builtin_fma(-Lm[k * LD + m], Lm[k * LD + m], s);
+      if (!(s > 0.0)) flag[0] = 0;
+      Lm[k * LD + k] = __builtin_sqrt(s);
+    }
+    __syncthreads();
+    const double piv = Lm[k * LD + k];
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) {
+      double s = Lm[i * LD + k];
+      for (int m = 0; m < k; ++m) s = __builtin_fma(-Lm[i * LD + m], Lm[k * LD + m], s);
+      Lm[i * LD + k] = s / piv;
+    }
+    __syncthreads();
+  }
+  return flag[0] != 0;
+}
+
+// Index-order inner product (one thread).
+__device__ __forceinline__ double mle_dot(const double* a, const double* b, int n) {
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s = __builtin_fma(a[k], b[k], s);
+  return s;
+}
+
+// l' and l'' at theta (all threads; results in sc[0], sc[1]; returns false
+// if K is not positive definite).
+__device__ bool mle_eval(const MleLds& L, int n, double g, double theta) {
+  const int tid = threadIdx.x, LD = n + 1, T = blockDim.x;
+  const double w = 1.0 / theta;
+  for (int t = tid; t < n * n; t += T) {
+    const int i = t / n, k = t % n;
+    const double a = L.D[i * LD + k] * w;
+    const double e = gexp(-a);
+    L.E[i * LD + k] = e;
+    L.Lm[i * LD + k] = e + (i == k ? g : 0.0);
+    L.Kd[i * LD + k] = (e * a) * w;
+  }
+  __syncthreads();
+  if (!mle_cholesky(L.Lm, n, LD, L.flag)) return false;
+  // L^{-1}, column c by forward substitution
+  for (int c = tid; c < n; c += T)
+    for (int i = c; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int m = c; m < i; ++m) s = __builtin_fma(-L.Lm[i * LD + m], L.Li[m * LD + c], s);
+      L.Li[i * LD + c] = s / L.Lm[i * LD + i];
+    }
+  __syncthreads();
+  // K^{-1} = L^{-T} L^{-1}
+  for (int t = tid; t < n * n; t += T) {
+    const int i = t / n, k = t % n;
+    double s = 0.0;
+    for (int m = (i > k ? i : k); m < n; ++m) s = __builtin_fma(L.Li[m * LD + i], L.Li[m * LD + k], s);
+    L.Ki[i * LD + k] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += T) L.al[i] = mle_dot(L.Ki + i * LD, L.y, n);
+  __syncthreads();
+  const double ww = w * w;
+  for (int i = tid; i < n; i += T) {
+    double b = 0.0, d = 0.0;
+    for (int k = 0; k < n; ++k) {
+      b = __builtin_fma(L.Kd[i * LD + k], L.al[k], b);
+      const double a = L.D[i * LD + k] * w;
+      const double kdd = (L.E[i * LD + k] * (a * a - 2.0 * a)) * ww;
+      d = __builtin_fma(kdd, L.al[k], d);
+    }
+    L.be[i] = b;
+    L.de[i] = d;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += T) L.ga[i] = mle_dot(L.Ki + i * LD, L.be, n);
+  // P = K^{-1} Kd into the L^{-1} buffer (no longer needed)
+  for (int t = tid; t < n * n; t += T) {
+    const int i = t / n, k = t % n;
+    double s = 0.0;
+    for (int m = 0; m < n; ++m) s = __builtin_fma(L.Ki[i * LD + m], L.Kd[m * LD + k], s);
+    L.Li[i * LD + k] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += T) {
+    double r1 = 0.0, r2 = 0.0, r3 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double kik = L.Ki[i * LD + k];
+      r1 = __builtin_fma(kik, L.Kd[k * LD + i], r1);
+      const double a = L.D[k * LD + i] * w;
+      const double kdd = (L.E[k * LD + i] * (a * a - 2.0 * a)) * ww;
+      r2 = __builtin_fma(kik, kdd, r2);
+      r3 = __builtin_fma(L.Li[i * LD + k], L.Li[k * LD + i], r3);
+    }
+    L.r[i] = r1;
+    L.r[n + i] = r2;
+    L.r[2 * n + i] = r3;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double psi = mle_dot(L.y, L.al, n);
+    const double ab = mle_dot(L.al, L.be, n);
+    const double bgb = mle_dot(L.be, L.ga, n);
+    const double add = mle_dot(L.al, L.de, n);
+    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    for (int i = 0; i < n; ++i) {
+      t1 = t1 + L.r[i];
+      t2 = t2 + L.r[n + i];
+      t3 = t3 + L.r[2 * n + i];
+    }
+    const double hn = 0.5 * (double)n;
+    const double q = ab / psi;
+    L.sc[0] = -0.5 * t1 + hn * q;
+    L.sc[1] = -0.5 * (t2 - t3) + hn * ((add - 2.0 * bgb) / psi + q * q);
+  }
+  __syncthreads();
+  return true;
+}
+
+__global__ __launch_bounds__(MLE_THREADS) void k_mle(MleArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = a.n, p = a.p, LD = n + 1, tid = threadIdx.x, T = blockDim.x;
+  const int64_t m = blockIdx.x;
+  const MleLds L = mle_carve(smem, n, p);
+  const int32_t* J = a.sel + m * n;
+  const int st_in = a.status_in ? a.status_in[m] : 0;
+  const int fl_prev = a.flags_prev ? a.flags_prev[m] : 0;
+  const int it_prev = a.iters_prev ? a.iters_prev[m] : 0;
+  const double th0 = a.theta0 ? a.theta0[m] : a.d0;
+  const bool skip = !(th0 > 0.0) || (st_in & (LAGP_STATUS_NOTPD | LAGP_STATUS_NONFINITE));
+  if (skip) {  // the design stage failed (here or in an earlier stage): nothing to fit
+    if (tid == 0) {
+      a.theta_out[m] = a.nan_on_skip ? __builtin_nan("") : (th0 > 0.0 ? th0 : a.d0);
+      a.status_out[m] = st_in | fl_prev;
+      a.iters_out[m] = it_prev;
+      if (a.mean) {
+        a.mean[m] = __builtin_nan("");
+        a.s2[m] = __builtin_nan("");
+        a.df[m] = (double)n;
+      }
+    }
+    return;
+  }
+  for (int t = tid; t < n * p; t += T) L.XJ[t] = a.X[(int64_t)J[t / p] * p + (t % p)];
+  for (int i = tid; i < n; i += T) L.y[i] = a.y[J[i]];
+  for (int k = tid; k < LAGP_MAX_DIM; k += T) L.x[k] = k < p ? a.XX[m * p + k] : 0.0;
+  __syncthreads();
+  for (int t = tid; t < n * n; t += T) {
+    const int i = t / n, k = t % n;
+    L.D[i * LD + k] = sqdist(L.XJ + i * p, L.XJ + k * p, p);
+  }
+  __syncthreads();
+
+  // safeguarded Newton iteration (thread 0 decides, everyone evaluates)
+  double lo = a.dmin, hi = a.dmax;
+  double theta = th0 < lo ? lo : (th0 > hi ? hi : th0);
+  int it = 0, conv = 0, flags = 0;
+  while (it < a.maxit) {
+    const bool ok = mle_eval(L, n, a.g, theta);
+    ++it;
+    double d1 = -1.0, d2 = 0.0;
+    if (ok) {
+      d1 = L.sc[0];
+      d2 = L.sc[1];
+    } else {
+      flags |= LAGP_STATUS_MLE_NOTPD;
+    }
+    __syncthreads();  // every thread has read sc before the next evaluation writes it
+    if (d1 == 0.0) {
+      conv = 1;
+      break;
+    }
+    if (d1 > 0.0)
+      lo = theta;
+    else
+      hi = theta;
+    double tn = (d2 < 0.0) ? theta - d1 / d2 : lo;
+    if (!(tn > lo && tn < hi)) tn = __builtin_sqrt(lo * hi);
+    const bool done = fabs(tn - theta) <= a.tol * theta;
+    theta = tn;
+    if (done) {
+      conv = 1;
+      break;
+    }
+  }
+  if (!conv) flags |= LAGP_STATUS_MLE_MAXIT;
+  if (theta <= a.dmin * (1.0 + a.tol) || theta >= a.dmax * (1.0 - a.tol)) flags |= LAGP_STATUS_MLE_BOUND;
+
+  int st = st_in | fl_prev | flags;
+  if (a.mean) {
+    // prediction at the estimate through the Cholesky factor
+    const double w = 1.0 / theta;
+    for (int t = tid; t < n * n; t += T) {
+      const int i = t / n, k = t % n;
+      L.Lm[i * LD + k] = gexp(-(L.D[i * LD + k] * w)) + (i == k ? a.g : 0.0);
+    }
+    __syncthreads();
+    const bool pd = mle_cholesky(L.Lm, n, LD, L.flag);
+    for (int i = tid; i < n; i += T) L.be[i] = gexp(-(sqdist(L.XJ + i * p, L.x, p) * w));  // k_x
+    __syncthreads();
+    if (tid == 0) {
+      double mu = __builtin_nan(""), sc = __builtin_nan("");
+      if (pd) {
+        for (int i = 0; i < n; ++i) {  // w = L^{-1} k_x into ga, z = L^{-1} y into de
+          double u = L.be[i], v = L.y[i];
+          for (int k = 0; k < i; ++k) {
+            u = __builtin_fma(-L.Lm[i * LD + k], L.ga[k], u);
+            v = __builtin_fma(-L.Lm[i * LD + k], L.de[k], v);
+          }
+          L.ga[i] = u / L.Lm[i * LD + i];
+          L.de[i] = v / L.Lm[i * LD + i];
+        }
+        mu = mle_dot(L.ga, L.de, n);
+        const double psi = mle_dot(L.de, L.de, n);
+        sc = psi * ((1.0 + a.g) - mle_dot(L.ga, L.ga, n)) / (double)n;
+      } else {
+        st |= LAGP_STATUS_NOTPD;
+      }
+      if (!(fabs(mu) <= 1.7976931348623157e308 && fabs(sc) <= 1.7976931348623157e308)) st |= LAGP_STATUS_NONFINITE;
+      a.mean[m] = mu;
+      a.s2[m] = sc;
+      a.df[m] = (double)n;
+    }
+  }
+  if (tid == 0) {
+    a.theta_out[m] = theta;
+    a.status_out[m] = st;
+    a.iters_out[m] = it_prev + it;
+  }
+}
+
+}  // namespace
+
+size_t mle_lds_bytes(int n, int p) { return mle_lds_bytes_n(n, p); }
+
+bool mle_supported(int n, int p, size_t lds_max) { return n <= MLE_NMAX && mle_lds_bytes_n(n, p) <= lds_max; }
+
+hipError_t launch_mle(const MleArgs& a, hipStream_t s) {
+  if (a.M <= 0) return hipSuccess;
+  const size_t lds = mle_lds_bytes_n(a.n, a.p);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mle),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mle, dim3(a.M), dim3(MLE_THREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lagp

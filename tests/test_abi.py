@@ -57,8 +57,10 @@ def test_params_struct_layout_matches_c():
 #include <stdio.h>
 #include "lagp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(lagp_params), offsetof(lagp_params, d), offsetof(lagp_params, g),
-         offsetof(lagp_params, brent_maxit), offsetof(lagp_params, brent_tol));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lagp_params), offsetof(lagp_params, d),
+         offsetof(lagp_params, g), offsetof(lagp_params, brent_maxit), offsetof(lagp_params, brent_tol),
+         offsetof(lagp_params, scoring), sizeof(lagp_mle_params), offsetof(lagp_mle_params, dmin),
+         offsetof(lagp_mle_params, tol));
   return 0;
 }
 """
@@ -69,8 +71,9 @@ int main(void) {
         subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), c, "-o", exe],
                        check=True)
         got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
-    P = lg.lagp_params
-    assert got == [ctypes.sizeof(P), P.d.offset, P.g.offset, P.brent_maxit.offset, P.brent_tol.offset]
+    P, Q = lg.lagp_params, lg.lagp_mle_params
+    assert got == [ctypes.sizeof(P), P.d.offset, P.g.offset, P.brent_maxit.offset, P.brent_tol.offset,
+                   P.scoring.offset, ctypes.sizeof(Q), Q.dmin.offset, Q.tol.offset]
 
 
 def test_header_compiles_as_c_and_cxx():

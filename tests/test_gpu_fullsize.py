@@ -88,6 +88,28 @@ def test_uniform8d_full_size_sampled_chol(lg):
     assert np.array_equal(g["mean"][idx], o["mean"]) and np.array_equal(g["s2"][idx], o["s2"])
 
 
+def test_uniform8d_full_size_two_stage_mle_sampled(lg):
+    """Two-stage local MLE over all 1e4 locations of the full-size 8-d
+    workload (isotropic d0 = 0.5), as the benchmark runs it; 8 sampled
+    locations recomputed by the oracle, bit for bit."""
+    import torch
+
+    w = W.uniform8d()
+    prm = w.params.replace(d=(0.5,), scoring=W.SCORING_CHOL)
+    d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
+    try:
+        out = d.predict_mle(torch.from_numpy(w.XX), prm, 2)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+    finally:
+        d.close()
+    assert np.all(np.isfinite(g["mean"]))
+    idx = _sample(w.XX.shape[0], 8, 509)
+    o = oracle.predict_mle(w.X, w.y, w.XX[idx], prm, 2)
+    for k in ("sel", "dhat", "iters", "status", "mean", "s2"):
+        assert np.array_equal(g[k][idx], o[k]), k
+
+
 def test_grid2d_full_size_sampled(lg):
     """1000 x 1000 grid design, n = 100, N' = 4000, the first 2000 locations
     through lagp_predict (as the benchmark's grid leg), 6 sampled locations
