@@ -32,6 +32,7 @@ namespace {
 
 constexpr int MLE_THREADS = 256;
 constexpr int MLE_NMAX = 50;
+static_assert(MLE_NMAX <= 64, "the factor's trailing updates take one lane per column");
 
 struct MleLds {
   double* XJ;   // n x p
@@ -47,15 +48,14 @@ struct MleLds {
   double* ga;   // n: K^{-1} beta
   double* de;   // n: Kdd alpha
   double* r;    // 3 n: row sums of the three traces
+  double* dg;   // n: diagonal of the Cholesky factor
   double* x;    // LAGP_MAX_DIM
-  double* sc;   // 8 scalars
-  int* flag;    // 4 ints
+  double* sc;   // 12 scalars
 };
 
 __host__ __device__ inline size_t mle_lds_bytes_n(int n, int p) {
   const int LD = n + 1;
-  return sizeof(double) * ((size_t)n * p + 6 * (size_t)n * LD + 8 * (size_t)n + LAGP_MAX_DIM + 8) +
-         4 * sizeof(int);
+  return sizeof(double) * ((size_t)n * p + 6 * (size_t)n * LD + 9 * (size_t)n + LAGP_MAX_DIM + 12);
 }
 
 __device__ inline MleLds mle_carve(unsigned char* s, int n, int p) {
@@ -75,37 +75,88 @@ __device__ inline MleLds mle_carve(unsigned char* s, int n, int p) {
   L.ga = d; d += n;
   L.de = d; d += n;
   L.r = d; d += 3 * n;
+  L.dg = d; d += n;
   L.x = d; d += LAGP_MAX_DIM;
-  L.sc = d; d += 8;
-  L.flag = reinterpret_cast<int*>(d);
+  L.sc = d;
   return L;
 }
 
-// In-place Cholesky factor of the n x n matrix in Lm (column by column: the
-// pivot, then the rows below it), the arithmetic of every element as
-// L_ik = (K_ik - sum_{m<k} L_im L_km) / L_kk, L_kk = sqrt(K_kk - sum_{m<k} L_km^2).
-// Returns false if a pivot is not positive.
-__device__ bool mle_cholesky(double* Lm, int n, int LD, int* flag) {
-  const int tid = threadIdx.x;
-  if (tid == 0) flag[0] = 1;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      double s = Lm[k * LD + k];
-      for (int m = 0; m < k; ++m) s = __builtin_fma(-Lm[k * LD + m], Lm[k * LD + m], s);
-      if (!(s > 0.0)) flag[0] = 0;
-      Lm[k * LD + k] = __builtin_sqrt(s);
+// Cholesky factor of the n x n matrix in Lm and, when Li is given, the
+// inverse of the factor, both right-looking so that every step is parallel:
+// step m takes the pivot L_mm = sqrt(s_mm) (kept in dg; Lm's diagonal is not
+// overwritten), divides column m of L and row m of L^{-1} by it, then
+// subtracts L_im L_km from every trailing s_ik (m < k <= i) and L_im
+// (L^{-1})_mc from every s'_ic (m < i, c <= m).  Each element therefore
+// receives exactly the terms of its defining sum
+//   L_ik = (K_ik - sum_{m<k} L_im L_km) / L_kk,
+//   (L^{-1})_ic = ([i = c] - sum_{c<=m<i} L_im (L^{-1})_mc) / L_ii
+// in ascending m, one fused multiply-add each: the values of the
+// column-by-column algorithm, bit for bit.  Li must hold the identity on and
+// below the diagonal on entry.  Returns false if a pivot is not positive.
+__device__ bool mle_cholesky(double* Lm, double* dg, double* Li, int n, int LD) {
+  const int tid = threadIdx.x, T = blockDim.x;
+  for (int m = 0; m < n; ++m) {
+    const double smm = Lm[m * LD + m];
+    if (!(smm > 0.0)) return false;  // (every thread reads the same value)
+    const double piv = __builtin_sqrt(smm);
+    const int nl = n - m - 1, nr = Li ? m + 1 : 0;
+    for (int t = tid; t < nl + nr; t += T) {
+      if (t < nl) {
+        const int i = m + 1 + t;
+        Lm[i * LD + m] = Lm[i * LD + m] / piv;
+      } else {
+        const int c = t - nl;
+        Li[m * LD + c] = Li[m * LD + c] / piv;
+      }
     }
+    if (tid == 0) dg[m] = piv;
     __syncthreads();
-    const double piv = Lm[k * LD + k];
-    for (int i = k + 1 + tid; i < n; i += blockDim.x) {
-      double s = Lm[i * LD + k];
-      for (int m = 0; m < k; ++m) s = __builtin_fma(-Lm[i * LD + m], Lm[k * LD + m], s);
-      Lm[i * LD + k] = s / piv;
+    // trailing updates, one row of the block per wave at a time (n <= 64:
+    // a lane per column): (i, k) with m < k <= i, and (i, c) with c <= m
+    const int lane = tid & 63, nwv = T >> 6;
+    for (int r = tid >> 6; r < nl; r += nwv) {
+      const int i = m + 1 + r;
+      const double lim = Lm[i * LD + m];
+      if (lane <= r) {
+        const int k = m + 1 + lane;
+        Lm[i * LD + k] = __builtin_fma(-lim, Lm[k * LD + m], Lm[i * LD + k]);
+      }
+      if (lane < nr) Li[i * LD + lane] = __builtin_fma(-lim, Li[m * LD + lane], Li[i * LD + lane]);
     }
     __syncthreads();
   }
-  return flag[0] != 0;
+  return true;
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// C = A B for n x n operands on f64 MFMA: 16 x 16 tiles, one per wave at a
+// time, k in chunks of 4 in ascending order.  v_mfma_f64_16x16x4f64 adds
+// sum_k A[i][k] B[k][j] to its accumulator as fused multiply-adds in
+// ascending k, so every element is the index-order fma chain from 0.0 (the
+// padding past n adds exact zeros).  Lane layout: A[i][k] from lane
+// 16k + i, B[k][j] from lane 16k + j, C[i][j] in register i/4 of lane
+// 16(i%4) + j.
+template <class FA, class FB, class ST>
+__device__ __forceinline__ void mle_gemm(int n, const FA& fa, const FB& fb, const ST& st) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nt = (n + 15) / 16, nk = (n + 3) / 4;
+  for (int t = wv; t < nt * nt; t += nw) {
+    const int ti = t / nt, tj = t % nt;
+    const int ai = 16 * ti + (lane & 15), bj = 16 * tj + (lane & 15), kl = lane >> 4;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < nk; ++kc) {
+      const int k = 4 * kc + kl;
+      const double av = (ai < n && k < n) ? fa(ai, k) : 0.0;
+      const double bv = (k < n && bj < n) ? fb(k, bj) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * ti + 4 * r + kl;
+      if (i < n && bj < n) st(i, bj, acc[r]);
+    }
+  }
 }
 
 // Index-order inner product (one thread).
@@ -127,23 +178,18 @@ __device__ bool mle_eval(const MleLds& L, int n, double g, double theta) {
     L.E[i * LD + k] = e;
     L.Lm[i * LD + k] = e + (i == k ? g : 0.0);
     L.Kd[i * LD + k] = (e * a) * w;
+    L.Li[i * LD + k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (!mle_cholesky(L.Lm, n, LD, L.flag)) return false;
-  // L^{-1}, column c by forward substitution
-  for (int c = tid; c < n; c += T)
-    for (int i = c; i < n; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int m = c; m < i; ++m) s = __builtin_fma(-L.Lm[i * LD + m], L.Li[m * LD + c], s);
-      L.Li[i * LD + c] = s / L.Lm[i * LD + i];
-    }
-  __syncthreads();
-  // K^{-1} = L^{-T} L^{-1}
-  for (int t = tid; t < n * n; t += T) {
-    const int i = t / n, k = t % n;
-    double s = 0.0;
-    for (int m = (i > k ? i : k); m < n; ++m) s = __builtin_fma(L.Li[m * LD + i], L.Li[m * LD + k], s);
-    L.Ki[i * LD + k] = s;
+  if (!mle_cholesky(L.Lm, L.dg, L.Li, n, LD)) return false;
+  // K^{-1} = L^{-T} L^{-1}: (K^{-1})_ik = sum_{m >= max(i,k)} (L^{-1})_mi (L^{-1})_mk,
+  // the terms below max(i,k) being exact zeros of the lower triangular factor
+  {
+    const double* Li = L.Li;
+    double* Ki = L.Ki;
+    mle_gemm(
+        n, [=](int i, int k) { return Li[k * LD + i]; }, [=](int k, int j) { return Li[k * LD + j]; },
+        [=](int i, int j, double v) { Ki[i * LD + j] = v; });
   }
   __syncthreads();
   for (int i = tid; i < n; i += T) L.al[i] = mle_dot(L.Ki + i * LD, L.y, n);
@@ -163,11 +209,13 @@ __device__ bool mle_eval(const MleLds& L, int n, double g, double theta) {
   __syncthreads();
   for (int i = tid; i < n; i += T) L.ga[i] = mle_dot(L.Ki + i * LD, L.be, n);
   // P = K^{-1} Kd into the L^{-1} buffer (no longer needed)
-  for (int t = tid; t < n * n; t += T) {
-    const int i = t / n, k = t % n;
-    double s = 0.0;
-    for (int m = 0; m < n; ++m) s = __builtin_fma(L.Ki[i * LD + m], L.Kd[m * LD + k], s);
-    L.Li[i * LD + k] = s;
+  {
+    const double* Ki = L.Ki;
+    const double* Kd = L.Kd;
+    double* P = L.Li;
+    mle_gemm(
+        n, [=](int i, int k) { return Ki[i * LD + k]; }, [=](int k, int j) { return Kd[k * LD + j]; },
+        [=](int i, int j, double v) { P[i * LD + j] = v; });
   }
   __syncthreads();
   for (int i = tid; i < n; i += T) {
@@ -185,17 +233,27 @@ __device__ bool mle_eval(const MleLds& L, int n, double g, double theta) {
     L.r[2 * n + i] = r3;
   }
   __syncthreads();
-  if (tid == 0) {
-    const double psi = mle_dot(L.y, L.al, n);
-    const double ab = mle_dot(L.al, L.be, n);
-    const double bgb = mle_dot(L.be, L.ga, n);
-    const double add = mle_dot(L.al, L.de, n);
-    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
-    for (int i = 0; i < n; ++i) {
-      t1 = t1 + L.r[i];
-      t2 = t2 + L.r[n + i];
-      t3 = t3 + L.r[2 * n + i];
+  // the seven scalar sums, each one in-order chain, on lanes of different waves
+  {
+    const int job = (tid & 63) == 0 ? tid >> 6 : -1;
+    const int nw = T >> 6;
+    for (int q = job; q >= 0 && q < 7; q += nw) {
+      double v = 0.0;
+      if (q == 0) v = mle_dot(L.y, L.al, n);   // psi
+      if (q == 1) v = mle_dot(L.al, L.be, n);  // alpha^T Kd alpha
+      if (q == 2) v = mle_dot(L.be, L.ga, n);  // beta^T K^{-1} beta
+      if (q == 3) v = mle_dot(L.al, L.de, n);  // alpha^T Kdd alpha
+      if (q >= 4) {
+        const double* rr = L.r + (q - 4) * n;  // the traces: in-order sums of the row sums
+        for (int i = 0; i < n; ++i) v = v + rr[i];
+      }
+      L.sc[2 + q] = v;
     }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double psi = L.sc[2], ab = L.sc[3], bgb = L.sc[4], add = L.sc[5];
+    const double t1 = L.sc[6], t2 = L.sc[7], t3 = L.sc[8];
     const double hn = 0.5 * (double)n;
     const double q = ab / psi;
     L.sc[0] = -0.5 * t1 + hn * q;
@@ -283,7 +341,7 @@ __global__ __launch_bounds__(MLE_THREADS) void k_mle(MleArgs a) {
       L.Lm[i * LD + k] = gexp(-(L.D[i * LD + k] * w)) + (i == k ? a.g : 0.0);
     }
     __syncthreads();
-    const bool pd = mle_cholesky(L.Lm, n, LD, L.flag);
+    const bool pd = mle_cholesky(L.Lm, L.dg, nullptr, n, LD);
     for (int i = tid; i < n; i += T) L.be[i] = gexp(-(sqdist(L.XJ + i * p, L.x, p) * w));  // k_x
     __syncthreads();
     if (tid == 0) {
@@ -295,8 +353,8 @@ __global__ __launch_bounds__(MLE_THREADS) void k_mle(MleArgs a) {
             u = __builtin_fma(-L.Lm[i * LD + k], L.ga[k], u);
             v = __builtin_fma(-L.Lm[i * LD + k], L.de[k], v);
           }
-          L.ga[i] = u / L.Lm[i * LD + i];
-          L.de[i] = v / L.Lm[i * LD + i];
+          L.ga[i] = u / L.dg[i];
+          L.de[i] = v / L.dg[i];
         }
         mu = mle_dot(L.ga, L.de, n);
         const double psi = mle_dot(L.de, L.de, n);
