@@ -32,7 +32,9 @@ def _requests(rng, count):
         m = int(np.floor(10 ** rng.uniform(0, 2.5)))
         n = [30, 50, 100][k % 3]
         search = W.SEARCH_RAY if k % 2 else W.SEARCH_EXHAUSTIVE
-        prm = W.Params(n0=6, n=n, ncand=1000 if n < 100 else 1200, search=search, numrays=4, d=(0.1,), g=1e-6)
+        chol = search == W.SEARCH_EXHAUSTIVE and n <= 50 and k % 4 == 0  # both scoring forms in the mix
+        prm = W.Params(n0=6, n=n, ncand=1000 if n < 100 else 1200, search=search, numrays=4, d=(0.1,), g=1e-6,
+                       scoring=W.SCORING_CHOL if chol else W.SCORING_PARTINV)
         out.append((rng.random((m, 4)), prm))
     return out
 
