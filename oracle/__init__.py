@@ -76,8 +76,9 @@ def lib():
         L.orc_spd_inverse.argtypes = [_dp, ctypes.c_int, _dp]
         L.orc_spd_inverse.restype = ctypes.c_int
         i32 = ctypes.c_int
-        L.orc_predict_mle.argtypes = common + [_dp, ctypes.c_int64, i32, i32, i32, ctypes.c_double, ctypes.c_double,
-                                               i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32, i32,
+        L.orc_predict_mle.argtypes = common + [_dp, ctypes.c_int64, i32, i32, i32, i32, i32, ctypes.c_double,
+                                               ctypes.c_double, i32, ctypes.c_double, i32, i32, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, i32, i32,
                                                _dp, _dp, _dp, _i32p, _dp, _i32p, _i32p]
         L.orc_predict_mle.restype = ctypes.c_int
         L.orc_mle_eval.argtypes = [i32, i32, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
@@ -171,7 +172,8 @@ def predict_mle(X, y, XX, params, mode: int, dmin: float = 0.0, dmax: float = 0.
                 maxit: int = 0, nthreads: int | None = None):
     """Local MLE of an isotropic lengthscale (mode 1: on the design searched
     under params.d; mode 2: two-stage re-design) and the prediction under the
-    estimate, at every row of XX (exhaustive search, params.scoring)."""
+    estimate, at every row of XX (any search mode of params; exhaustive
+    search scored as params.scoring)."""
     X, y, XX = _f64(X), _f64(y), _f64(np.atleast_2d(XX))
     N, p = X.shape
     M = XX.shape[0]
@@ -179,7 +181,8 @@ def predict_mle(X, y, XX, params, mode: int, dmin: float = 0.0, dmax: float = 0.
     d0 = float(np.atleast_1d(params.d)[0])
     out = dict(mean=np.empty(M), s2=np.empty(M), df=np.empty(M), sel=np.empty((M, n), np.int32),
                dhat=np.empty(M), iters=np.empty(M, np.int32), status=np.empty(M, np.int32))
-    rc = lib().orc_predict_mle(_p(X), _p(y), N, p, _p(XX), M, params.n0, n, params.ncand, d0, params.g,
+    rc = lib().orc_predict_mle(_p(X), _p(y), N, p, _p(XX), M, params.n0, n, params.ncand, params.search,
+                               params.numrays, d0, params.g, params.brent_maxit, params.brent_tol,
                                getattr(params, "scoring", 0), mode, dmin, dmax, tol, maxit,
                                nthreads or default_threads(), _p(out["mean"]), _p(out["s2"]), _p(out["df"]),
                                _p(out["sel"], _i32p), _p(out["dhat"]), _p(out["iters"], _i32p),

@@ -1155,11 +1155,12 @@ int orc_trace(const double *X, const double *y, int64_t N, int p, const double *
  * <= 0 for the defaults d0/1000, 100 d0, 1e-8, 100).  Outputs mean, s2, df,
  * dhat (the estimate used), iters (Newton evaluations), sel (M x n), status. */
 int orc_predict_mle(const double *X, const double *y, int64_t N, int p, const double *XX, int64_t M, int n0, int n,
-                    int ncand, double d0, double g, int scoring, int mode, double dmin, double dmax, double tol,
-                    int maxit, int nthreads, double *mean, double *s2, double *df, int32_t *sel, double *dhat,
-                    int32_t *iters, int32_t *status)
+                    int ncand, int search, int numrays, double d0, double g, int brent_maxit, double brent_tol,
+                    int scoring, int mode, double dmin, double dmax, double tol, int maxit, int nthreads,
+                    double *mean, double *s2, double *df, int32_t *sel, double *dhat, int32_t *iters,
+                    int32_t *status)
 {
-    if (check_args(N, p, n0, n, ncand, 0, 0, &d0, 1, g, scoring) != 0 || M < 0) return -1;
+    if (check_args(N, p, n0, n, ncand, search, numrays, &d0, 1, g, scoring) != 0 || M < 0) return -1;
     if (mode < 1 || mode > 2) return -1;
     if (!(dmin > 0.0)) dmin = d0 / 1000.0;
     if (!(dmax > 0.0)) dmax = 100.0 * d0;
@@ -1168,7 +1169,9 @@ int orc_predict_mle(const double *X, const double *y, int64_t N, int p, const do
     if (!(dmin < dmax)) return -1;
     double lo[16], hi[16], w0 = 1.0 / d0;
     bbox(X, N, p, lo, hi);
-    ctx_t c = {X, y, N, p, n0, n, ncand, 0, 0, &w0, 1, g, 100, ldexp(1.0, -13), lo, hi, scoring};
+    ctx_t c = {X, y, N, p, n0, n, ncand, search, numrays, &w0, 1, g,
+               brent_maxit > 0 ? brent_maxit : 100, brent_tol > 0.0 ? brent_tol : ldexp(1.0, -13), lo, hi,
+               scoring};
     int err = 0;
 #pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
     {

@@ -96,6 +96,17 @@ def f_mix4(X: np.ndarray) -> np.ndarray:
     return np.sin(3.0 * X[:, 0]) * np.cos(2.0 * X[:, 1]) + X[:, 2] ** 2 - 0.5 * X[:, 3]
 
 
+def w_sec51(x: np.ndarray) -> np.ndarray:
+    """The factor of the 2-d test function of Sec. 5.1:
+    w(x) = exp(-(x-1)^2) + exp(-0.8 (x+1)^2) - 0.05 sin(8 (x+0.1))."""
+    return np.exp(-((x - 1.0) ** 2)) + np.exp(-0.8 * (x + 1.0) ** 2) - 0.05 * np.sin(8.0 * (x + 0.1))
+
+
+def f_sec51(X: np.ndarray) -> np.ndarray:
+    """The 2-d test function of Sec. 5.1: f(x1, x2) = -w(x1) w(x2)."""
+    return -w_sec51(X[:, 0]) * w_sec51(X[:, 1])
+
+
 def grid2(side: int) -> np.ndarray:
     """Regular side x side grid on [0,1]^2, x = i/(side-1); first axis slowest."""
     g = np.arange(side, dtype=np.float64) / (side - 1)
@@ -139,6 +150,32 @@ def grid2d(M: int | None = None, side: int = 1000, precision: int = PREC_FP64) -
     p = Params(n0=6, n=100, ncand=4000, search=SEARCH_EXHAUSTIVE, d=(0.05,), g=1e-6, precision=precision)
     tag = "mixed" if precision == PREC_MIXED else "fp64"
     return Workload(f"grid2d_N{side * side}_M{XX.shape[0]}_n100_cand4000_{tag}", X, f_bump2(X), XX, p, f_bump2(XX))
+
+
+def paper2d(M: int | None = None, n: int = 50, search: int = SEARCH_EXHAUSTIVE, numrays: int = 1,
+            ncand: int = 1000, scoring: int = SCORING_CHOL) -> Workload:
+    """The 2-d experiment of Sec. 5.1: a 201 x 201 grid design on [-2, 2]^2
+    (N = 40401, spacing 0.02) with f = -w(x1) w(x2), no noise, and a 99 x 99
+    predictive grid spaced to avoid the design: x_i = -1.95 + 0.04 i in each
+    coordinate (every value midway between two design lines).  n0 = 6,
+    N' = 1000 nearest candidates, one ray per step (as the section uses on
+    this dense design), starting lengthscale d0 = 0.5 (the value of the
+    section's illustrations on this grid; it is refitted by local MLE) and
+    nugget g = 1e-6."""
+    t = -2.0 + 0.02 * np.arange(201, dtype=np.float64)
+    a, b = np.meshgrid(t, t, indexing="ij")
+    X = np.ascontiguousarray(np.stack([a.ravel(), b.ravel()], axis=1))
+    u = -1.95 + 0.04 * np.arange(99, dtype=np.float64)
+    a, b = np.meshgrid(u, u, indexing="ij")
+    XX = np.ascontiguousarray(np.stack([a.ravel(), b.ravel()], axis=1))
+    if M is not None:
+        XX = XX[:M]
+    ray = search == SEARCH_RAY
+    p = Params(n0=6, n=n, ncand=ncand, search=search, numrays=numrays if ray else 0, d=(0.5,), g=1e-6,
+               scoring=scoring if search == SEARCH_EXHAUSTIVE else SCORING_PARTINV)
+    mode = {SEARCH_EXHAUSTIVE: "exhaustive", SEARCH_RAY: f"ray{numrays}", SEARCH_NN: "nn"}[search]
+    return Workload(f"sec51grid2d_N40401_M{XX.shape[0]}_n{n}_cand{ncand}_{mode}", X, f_sec51(X), XX, p,
+                    f_sec51(XX))
 
 
 def serving4d(N: int = 2_000_000) -> Workload:
@@ -198,6 +235,7 @@ WORKLOADS = {
     "uniform2d_tiny": tiny_2d,
     "uniform8d_exhaustive": lambda M=None: uniform8d(M, search=SEARCH_EXHAUSTIVE),
     "uniform8d_ray": lambda M=None: uniform8d(M, search=SEARCH_RAY),
+    "sec51grid2d": paper2d,
     "grid2d_fp64": lambda M=None: grid2d(M, precision=PREC_FP64),
     "grid2d_mixed": lambda M=None: grid2d(M, precision=PREC_MIXED),
 }

@@ -799,3 +799,31 @@ def test_two_stage_is_search_estimate_search_estimate(orc):
     # the mode-1 design is the ordinary search under d0
     base = orc.predict(w.X, w.y, w.XX, prm, nthreads=1)
     assert np.array_equal(base["sel"], o1["sel"])
+
+
+@pytest.mark.parametrize("search,numrays", [(W.SEARCH_RAY, 1), (W.SEARCH_NN, 0)])
+def test_two_stage_with_rays_and_nearest_neighbours(orc, search, numrays):
+    """Sec. 5 couples every design search with local inference.  With rays
+    or nearest neighbours the stages compose the same way: the design
+    searched under d0, the estimate fitted on it from d0, the design searched
+    under that estimate, the estimate refitted from it.  The nearest-neighbour
+    design is the n nearest by brute force at both stages (it does not depend
+    on d), so its two stages share one design."""
+    w = W.tiny_2d(M=3)
+    prm = w.params.replace(search=search, numrays=numrays)
+    o1 = orc.predict_mle(w.X, w.y, w.XX, prm, 1, nthreads=1)
+    o2 = orc.predict_mle(w.X, w.y, w.XX, prm, 2, nthreads=1)
+    lo, hi = prm.d[0] / 1000, 100 * prm.d[0]
+    for m in range(3):
+        s1 = orc.predict(w.X, w.y, w.XX[m:m + 1], prm, nthreads=1)["sel"][0]
+        assert np.array_equal(s1, o1["sel"][m])
+        t1, it1, _ = orc.mle_fit(w.X[s1], w.y[s1], prm.g, prm.d[0], lo, hi)
+        assert t1 == o1["dhat"][m] and it1 == o1["iters"][m]
+        s2 = orc.predict(w.X, w.y, w.XX[m:m + 1], prm.replace(d=(float(t1),)), nthreads=1)["sel"][0]
+        assert np.array_equal(s2, o2["sel"][m])
+        t2, it2, _ = orc.mle_fit(w.X[s2], w.y[s2], prm.g, t1, lo, hi)
+        assert t2 == o2["dhat"][m] and it1 + it2 == o2["iters"][m]
+        if search == W.SEARCH_NN:
+            near = np.argsort(((w.X - w.XX[m]) ** 2).sum(axis=1), kind="stable")[:prm.n]
+            assert set(near) == set(s1) == set(s2)
+    assert np.all(np.isfinite(o2["mean"])) and np.all(o2["s2"] > 0)
