@@ -36,10 +36,10 @@ COMMON_SOURCES = ("paper_1409_0074_amd/csrc/dev_math.h", "paper_1409_0074_amd/cs
 KERNEL_SOURCES = {"k_chol": ("paper_1409_0074_amd/csrc/chol.hip",) + COMMON_SOURCES,
                   "k_local": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES}
 MEASURED_TRAFFIC = {
-    "k_chol": {"sha256": "d5fbf2bffceb3be05e4173eb6f60f32e2a56b8bf43827eeafd0ac823cbb8bb1a",
-               "bytes": 2.295e9, "fetch_kib": 1119846.4, "write_kib": 1255.5},
-    "k_local": {"sha256": "df70cb53e2ae6201c135595ccf412d0a691cc8d41eb92d0b5ea156ceecfc23a4",
-                "bytes": 1.405e11, "fetch_kib": 66323586.4, "write_kib": 4578536.8},
+    "k_chol": {"sha256": "cacd3c2c861cb153b04418d80833a3187a31a71f5375df0fe53afd35b01dc255",
+               "bytes": 2.296e9, "fetch_kib": 1120560.8, "write_kib": 1257.9},
+    "k_local": {"sha256": "03f296cfa443338131bd0a56d4dd0352ed9009c2bd54fdd52c2b58dbbb2058ee",
+                "bytes": 1.405e11, "fetch_kib": 66299878.6, "write_kib": 4579154.5},
 }
 
 
@@ -190,6 +190,99 @@ def grid(M: int):
     return out
 
 
+# Table 1 of Sec. 5.1 (left: 2010 iMac, 8 threads; right: 16 Sandy Bridge
+# threads with two M2090 GPUs for the exhaustive search), seconds for the
+# 9801 predictive locations: context beside this GPU's times, not a target.
+SEC51_PAPER_SECS = {"ray_n50_stage2": 87.8, "ext_n50_stage2": 436.8, "ray_n50_stage1": 45.6,
+                    "ext_n50_stage1": 390.4, "nn_n50": 11.5}
+SEC51_PAPER_RIGHT = {"ext_n50_cand1000_stage1": {"cpu_gpu": 91, "imac_rays": 46},
+                     "ext_n50_cand2000_stage1": {"cpu_gpu": 120, "imac_rays": 46}}
+
+
+def sec51(steps: int):
+    """The 2-d experiment of Sec. 5.1 at n = 50 (the rows of Table 1 that local
+    inference up to n = 50 covers): every design search coupled with local MLE
+    of the lengthscale, one and two stages, over the 99 x 99 predictive grid.
+    Times cover the neighbour search, the designs, the fits and the
+    predictions of all 9801 locations (inputs resident on the GPU)."""
+    import torch
+    from scipy.stats import t as student_t
+
+    import paper_1409_0074_amd as lg
+    from paper_1409_0074_amd import workloads as W
+
+    w = W.paper2d()
+    d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
+    XX = torch.from_numpy(w.XX).cuda()
+    rows = [("ray_n50_stage2", W.SEARCH_RAY, 2, 1000, W.SCORING_PARTINV),
+            ("ext_n50_stage2", W.SEARCH_EXHAUSTIVE, 2, 1000, W.SCORING_CHOL),
+            ("ray_n50_stage1", W.SEARCH_RAY, 1, 1000, W.SCORING_PARTINV),
+            ("ext_n50_stage1", W.SEARCH_EXHAUSTIVE, 1, 1000, W.SCORING_CHOL),
+            ("nn_n50", W.SEARCH_NN, 1, 1000, W.SCORING_PARTINV),
+            ("ext_n50_cand2000_stage1", W.SEARCH_EXHAUSTIVE, 1, 2000, W.SCORING_PARTINV)]
+    out = {"workload": w.name.replace("_exhaustive", ""), "M": int(w.XX.shape[0]), "d0": w.params.d[0],
+           "g": w.params.g, "numrays": 1, "paper_secs_context": SEC51_PAPER_SECS,
+           "paper_right_table_secs_context": SEC51_PAPER_RIGHT, "rows": {}}
+    for name, search, mode, nc, scoring in rows:
+        prm = w.params.replace(search=search, numrays=1 if search == W.SEARCH_RAY else 0, ncand=nc,
+                               scoring=scoring if search == W.SEARCH_EXHAUSTIVE else W.SCORING_PARTINV)
+        d.predict_mle(XX[:256], prm, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            o = d.predict_mle(XX, prm, mode)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        mu, s2 = o["mean"].cpu().numpy(), o["s2"].cpu().numpy()
+        df = o["df"].cpu().numpy()
+        half = student_t.ppf(0.975, df) * np.sqrt(s2)
+        out["rows"][name] = {
+            "seconds": round(dt, 4), "pred_per_s": round(w.XX.shape[0] / dt, 1),
+            "rmse": float(np.sqrt(np.mean((mu - w.truth) ** 2))), "sd_mean": float(np.mean(np.sqrt(s2))),
+            "coverage95": float(np.mean(np.abs(w.truth - mu) <= half)),
+            "dhat_median": float(np.median(o["dhat"].cpu().numpy())),
+            "likelihood_evaluations_mean": float(o["iters"].float().mean().cpu()),
+            "status_nonzero": int((o["status"] != 0).sum().cpu())}
+    d.close()
+    return out
+
+
+def ray_sweep(w, steps: int, counts):
+    """Rays per greedy step R = 1..p on the 8-d workload (fixed d, the same
+    candidates): rate of the design search and accuracy against the truth,
+    beside the exhaustive search's (Sec. 5.3 reports no gain beyond p rays)."""
+    import torch
+
+    import paper_1409_0074_amd as lg
+    from paper_1409_0074_amd import workloads as W
+
+    d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
+    XX = torch.from_numpy(w.XX).cuda()
+    idx, _ = d.candidates(XX, w.params.ncand)
+    M = XX.shape[0]
+    out = {"workload": w.name.replace("_exhaustive", ""), "M": M, "rows": {}}
+    f64 = dict(dtype=torch.float64, device="cuda")
+    mean, s2, df = torch.empty(M, **f64), torch.empty(M, **f64), torch.empty(M, **f64)
+    status = torch.empty(M, dtype=torch.int32, device="cuda")
+    for R in counts:
+        prm = w.params.replace(search=W.SEARCH_RAY, numrays=R) if R else w.params.replace(scoring=W.SCORING_CHOL)
+        P = lg.make_params(prm)
+        lg.lagp_predict_candidates(d.handle, XX[:256], idx[:256], P, mean[:256], s2[:256], df[:256], None, None,
+                                   status[:256])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lg.lagp_predict_candidates(d.handle, XX, idx, P, mean, s2, df, None, None, status)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        mu = mean.cpu().numpy()
+        out["rows"][f"rays{R}" if R else "exhaustive"] = {
+            "design_ms": round(dt * 1e3, 3), "pred_per_s": round(M / dt, 1),
+            "rmse": float(np.sqrt(np.mean((mu - w.truth) ** 2))), "status_nonzero": int((status != 0).sum().cpu())}
+    d.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +295,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--no-sec51", action="store_true", help="skip the Sec. 5.1 2-d experiment (Table 1 rows)")
+    ap.add_argument("--no-ray-sweep", action="store_true", help="skip the rays-per-step sweep R = 1..p")
     ap.add_argument("--grid", action="store_true", help="also run the 2-d grid workload, FP64 and mixed")
     ap.add_argument("--grid-M", type=int, default=2000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -256,8 +351,8 @@ def main() -> int:
         step(dummy, sel_out=sel)
     torch.cuda.synchronize()
     ex_sel = sel.cpu().numpy().copy()
-    ex_mean = mean.cpu().numpy().copy()
     (t_knn, t_local), wall = time_steps(step, args.steps, 2)
+    ex_mean = mean.cpu().numpy().copy()  # (the last timed step's)
     ms_step = wall / args.steps
     value = M / (ms_step / 1e3)
     st = status.cpu().numpy()
@@ -328,10 +423,12 @@ def main() -> int:
                               "frac": round(p_tf / FP64_PEAK_TFLOPS, 4),
                               "work": f"sum_j 2 j^2 (ncand - j): {scoring_flops(prm.n0, prm.n, nc):.4g} "
                                       f"FLOP/location"}},
-        "identical_designs_vs_cholesky": float(np.mean(same)),
-        "mean_relerr_max_vs_cholesky": float(np.max(np.abs(pi_mean[same] - ex_mean[same]) /
-                                                    np.maximum(np.abs(ex_mean[same]), 1e-12), initial=0.0)),
     }
+    if args.warmup > 0:  # (the Cholesky form's designs come from its warm-up step)
+        result["partitioned_inverse"].update({
+            "identical_designs_vs_cholesky": float(np.mean(same)),
+            "mean_relerr_max_vs_cholesky": float(np.max(np.abs(pi_mean[same] - ex_mean[same]) /
+                                                        np.maximum(np.abs(ex_mean[same]), 1e-12), initial=0.0))})
 
     if not args.no_mle:
         # the paper's full local procedure (Sec. 5): local MLE of an isotropic
@@ -380,6 +477,11 @@ def main() -> int:
                          "rmse_ray_vs_exhaustive": float(np.sqrt(np.mean((ry_mean - ex_mean) ** 2)))}
 
     lg.lagp_design_destroy(design)
+    del X, y, XX, cand
+    if not args.no_ray_sweep:
+        result["ray_sweep"] = ray_sweep(w, args.ray_steps, [0] + list(range(1, w.X.shape[1] + 1)))
+    if not args.no_sec51:
+        result["sec51"] = sec51(args.ray_steps)
     if not args.no_serving:
         result["serving"] = serving(args.serving_requests)
     if args.grid:

@@ -200,9 +200,11 @@ int32_t lagp_predict_candidates(const lagp_design* design, const double* XX, int
  * second derivatives, kept inside a bracket that shrinks from [dmin, dmax]
  * (geometric bisection when a Newton step would leave it); the prediction
  * (Eqs. predgp, preds2 with n local points) is taken under the estimate
- * through the Cholesky factor of K.  Needs exhaustive search with
- * LAGP_SCORING_CHOL (so n <= 50), an isotropic lengthscale (d_len = 1) and
- * precision FP64.  cand_idx (nullable, device, M x ncand int32) gives the
+ * through the Cholesky factor of K.  The design search is any of the three
+ * (Sec. 5 couples each with local inference): exhaustive (either scoring),
+ * rays, or nearest neighbours (whose design does not depend on d, so its
+ * second stage repeats the first).  Needs n <= 50, an isotropic lengthscale
+ * (d_len = 1) and precision FP64.  cand_idx (nullable, device, M x ncand int32) gives the
  * candidate lists as lagp_candidates writes them; NULL searches them here.
  * Outputs (device): mean, s2, df (M); dhat (M) the estimate used; sel_idx
  * (nullable, M x n) the final local design; iters (nullable, M) likelihood

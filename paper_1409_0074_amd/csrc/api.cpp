@@ -236,6 +236,38 @@ int32_t lagp_candidates(const lagp_design* d, const double* XX, int64_t M, int32
 
 namespace lagp {
 
+// The search arguments every entry point shares: design, locations,
+// candidates and the method's parameters (workspace and outputs are the
+// caller's to fill in).
+lagp::LocalArgs local_args(const lagp_design* d, const lagp_params* P, int rays, const double* XX, int32_t M,
+                           const int32_t* cand) {
+  lagp::LocalArgs a{};
+  a.X = d->X;
+  a.y = d->y;
+  a.lo = d->lo;
+  a.hi = d->hi;
+  a.XX = XX;
+  a.cand = cand;
+  a.N = d->N;
+  a.M = M;
+  a.p = d->p;
+  a.n = P->n;
+  a.n0 = P->search == LAGP_SEARCH_NN ? P->n : P->n0;
+  a.ncand = P->ncand;
+  a.ncs = (P->ncand + 15) & ~15;
+  a.kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? (P->n + 3) / 4 * 4 : a.n0;  // exact tiles read whole chunks
+  a.numrays = rays;
+  a.search = P->search;
+  a.precision = P->precision;
+  a.rescore_k = P->rescore_k;
+  a.dlen = P->d_len;
+  a.brent_maxit = P->brent_maxit > 0 ? P->brent_maxit : 100;
+  a.brent_tol = P->brent_tol > 0.0 ? P->brent_tol : std::ldexp(1.0, -13);
+  a.g = P->g;
+  for (int q = 0; q < P->d_len; ++q) a.w[q] = 1.0 / P->d[q];
+  return a;
+}
+
 // Bytes run_predict allocates for M locations under a workspace cap, and the
 // per-location figure (kNN buffers when candidates are not given, the kernel
 // rows, k(x_c, x), the candidates' coordinates, the starting-inverse scratch
@@ -318,13 +350,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
       LAGP_HIP(launch_knn2(knn_args(d, XX + m0 * p, mc, nc, base + o_knn, chunk, base + o_sub,
                                     reinterpret_cast<int32_t*>(base + o_cand), nullptr),
                            s));
-    lagp::LocalArgs a{};
-    a.X = d->X;
-    a.y = d->y;
-    a.lo = d->lo;
-    a.hi = d->hi;
-    a.XX = XX + m0 * p;
-    a.cand = cand;
+    lagp::LocalArgs a = local_args(d, P, rays, XX + m0 * p, mc, cand);
     a.Kc = reinterpret_cast<double*>(base + o_kc);
     a.Kc32 = b_kc32 ? reinterpret_cast<float*>(base + o_kc32) : nullptr;
     a.kxc = reinterpret_cast<double*>(base + o_kxc);
@@ -336,23 +362,6 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.sel = sel_idx ? sel_idx + m0 * n : nullptr;
     a.diag = diag ? diag + m0 * (int64_t)(n - n0) * 2 : nullptr;
     a.status = status ? status + m0 : reinterpret_cast<int32_t*>(base + o_st);
-    a.N = d->N;
-    a.M = mc;
-    a.p = p;
-    a.n0 = n0;
-    a.n = n;
-    a.ncand = nc;
-    a.ncs = ncs;
-    a.kc_rows = kc_rows;
-    a.numrays = rays;
-    a.search = P->search;
-    a.precision = P->precision;
-    a.rescore_k = P->rescore_k;
-    a.dlen = P->d_len;
-    a.brent_maxit = P->brent_maxit > 0 ? P->brent_maxit : 100;
-    a.brent_tol = P->brent_tol > 0.0 ? P->brent_tol : std::ldexp(1.0, -13);
-    a.g = P->g;
-    for (int q = 0; q < P->d_len; ++q) a.w[q] = 1.0 / P->d[q];
     LAGP_HIP(chol ? lagp::launch_chol(a, s) : lagp::launch_local(a, s));
   }
   return LAGP_OK;
@@ -384,8 +393,10 @@ int32_t lagp_predict_candidates(const lagp_design* d, const double* XX, int64_t 
   return lagp::run_predict(d, XX, M, cand_idx, P, mean, s2, df, sel_idx, diag, status, stream, workspace_budget());
 }
 
-// Local MLE (mle.hip) around the Cholesky-form search (chol.hip): search
-// under d0, estimate, [search under the estimate, estimate again], predict.
+// Local MLE (mle.hip) around a design search (the Cholesky form of
+// chol.hip, or local.hip's exhaustive, ray or nearest-neighbour search):
+// search under d0, estimate, [search under the estimate, estimate again],
+// predict.
 int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
                          const lagp_params* P, const lagp_mle_params* mle, double* mean, double* s2, double* df,
                          double* dhat, int32_t* sel_idx, int32_t* iters, int32_t* status, void* stream) {
@@ -396,10 +407,10 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
   if (rc != LAGP_OK) return rc;
   if (!mle) return fail(LAGP_EINVAL, "mle is NULL");
   if (mle->mode != 1 && mle->mode != 2) return fail(LAGP_EINVAL, "mle->mode must be 1 or 2");
-  if (P->search != LAGP_SEARCH_EXHAUSTIVE || P->scoring != LAGP_SCORING_CHOL || P->precision != LAGP_PREC_FP64)
-    return fail(LAGP_EINVAL, "local MLE needs exhaustive search with LAGP_SCORING_CHOL in FP64");
+  if (P->precision != LAGP_PREC_FP64) return fail(LAGP_EINVAL, "local MLE runs in FP64 only");
   if (P->d_len != 1) return fail(LAGP_EINVAL, "local MLE estimates one isotropic lengthscale: d_len must be 1");
   const int p = d->p, n = P->n, nc = P->ncand;
+  const bool chol = P->scoring == LAGP_SCORING_CHOL;  // else k_local's search (any mode)
   const double d0 = P->d[0];
   const double dmin = mle->dmin > 0.0 ? mle->dmin : d0 / 1000.0;
   const double dmax = mle->dmax > 0.0 ? mle->dmax : 100.0 * d0;
@@ -408,6 +419,8 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
   if (!(dmin < dmax) || !std::isfinite(dmax)) return fail(LAGP_EINVAL, "need 0 < dmin < dmax (finite)");
   const int lds_max = max_lds_per_block();
   if (!lagp::mle_supported(n, p, (size_t)lds_max)) return fail(LAGP_EINVAL, "local MLE needs n <= 50");
+  if (!chol && lagp::local_lds_bytes(n, (nc + 15) & ~15, p, rays, false) > (size_t)lds_max)
+    return fail(LAGP_EINVAL, "local design too large for LDS (n, p, numrays)");
   if (M == 0) return LAGP_OK;
   if (!XX || !mean || !s2 || !df || !dhat) return fail(LAGP_EINVAL, "XX, mean, s2, df and dhat must not be NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -419,12 +432,16 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
   const size_t b_sel = sel_idx ? 0 : sizeof(int32_t) * (size_t)n;
   // stage scratch: status of each search, the stage-one estimate, flags and evaluations
   const size_t b_st = sizeof(int32_t) * 6, b_th = sizeof(double);
-  const size_t per = b_knn + b_cand + b_sel + b_st + b_th;
+  // k_local's per-location buffers (kernel rows, k(x_c, x), coordinates,
+  // starting-inverse scratch, status) for the ray and nearest-neighbour searches
+  const size_t b_loc = chol ? 0 : lagp::predict_per_location_bytes(d, P, true);
+  const size_t per = b_knn + b_cand + b_sel + b_st + b_th + b_loc;
   const int64_t chunk = std::min<int64_t>(M, std::max<int64_t>(lagp::KNN_QB, (int64_t)(workspace_budget() / per)));
   Workspace ws;
   ws.s = s;
   const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_sel = o_cand + al(b_cand * chunk),
-               o_st = o_sel + al(b_sel * chunk), o_th = o_st + al(b_st * chunk), o_sub = o_th + al(b_th * chunk),
+               o_st = o_sel + al(b_sel * chunk), o_th = o_st + al(b_st * chunk), o_loc = o_th + al(b_th * chunk),
+               o_sub = o_loc + al(b_loc * chunk) + 4 * 256,
                total = o_sub + (cand_in ? 0 : lagp::knn2_shared_bytes(d->N, p, nc));
   LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
   char* base = reinterpret_cast<char*>(ws.ptr);
@@ -441,31 +458,22 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
     int32_t* st_out = status ? status + m0 : stw + 4 * chunk;
     int32_t* it_out = iters ? iters + m0 : stw + 5 * chunk;
     double* th1 = reinterpret_cast<double*>(base + o_th);
-    lagp::LocalArgs a{};
-    a.X = d->X;
-    a.y = d->y;
-    a.lo = d->lo;
-    a.hi = d->hi;
-    a.XX = XX + m0 * p;
-    a.cand = cand;
+    lagp::LocalArgs a = lagp::local_args(d, P, rays, XX + m0 * p, mc, cand);
+    if (!chol) {  // [Kc: kc_rows x ncs][kxc: ncs][Xc: ncs x p][start scratch: 2 n0^2], per location
+      const size_t ncs = (size_t)a.ncs, o_kxc = al(sizeof(double) * a.kc_rows * ncs * chunk),
+                   o_xc = o_kxc + al(sizeof(double) * ncs * chunk), o_ch = o_xc + al(sizeof(double) * ncs * p * chunk);
+      a.Kc = reinterpret_cast<double*>(base + o_loc);
+      a.kxc = reinterpret_cast<double*>(base + o_loc + o_kxc);
+      a.Xc = reinterpret_cast<double*>(base + o_loc + o_xc);
+      a.chol = reinterpret_cast<double*>(base + o_loc + o_ch);
+    }
     a.mean = mean + m0;  // (overwritten by the prediction under the estimate)
     a.s2 = s2 + m0;
     a.df = df + m0;
     a.sel = sel;
     a.status = st1;
-    a.N = d->N;
-    a.M = mc;
-    a.p = p;
-    a.n0 = P->n0;
-    a.n = n;
-    a.ncand = nc;
-    a.ncs = (nc + 15) & ~15;
-    a.search = P->search;
-    a.precision = P->precision;
-    a.dlen = 1;
-    a.g = P->g;
-    a.w[0] = 1.0 / d0;
-    LAGP_HIP(lagp::launch_chol(a, s));
+    auto search = [&]() { return chol ? lagp::launch_chol(a, s) : lagp::launch_local(a, s); };
+    LAGP_HIP(search());
     lagp::MleArgs e{};
     e.X = d->X;
     e.y = d->y;
@@ -498,7 +506,7 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
     LAGP_HIP(lagp::launch_mle(e, s));
     a.dloc = th1;  // second stage: search under the estimate
     a.status = st2;
-    LAGP_HIP(lagp::launch_chol(a, s));
+    LAGP_HIP(search());
     e.theta0 = th1;
     e.status_in = st2;
     e.flags_prev = fl1;

@@ -112,6 +112,19 @@ __device__ __forceinline__ double corr(const double* a, const double* b, int p, 
   return gexp(-s);
 }
 
+// The same with the isotropic reciprocal lengthscale passed by value (a
+// location's own, or w[0]); the separable case reads w.
+__device__ __forceinline__ double corr(const double* a, const double* b, int p, double w0, const double* w,
+                                       int dlen) {
+  if (dlen == 1) return gexp(-(sqdist(a, b, p) * w0));
+  double s = 0.0;
+  for (int k = 0; k < p; ++k) {
+    const double t = a[k] - b[k];
+    s = __builtin_fma(t * t, w[k], s);
+  }
+  return gexp(-s);
+}
+
 // (d2, row) strict order used for the nearest-candidate lists.
 __device__ __forceinline__ bool key_less(double da, int ia, double db, int ib) {
   return da < db || (da == db && ia < ib);

@@ -51,6 +51,7 @@ struct Lds {
   double* gv;    // NP: g_j
   double* yJ;    // NP
   double* x;     // LAGP_MAX_DIM: the location
+  double w0;     // isotropic reciprocal lengthscale of this location (dlen = 1)
   double* xj;    // n x p: coordinates of the local design
   double* kzb;   // NW x RB x kzs: ray objective scratch, per wave and slot
   double* wvb;   // NW x RB x kzs
@@ -78,7 +79,7 @@ __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(
 // different LDS banks.
 struct LdsPlan {
   int NP, NR, LD, R, KZS;
-  size_t off[24];
+  size_t off[28];
   size_t bytes;
 };
 
@@ -200,7 +201,8 @@ __device__ __forceinline__ bool start_inverse(const LocalArgs& a, const Lds& L, 
 // Gaussian correlation with the dimension loop unrolled to PM >= p (same
 // arithmetic as corr(): t = u_k - v_k, first argument first).
 template <int PM>
-__device__ __forceinline__ double corr_pm(const double* u, const double* v, int p, const double* w, int dlen) {
+__device__ __forceinline__ double corr_pm(const double* u, const double* v, int p, double w0, const double* w,
+                                          int dlen) {
   double acc = 0.0;
   if (dlen == 1) {
 #pragma unroll
@@ -209,7 +211,7 @@ __device__ __forceinline__ double corr_pm(const double* u, const double* v, int 
         const double t = u[k] - v[k];
         acc = __builtin_fma(t, t, acc);
       }
-    return gexp(-(acc * w[0]));
+    return gexp(-(acc * w0));
   }
 #pragma unroll
   for (int k = 0; k < PM; ++k)
@@ -255,10 +257,10 @@ __device__ __forceinline__ void gather_candidates(const LocalArgs& a, const Lds&
         if (!live) r[u][k] = 0.0;
         if (k < p) Xc[(int64_t)c * p + k] = r[u][k];
       }
-      kxc[c] = live ? corr_pm<PM>(r[u], L.x, p, a.w, a.dlen) : 0.0;
+      kxc[c] = live ? corr_pm<PM>(r[u], L.x, p, L.w0, a.w, a.dlen) : 0.0;
       if (c < kcols)
         for (int i = 0; i < n0; ++i) {
-          const double kv = live ? corr_pm<PM>(L.xj + i * p, r[u], p, a.w, a.dlen) : 0.0;
+          const double kv = live ? corr_pm<PM>(L.xj + i * p, r[u], p, L.w0, a.w, a.dlen) : 0.0;
           Kc[(int64_t)i * ncs + c] = kv;
           if (Kc32) Kc32[(int64_t)i * ncs + c] = (float)kv;
         }
@@ -269,7 +271,7 @@ __device__ __forceinline__ void gather_candidates(const LocalArgs& a, const Lds&
 // New kernel row K(x_s, x_c) for every candidate from the gathered
 // coordinates (each thread reads back the rows it gathered).
 template <int PM>
-__device__ __forceinline__ void kernel_row(const LocalArgs& a, const double* xs, const double* Xc, double* row,
+__device__ __forceinline__ void kernel_row(const LocalArgs& a, double w0, const double* xs, const double* Xc, double* row,
                                            float* row32) {
   constexpr int GATHER = gather_width<PM>();
   const int p = a.p, nc = a.ncand, ncs = a.ncs, nt = blockDim.x;
@@ -288,7 +290,7 @@ __device__ __forceinline__ void kernel_row(const LocalArgs& a, const double* xs,
     for (int u = 0; u < GATHER; ++u) {
       const int c = c0 + u * nt;
       if (c >= ncs) break;
-      const double kv = c < nc ? corr_pm<PM>(s, r[u], p, a.w, a.dlen) : 0.0;
+      const double kv = c < nc ? corr_pm<PM>(s, r[u], p, w0, a.w, a.dlen) : 0.0;
       row[c] = kv;
       if (row32) row32[c] = (float)kv;
     }
@@ -664,7 +666,7 @@ __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, in
   const double* xs = L.xj + j * p;
   // K(x_J, x_s): the same arguments, in the same order, as the stored rows
   // K(x_{J_i}, x_c) (design point first), hence the same bits
-  for (int i = tid; i < j; i += blockDim.x) L.col[i] = corr(L.xj + i * p, xs, p, a.w, a.dlen);
+  for (int i = tid; i < j; i += blockDim.x) L.col[i] = corr(L.xj + i * p, xs, p, L.w0, a.w, a.dlen);
   __syncthreads();
   // Kinv is exactly symmetric (every update adds g_i g_k v with
   // g_i g_k == g_k g_i), so thread i reads column i: same values, same
@@ -702,10 +704,10 @@ __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, in
     double* row = Kc + (int64_t)j * ncs;
     float* row32 = Kc32 ? Kc32 + (int64_t)j * ncs : nullptr;
     if (p <= 8) {
-      kernel_row<8>(a, xs, Xc, row, row32);
+      kernel_row<8>(a, L.w0, xs, Xc, row, row32);
     } else {
       for (int c = tid; c < ncs; c += blockDim.x) {
-        const double kv = c < a.ncand ? corr(xs, Xc + (int64_t)c * p, p, a.w, a.dlen) : 0.0;
+        const double kv = c < a.ncand ? corr(xs, Xc + (int64_t)c * p, p, L.w0, a.w, a.dlen) : 0.0;
         row[c] = kv;
         if (row32) row32[c] = (float)kv;
       }
@@ -721,7 +723,8 @@ __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, in
 // Gaussian correlation of two vectors unrolled to the compile-time dimension
 // P (0: runtime p), first argument first (same arithmetic as corr()).
 template <int P>
-__device__ __forceinline__ double corr_regs(const double* u, const double* v, int p, const double* w, int dlen) {
+__device__ __forceinline__ double corr_regs(const double* u, const double* v, int p, double w0, const double* w,
+                                            int dlen) {
   constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
   double acc = 0.0;
   if (dlen == 1) {
@@ -731,7 +734,7 @@ __device__ __forceinline__ double corr_regs(const double* u, const double* v, in
         const double t = u[k] - v[k];
         acc = __builtin_fma(t, t, acc);
       }
-    return gexp(-(acc * w[0]));
+    return gexp(-(acc * w0));
   }
 #pragma unroll
   for (int k = 0; k < PM; ++k)
@@ -783,15 +786,15 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
     double z[PM];
     ray_point<P>(L, p, rids[t], ss[t], at_start, z);
     double* kz = L.kzb + (wave * RB + t) * L.kzs;
-    if (lane < j) kz[lane] = corr_regs<P>(xi, z, p, a.w, a.dlen);
-    if (lane + 64 < j) kz[lane + 64] = corr_regs<P>(L.xj + (lane + 64) * p, z, p, a.w, a.dlen);
+    if (lane < j) kz[lane] = corr_regs<P>(xi, z, p, L.w0, a.w, a.dlen);
+    if (lane + 64 < j) kz[lane + 64] = corr_regs<P>(L.xj + (lane + 64) * p, z, p, L.w0, a.w, a.dlen);
   }
   // K(z_t, x) on lane t
   double kzx = 0.0;
   if (lane < RB && ev) {
     double z[PM];
     ray_point<P>(L, p, rid, s, at_start, z);
-    kzx = corr_regs<P>(z, L.x, p, a.w, a.dlen);
+    kzx = corr_regs<P>(z, L.x, p, L.w0, a.w, a.dlen);
   }
   wave_sync();
   const int nb = (j + 7) >> 3;
@@ -1095,12 +1098,26 @@ void k_local(LocalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 0;
   const LdsPlan plan = plan_lds(a.n, a.ncs, a.p, R, MODE == MODE_MIXED);
-  const Lds L = carve(smem, plan);
+  Lds L = carve(smem, plan);
   const int LD = plan.LD;
   const int tid = threadIdx.x;
   const int m = blockIdx.x;
   const int p = a.p, n = a.n, nc = a.ncand, ncs = a.ncs;
   const int n0 = (a.search == LAGP_SEARCH_NN) ? n : a.n0;
+  // a per-location lengthscale (isotropic) replaces the common one; a
+  // location without a usable one (a failed earlier stage) is left alone
+  const double dl = a.dloc ? a.dloc[m] : 1.0;
+  if (!(dl > 0.0)) {
+    if (tid == 0) a.status[m] = 0;
+    return;
+  }
+  {  // uniform over the workgroup: held in scalar registers
+    const double w0 = a.dloc ? 1.0 / dl : a.w[0];
+    const unsigned long long b = (unsigned long long)__double_as_longlong(w0);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    L.w0 = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  }
   const int32_t* C = a.cand + (int64_t)m * nc;
   double* Kc = a.Kc + (int64_t)m * a.kc_rows * ncs;
   float* Kc32 = a.Kc32 ? a.Kc32 + (int64_t)m * a.kc_rows * ncs : nullptr;

@@ -110,6 +110,28 @@ def test_uniform8d_full_size_two_stage_mle_sampled(lg):
         assert np.array_equal(g[k][idx], o[k]), k
 
 
+@pytest.mark.parametrize("search,mode", [(W.SEARCH_RAY, 2), (W.SEARCH_EXHAUSTIVE, 2), (W.SEARCH_NN, 1)])
+def test_sec51_full_size_mle_sampled(lg, search, mode):
+    """The Sec. 5.1 experiment as the benchmark runs it: the 201 x 201 grid
+    design, all 9801 locations of the 99 x 99 predictive grid, n = 50, local
+    MLE; 16 sampled locations recomputed by the oracle, bit for bit."""
+    import torch
+
+    w = W.paper2d(search=search)
+    d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
+    try:
+        out = d.predict_mle(torch.from_numpy(w.XX), w.params, mode)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+    finally:
+        d.close()
+    assert np.all(np.isfinite(g["mean"])) and np.all(g["s2"] > 0)
+    idx = _sample(w.XX.shape[0], 16, 511 + search)
+    o = oracle.predict_mle(w.X, w.y, w.XX[idx], w.params, mode)
+    for k in ("sel", "dhat", "iters", "status", "mean", "s2"):
+        assert np.array_equal(g[k][idx], o[k]), k
+
+
 def test_grid2d_full_size_sampled(lg):
     """1000 x 1000 grid design, n = 100, N' = 4000, the first 2000 locations
     through lagp_predict (as the benchmark's grid leg), 6 sampled locations

@@ -71,6 +71,34 @@ def test_mle_uniform8d(lg, mode):
     _exact(lg, w, w.params, mode)
 
 
+@pytest.mark.parametrize("search,numrays", [(W.SEARCH_RAY, 1), (W.SEARCH_RAY, 2), (W.SEARCH_NN, 0)])
+@pytest.mark.parametrize("mode", [1, 2])
+def test_mle_rays_and_nearest_neighbours(lg, search, numrays, mode):
+    """The other two design searches under local inference (Sec. 5):
+    rays (k_local's lockstep Brent searches under each location's own
+    estimate at stage two) and the nearest-neighbour design."""
+    w = W.tiny_2d(M=16)
+    g, _ = _exact(lg, w, w.params.replace(search=search, numrays=numrays), mode)
+    assert np.all(np.isfinite(g["mean"]))
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_mle_partitioned_inverse_scoring(lg, mode):
+    """Exhaustive search scored by partitioned-inverse updates (k_local,
+    any N' the kernel takes) under local inference."""
+    w = W.tiny_2d(M=12)
+    _exact(lg, w, w.params.replace(ncand=1200), mode)
+
+
+def test_mle_rays_uniform8d(lg):
+    """p = 8, n = 50, N' = 1000, 8 rays, two stages."""
+    rng = np.random.default_rng(212)
+    X = rng.random((60000, 8))
+    w = W.Workload("u8r", X, W.f_sines8(X), rng.random((8, 8)),
+                   W.Params(n0=6, n=50, ncand=1000, search=W.SEARCH_RAY, numrays=8, d=(0.5,), g=1e-6))
+    _exact(lg, w, w.params, 2)
+
+
 def test_mle_bounds_and_budget(lg):
     """A narrow range pins estimates to a bound; a tiny budget stops the
     iteration: both reported as the oracle reports them."""
@@ -88,12 +116,15 @@ def test_mle_shapes(lg, p, n, n0, ncand):
     _exact(lg, w, w.params, 2)
 
 
-def test_mle_singular_start(lg):
+@pytest.mark.parametrize("search", [W.SEARCH_EXHAUSTIVE, W.SEARCH_RAY])
+def test_mle_singular_start(lg, search):
     """Duplicated points and g = 0: the first search fails; NaN, NOTPD and
-    the lengthscale searched under, as in the oracle."""
+    the lengthscale searched under, as in the oracle (the second stage
+    skips those locations in both search kernels)."""
     X = np.repeat(np.random.default_rng(107).random((300, 2)), 2, axis=0)
-    w = W.Workload("dup", X, W.f_bump2(X), X[:4].copy(), W.Params(n0=4, n=10, ncand=40, d=(0.1,), g=0.0,
-                                                                 scoring=CHOL))
+    prm = W.Params(n0=4, n=10, ncand=40, d=(0.1,), g=0.0, search=search, numrays=2,
+                   scoring=CHOL if search == W.SEARCH_EXHAUSTIVE else W.SCORING_PARTINV)
+    w = W.Workload("dup", X, W.f_bump2(X), X[:4].copy(), prm)
     g, _ = _exact(lg, w, w.params, 2)
     assert np.all(np.isnan(g["mean"])) and np.all(g["status"] & lg.LAGP_STATUS_NOTPD)
 
@@ -130,7 +161,8 @@ def test_mle_rejects_unsupported(lg):
     out = [torch.empty(2, dtype=torch.float64, device="cuda") for _ in range(4)]
     ok = w.params.replace(scoring=CHOL)
     bad = [(ok, lg.make_mle_params(3)), (ok.replace(d=(0.1, 0.2)), lg.make_mle_params(1)),
-           (w.params, lg.make_mle_params(1)), (ok, lg.make_mle_params(1, dmin=1.0, dmax=0.5)),
+           (ok.replace(scoring=W.SCORING_PARTINV, precision=W.PREC_MIXED), lg.make_mle_params(1)),
+           (ok, lg.make_mle_params(1, dmin=1.0, dmax=0.5)),
            (ok.replace(n=51), lg.make_mle_params(1))]
     for prm, q in bad:
         with pytest.raises(lg.LagpError) as e:
