@@ -33,15 +33,18 @@ namespace {
 constexpr int MLE_THREADS = 256;
 constexpr int MLE_NMAX = 50;
 static_assert(MLE_NMAX <= 64, "the factor's trailing updates take one lane per column");
+static_assert(MLE_THREADS == 256, "the per-row loops deal rows to exactly 4 waves");
+
+// Row handled by thread tid in the per-row loops: rows dealt to the
+// four waves in turn (i = 4 lane + wave), so all four SIMDs share them.
+__device__ __forceinline__ int mle_row_of_thread(int tid) { return 4 * (tid & 63) + (tid >> 6); }
 
 struct MleLds {
   double* XJ;   // n x p
-  double* D;    // n x LD: squared distances
-  double* E;    // n x LD: exp(-a)
-  double* Kd;   // n x LD
-  double* Lm;   // n x LD: K, then its Cholesky factor (lower triangle)
+  double* D;    // n (n+1) / 2: squared distances, packed lower triangle (exactly symmetric)
+  double* E;    // n (n+1) / 2: exp(-a), packed likewise
+  double* Lm;   // n x LD: K, then its Cholesky factor (lower triangle), then K^{-1}
   double* Li;   // n x LD: L^{-1} (lower), then K^{-1} Kd
-  double* Ki;   // n x LD
   double* y;    // n
   double* al;   // n: K^{-1} y
   double* be;   // n: Kd alpha
@@ -53,9 +56,15 @@ struct MleLds {
   double* sc;   // 12 scalars
 };
 
+// Position of (i, k) in a packed symmetric matrix (lower triangle by rows).
+__device__ __forceinline__ int sym(int i, int k) { return i >= k ? i * (i + 1) / 2 + k : k * (k + 1) / 2 + i; }
+
+// The two packed triangles and two full matrices stay under 80 KB at
+// n = 50, so two workgroups share a CU.
 __host__ __device__ inline size_t mle_lds_bytes_n(int n, int p) {
   const int LD = n + 1;
-  return sizeof(double) * ((size_t)n * p + 6 * (size_t)n * LD + 9 * (size_t)n + LAGP_MAX_DIM + 12);
+  return sizeof(double) * ((size_t)n * p + (size_t)n * (n + 1) + 2 * (size_t)n * LD + 9 * (size_t)n +
+                           LAGP_MAX_DIM + 12);
 }
 
 __device__ inline MleLds mle_carve(unsigned char* s, int n, int p) {
@@ -63,12 +72,10 @@ __device__ inline MleLds mle_carve(unsigned char* s, int n, int p) {
   MleLds L;
   double* d = reinterpret_cast<double*>(s);
   L.XJ = d; d += n * p;
-  L.D = d; d += n * LD;
-  L.E = d; d += n * LD;
-  L.Kd = d; d += n * LD;
+  L.D = d; d += n * (n + 1) / 2;
+  L.E = d; d += n * (n + 1) / 2;
   L.Lm = d; d += n * LD;
   L.Li = d; d += n * LD;
-  L.Ki = d; d += n * LD;
   L.y = d; d += n;
   L.al = d; d += n;
   L.be = d; d += n;
@@ -111,17 +118,19 @@ __device__ bool mle_cholesky(double* Lm, double* dg, double* Li, int n, int LD) 
     }
     if (tid == 0) dg[m] = piv;
     __syncthreads();
-    // trailing updates, one row of the block per wave at a time (n <= 64:
-    // a lane per column): (i, k) with m < k <= i, and (i, c) with c <= m
-    const int lane = tid & 63, nwv = T >> 6;
-    for (int r = tid >> 6; r < nl; r += nwv) {
+    // trailing updates, rows dealt to the waves in turn (n <= 64: a lane per
+    // column): (i, k) with m < k <= i, and (i, c) with c <= m.  Column m of
+    // L and row m of L^{-1} are not written here, so each lane reads its
+    // L_km and (L^{-1})_mc once.
+    const int lane = tid & 63, wv = tid >> 6, nwv = T >> 6;
+    const int k = m + 1 + lane;
+    const double lkm = lane < nl ? Lm[k * LD + m] : 0.0;
+    const double lmc = lane < nr ? Li[m * LD + lane] : 0.0;
+    for (int r = wv; r < nl; r += nwv) {
       const int i = m + 1 + r;
       const double lim = Lm[i * LD + m];
-      if (lane <= r) {
-        const int k = m + 1 + lane;
-        Lm[i * LD + k] = __builtin_fma(-lim, Lm[k * LD + m], Lm[i * LD + k]);
-      }
-      if (lane < nr) Li[i * LD + lane] = __builtin_fma(-lim, Li[m * LD + lane], Li[i * LD + lane]);
+      if (lane <= r) Lm[i * LD + k] = __builtin_fma(-lim, lkm, Lm[i * LD + k]);
+      if (lane < nr) Li[i * LD + lane] = __builtin_fma(-lim, lmc, Li[i * LD + lane]);
     }
     __syncthreads();
   }
@@ -166,6 +175,17 @@ __device__ __forceinline__ double mle_dot(const double* a, const double* b, int 
   return s;
 }
 
+// dK/dtheta and d2K/dtheta2 at (i, k) from the packed D and E (the same
+// expressions, hence the same values, wherever they are needed).
+__device__ __forceinline__ double mle_kd(const MleLds& L, int s, double w) {
+  const double a = L.D[s] * w;
+  return (L.E[s] * a) * w;
+}
+__device__ __forceinline__ double mle_kdd(const MleLds& L, int s, double w, double ww) {
+  const double a = L.D[s] * w;
+  return (L.E[s] * (a * a - 2.0 * a)) * ww;
+}
+
 // l' and l'' at theta (all threads; results in sc[0], sc[1]; returns false
 // if K is not positive definite).
 __device__ bool mle_eval(const MleLds& L, int n, double g, double theta) {
@@ -173,59 +193,62 @@ __device__ bool mle_eval(const MleLds& L, int n, double g, double theta) {
   const double w = 1.0 / theta;
   for (int t = tid; t < n * n; t += T) {
     const int i = t / n, k = t % n;
-    const double a = L.D[i * LD + k] * w;
-    const double e = gexp(-a);
-    L.E[i * LD + k] = e;
-    L.Lm[i * LD + k] = e + (i == k ? g : 0.0);
-    L.Kd[i * LD + k] = (e * a) * w;
+    if (k <= i) {  // the factorisation reads the lower triangle only
+      const int s = sym(i, k);
+      const double e = gexp(-(L.D[s] * w));
+      L.E[s] = e;
+      L.Lm[i * LD + k] = e + (i == k ? g : 0.0);
+    }
     L.Li[i * LD + k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
   if (!mle_cholesky(L.Lm, L.dg, L.Li, n, LD)) return false;
   // K^{-1} = L^{-T} L^{-1}: (K^{-1})_ik = sum_{m >= max(i,k)} (L^{-1})_mi (L^{-1})_mk,
-  // the terms below max(i,k) being exact zeros of the lower triangular factor
+  // the terms below max(i,k) being exact zeros of the lower triangular
+  // factor; written over the factor, which is no longer needed
   {
     const double* Li = L.Li;
-    double* Ki = L.Ki;
+    double* Ki = L.Lm;
     mle_gemm(
         n, [=](int i, int k) { return Li[k * LD + i]; }, [=](int k, int j) { return Li[k * LD + j]; },
         [=](int i, int j, double v) { Ki[i * LD + j] = v; });
   }
   __syncthreads();
-  for (int i = tid; i < n; i += T) L.al[i] = mle_dot(L.Ki + i * LD, L.y, n);
+  const double* Ki = L.Lm;
+  const int ri = mle_row_of_thread(tid);
+  if (ri < n) L.al[ri] = mle_dot(Ki + ri * LD, L.y, n);
   __syncthreads();
   const double ww = w * w;
-  for (int i = tid; i < n; i += T) {
+  if (ri < n) {
+    const int i = ri;
     double b = 0.0, d = 0.0;
     for (int k = 0; k < n; ++k) {
-      b = __builtin_fma(L.Kd[i * LD + k], L.al[k], b);
-      const double a = L.D[i * LD + k] * w;
-      const double kdd = (L.E[i * LD + k] * (a * a - 2.0 * a)) * ww;
-      d = __builtin_fma(kdd, L.al[k], d);
+      const int s = sym(i, k);
+      b = __builtin_fma(mle_kd(L, s, w), L.al[k], b);
+      d = __builtin_fma(mle_kdd(L, s, w, ww), L.al[k], d);
     }
     L.be[i] = b;
     L.de[i] = d;
   }
   __syncthreads();
-  for (int i = tid; i < n; i += T) L.ga[i] = mle_dot(L.Ki + i * LD, L.be, n);
+  if (ri < n) L.ga[ri] = mle_dot(Ki + ri * LD, L.be, n);
   // P = K^{-1} Kd into the L^{-1} buffer (no longer needed)
   {
-    const double* Ki = L.Ki;
-    const double* Kd = L.Kd;
     double* P = L.Li;
+    const MleLds& LL = L;
     mle_gemm(
-        n, [=](int i, int k) { return Ki[i * LD + k]; }, [=](int k, int j) { return Kd[k * LD + j]; },
+        n, [=](int i, int k) { return Ki[i * LD + k]; }, [&](int k, int j) { return mle_kd(LL, sym(k, j), w); },
         [=](int i, int j, double v) { P[i * LD + j] = v; });
   }
   __syncthreads();
-  for (int i = tid; i < n; i += T) {
+  if (ri < n) {
+    const int i = ri;
     double r1 = 0.0, r2 = 0.0, r3 = 0.0;
     for (int k = 0; k < n; ++k) {
-      const double kik = L.Ki[i * LD + k];
-      r1 = __builtin_fma(kik, L.Kd[k * LD + i], r1);
-      const double a = L.D[k * LD + i] * w;
-      const double kdd = (L.E[k * LD + i] * (a * a - 2.0 * a)) * ww;
-      r2 = __builtin_fma(kik, kdd, r2);
+      const double kik = Ki[i * LD + k];
+      const int s = sym(k, i);
+      r1 = __builtin_fma(kik, mle_kd(L, s, w), r1);
+      r2 = __builtin_fma(kik, mle_kdd(L, s, w, ww), r2);
       r3 = __builtin_fma(L.Li[i * LD + k], L.Li[k * LD + i], r3);
     }
     L.r[i] = r1;
@@ -293,7 +316,7 @@ __global__ __launch_bounds__(MLE_THREADS) void k_mle(MleArgs a) {
   __syncthreads();
   for (int t = tid; t < n * n; t += T) {
     const int i = t / n, k = t % n;
-    L.D[i * LD + k] = sqdist(L.XJ + i * p, L.XJ + k * p, p);
+    if (k <= i) L.D[sym(i, k)] = sqdist(L.XJ + i * p, L.XJ + k * p, p);
   }
   __syncthreads();
 
@@ -338,7 +361,7 @@ __global__ __launch_bounds__(MLE_THREADS) void k_mle(MleArgs a) {
     const double w = 1.0 / theta;
     for (int t = tid; t < n * n; t += T) {
       const int i = t / n, k = t % n;
-      L.Lm[i * LD + k] = gexp(-(L.D[i * LD + k] * w)) + (i == k ? a.g : 0.0);
+      if (k <= i) L.Lm[i * LD + k] = gexp(-(L.D[sym(i, k)] * w)) + (i == k ? a.g : 0.0);
     }
     __syncthreads();
     const bool pd = mle_cholesky(L.Lm, L.dg, nullptr, n, LD);
