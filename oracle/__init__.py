@@ -86,6 +86,11 @@ def lib():
         L.orc_mle_fit.argtypes = [i32, i32, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.orc_mle_fit.restype = ctypes.c_double
+        L.orc_sep_eval.argtypes = [i32, i32, _dp, _dp, ctypes.c_double, _dp, i32, _dp]
+        L.orc_sep_eval.restype = ctypes.c_int
+        L.orc_sep_fit.argtypes = [i32, i32, _dp, _dp, ctypes.c_double, _dp, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, i32, i32, ctypes.POINTER(i32)]
+        L.orc_sep_fit.restype = ctypes.c_int
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
@@ -208,6 +213,32 @@ def mle_fit(XJ, yJ, g: float, theta0: float, dmin: float, dmax: float, tol: floa
     t = lib().orc_mle_fit(XJ.shape[0], XJ.shape[1], _p(XJ), _p(yJ), g, theta0, dmin, dmax, tol, maxit,
                           ctypes.byref(it), ctypes.byref(fl))
     return t, it.value, fl.value
+
+
+def sep_eval(XS, yS, g: float, theta, k: int):
+    """(l, dl/dtheta_k, d2l/dtheta_k^2) of the separable likelihood, or None
+    if K is not positive definite."""
+    XS, yS = _f64(XS), _f64(yS)
+    th = _f64(np.atleast_1d(theta)).copy()
+    out = np.empty(3)
+    rc = lib().orc_sep_eval(XS.shape[0], XS.shape[1], _p(XS), _p(yS), g, _p(th), int(k), _p(out))
+    if rc == -2:
+        raise ValueError("orc_sep_eval: bad arguments")
+    return None if rc != 0 else tuple(out)
+
+
+def sep_fit(XS, yS, g: float, theta0, dmin: float, dmax: float, tol: float = 1e-8, maxit: int = 100,
+            maxsweep: int = 20):
+    """Global separable lengthscales by coordinate-wise Newton sweeps:
+    (theta_hat (p,), evaluations, flags)."""
+    XS, yS = _f64(XS), _f64(yS)
+    th = _f64(np.broadcast_to(np.atleast_1d(theta0), (XS.shape[1],))).copy()
+    it = ctypes.c_int()
+    fl = lib().orc_sep_fit(XS.shape[0], XS.shape[1], _p(XS), _p(yS), g, _p(th), dmin, dmax, tol, maxit, maxsweep,
+                           ctypes.byref(it))
+    if fl < 0:
+        raise ValueError(f"orc_sep_fit failed: {fl}")
+    return th, it.value, fl
 
 
 def brent_min(f, lo: float, hi: float, tol: float = 2.0 ** -13, maxit: int = 100):

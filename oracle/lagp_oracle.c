@@ -842,13 +842,13 @@ static void bbox(const double *X, int64_t N, int p, double *lo, double *hi)
  * fused multiply-add per term; a trace is the in-order sum of its row sums.
  * ws: 8 n^2 + 4 n doubles.  Returns 0, or -1 if K is not positive definite.
  */
+static int mle_eval_tail(int n, const double *y, double *ws, double *l, double *d1, double *d2);
+
 static int mle_eval(int n, const double *D, const double *y, double g, double theta, double *ws, double *l,
                     double *d1, double *d2)
 {
     const double w = 1.0 / theta;
-    double *E = ws, *K = E + n * n, *Kd = K + n * n, *Kdd = Kd + n * n, *Ki = Kdd + n * n, *P = Ki + n * n;
-    double *work = P + n * n; /* 2 n^2: L, then L^{-1} */
-    double *al = work + 2 * n * n, *be = al + n, *ga = be + n, *de = ga + n;
+    double *E = ws, *K = E + n * n, *Kd = K + n * n, *Kdd = Kd + n * n;
     for (int i = 0; i < n; i++)
         for (int k = 0; k < n; k++) {
             const double a = D[i * n + k] * w;
@@ -858,6 +858,16 @@ static int mle_eval(int n, const double *D, const double *y, double g, double th
             Kd[i * n + k] = (e * a) * w;
             Kdd[i * n + k] = (e * (a * a - 2.0 * a)) * (w * w);
         }
+    return mle_eval_tail(n, y, ws, l, d1, d2);
+}
+
+/* The rest of an evaluation, from K, Kd and Kdd in ws (laid out as in
+ * mle_eval): K^{-1}, the vectors, P = K^{-1} Kd, the traces, l, l', l''. */
+static int mle_eval_tail(int n, const double *y, double *ws, double *l, double *d1, double *d2)
+{
+    double *E = ws, *K = E + n * n, *Kd = K + n * n, *Kdd = Kd + n * n, *Ki = Kdd + n * n, *P = Ki + n * n;
+    double *work = P + n * n; /* 2 n^2: L, then L^{-1} */
+    double *al = work + 2 * n * n, *be = al + n, *ga = be + n, *de = ga + n;
     if (spd_inverse(K, n, Ki, work) != 0) return -1;
     double logdet = 0.0; /* log|K| / 2 = sum_i log L_ii */
     for (int i = 0; i < n; i++) logdet += log(work[i * n + i]);
@@ -906,8 +916,10 @@ static int mle_eval(int n, const double *D, const double *y, double g, double th
  * method only as Newton-like maximisation of the local posterior; reading:
  * a flat prior on theta (the likelihood itself).
  */
-static double mle_fit(int n, const double *D, const double *y, double g, double theta0, double dmin, double dmax,
-                      double tol, int maxit, double *ws, int *iters, int *flags)
+typedef int (*eval1_fn)(void *ctx, double theta, double *l, double *d1, double *d2);
+
+static double newton_1d(eval1_fn f, void *ctx, double theta0, double dmin, double dmax, double tol, int maxit,
+                        int *iters, int *flags)
 {
     double lo = dmin, hi = dmax;
     double theta = theta0 < lo ? lo : (theta0 > hi ? hi : theta0);
@@ -915,7 +927,7 @@ static double mle_fit(int n, const double *D, const double *y, double g, double 
     *flags = 0;
     while (it < maxit) {
         double l, d1, d2;
-        const int bad = mle_eval(n, D, y, g, theta, ws, &l, &d1, &d2) != 0;
+        const int bad = f(ctx, theta, &l, &d1, &d2) != 0;
         it++;
         if (bad) {
             *flags |= ORC_STATUS_MLE_NOTPD;
@@ -941,6 +953,26 @@ static double mle_fit(int n, const double *D, const double *y, double g, double 
     if (theta <= dmin * (1.0 + tol) || theta >= dmax * (1.0 - tol)) *flags |= ORC_STATUS_MLE_BOUND;
     *iters = it;
     return theta;
+}
+
+typedef struct {
+    int n;
+    const double *D, *y;
+    double g;
+    double *ws;
+} iso_ctx;
+
+static int iso_eval1(void *vp, double theta, double *l, double *d1, double *d2)
+{
+    const iso_ctx *c = (const iso_ctx *)vp;
+    return mle_eval(c->n, c->D, c->y, c->g, theta, c->ws, l, d1, d2);
+}
+
+static double mle_fit(int n, const double *D, const double *y, double g, double theta0, double dmin, double dmax,
+                      double tol, int maxit, double *ws, int *iters, int *flags)
+{
+    iso_ctx c = {n, D, y, g, ws};
+    return newton_1d(iso_eval1, &c, theta0, dmin, dmax, tol, maxit, iters, flags);
 }
 
 /* Squared distances of the n design points (coordinates XJ, n x p). */
@@ -1057,6 +1089,96 @@ out:
     free(D);
     free(ws);
     return status;
+}
+
+/* ---------------------------------------------------------------- O9 ---- */
+
+/*
+ * Global separable lengthscales from a data subset, for pre-scaling the
+ * inputs (Sec. 5.3: inputs divided by the square roots of global
+ * lengthscales estimated on subsets of the data).  The likelihood is O8's
+ * with the separable kernel of O1, K_ij = exp(-sum_k (x_ik - x_jk)^2 w_k)
+ * + g [i = j], w_k = 1/theta_k, the exponent summed in k order with one
+ * fused multiply-add per term.  Its derivatives in theta_k are O8's with
+ * a_ij = (x_ik - x_jk)^2 w_k: dK/dtheta_k = E a w_k, d2K/dtheta_k^2 =
+ * E (a^2 - 2a) w_k^2.  Reading (the paper names no optimiser for the
+ * global fit): coordinate-wise maximisation, each coordinate by O8's
+ * bracketed Newton iteration with the others fixed, in sweeps over
+ * k = 0..p-1 that repeat until a sweep moves no theta_k by more than
+ * tol theta_k, or maxsweep sweeps.  With p = 1 the exponent and derivatives
+ * are O8's exactly.
+ */
+static int sep_eval(int n, int p, const double *XS, const double *y, double g, const double *theta, int k,
+                    double *ws, double *l, double *d1, double *d2)
+{
+    double w[16];
+    for (int q = 0; q < p; q++) w[q] = 1.0 / theta[q];
+    const double wk = w[k];
+    double *E = ws, *K = E + n * n, *Kd = K + n * n, *Kdd = Kd + n * n;
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            double s = 0.0;
+            for (int q = 0; q < p; q++) {
+                const double t = XS[i * p + q] - XS[j * p + q];
+                s = fma(t * t, w[q], s);
+            }
+            const double e = oexp(-s);
+            const double tk = XS[i * p + k] - XS[j * p + k];
+            const double a = (tk * tk) * wk;
+            E[i * n + j] = e;
+            K[i * n + j] = e + (i == j ? g : 0.0);
+            Kd[i * n + j] = (e * a) * wk;
+            Kdd[i * n + j] = (e * (a * a - 2.0 * a)) * (wk * wk);
+        }
+    return mle_eval_tail(n, y, ws, l, d1, d2);
+}
+
+typedef struct {
+    int n, p, k;
+    const double *XS, *y;
+    double g;
+    double *theta, *ws;
+} sep_ctx;
+
+static int sep_eval1(void *vp, double t, double *l, double *d1, double *d2)
+{
+    sep_ctx *c = (sep_ctx *)vp;
+    const double keep = c->theta[c->k];
+    c->theta[c->k] = t;
+    const int r = sep_eval(c->n, c->p, c->XS, c->y, c->g, c->theta, c->k, c->ws, l, d1, d2);
+    c->theta[c->k] = keep;
+    return r;
+}
+
+/* theta: p starting values in, estimates out.  Returns the status flags
+ * (ORC_STATUS_MLE_*), or -2 if out of memory. */
+static int sep_fit(int n, int p, const double *XS, const double *y, double g, double *theta, double dmin,
+                   double dmax, double tol, int maxit, int maxsweep, int *iters)
+{
+    double *ws = malloc(sizeof(double) * (8 * (size_t)n * n + 4 * (size_t)n));
+    if (!ws) return -2;
+    int flags = 0, total = 0, conv = 0;
+    sep_ctx c = {n, p, 0, XS, y, g, theta, ws};
+    for (int sweep = 0; sweep < maxsweep && !conv; sweep++) {
+        int moved = 0;
+        for (int k = 0; k < p; k++) {
+            const double before = theta[k];
+            int it, fl;
+            c.k = k;
+            const double t = newton_1d(sep_eval1, &c, before, dmin, dmax, tol, maxit, &it, &fl);
+            theta[k] = t;
+            total += it;
+            flags |= fl & (ORC_STATUS_MLE_NOTPD | ORC_STATUS_MLE_MAXIT);
+            if (fabs(t - before) > tol * before) moved = 1;
+        }
+        if (!moved) conv = 1;
+    }
+    if (!conv) flags |= ORC_STATUS_MLE_MAXIT;
+    for (int k = 0; k < p; k++)
+        if (theta[k] <= dmin * (1.0 + tol) || theta[k] >= dmax * (1.0 - tol)) flags |= ORC_STATUS_MLE_BOUND;
+    *iters = total;
+    free(ws);
+    return flags;
 }
 
 /* ------------------------------------------------------------ exports --- */
@@ -1230,6 +1352,25 @@ double orc_mle_fit(int n, int p, const double *XJ, const double *yJ, double g, d
 }
 
 /* Exported for direct checks of the pieces. */
+/* O9 exports: one evaluation (l, l', l'' in theta_k) and the global fit. */
+int orc_sep_eval(int n, int p, const double *XS, const double *y, double g, const double *theta, int k,
+                 double *out3)
+{
+    if (n < 1 || p < 1 || p > 16 || k < 0 || k >= p) return -2;
+    double *ws = malloc(sizeof(double) * (8 * (size_t)n * n + 4 * (size_t)n));
+    if (!ws) return -2;
+    const int r = sep_eval(n, p, XS, y, g, theta, k, ws, out3, out3 + 1, out3 + 2);
+    free(ws);
+    return r;
+}
+
+int orc_sep_fit(int n, int p, const double *XS, const double *y, double g, double *theta, double dmin,
+                double dmax, double tol, int maxit, int maxsweep, int *iters)
+{
+    if (n < 1 || p < 1 || p > 16 || !(dmin > 0.0) || !(dmin < dmax) || maxit < 1 || maxsweep < 1) return -1;
+    return sep_fit(n, p, XS, y, g, theta, dmin, dmax, tol, maxit, maxsweep, iters);
+}
+
 double orc_exp(double x)
 {
     return oexp(x);

@@ -107,6 +107,14 @@ def f_sec51(X: np.ndarray) -> np.ndarray:
     return -w_sec51(X[:, 0]) * w_sec51(X[:, 1])
 
 
+def f_aniso8(X: np.ndarray) -> np.ndarray:
+    """Anisotropic 8-d response: sin(3 pi x1) + 2 x2^2 - x3 + 0.2 sin(2 pi x4);
+    x5..x8 do not enter (global lengthscales differ by orders of magnitude
+    across the inputs)."""
+    return (np.sin(3.0 * math.pi * X[:, 0]) + 2.0 * X[:, 1] ** 2 - X[:, 2]
+            + 0.2 * np.sin(2.0 * math.pi * X[:, 3]))
+
+
 def grid2(side: int) -> np.ndarray:
     """Regular side x side grid on [0,1]^2, x = i/(side-1); first axis slowest."""
     g = np.arange(side, dtype=np.float64) / (side - 1)
@@ -176,6 +184,24 @@ def paper2d(M: int | None = None, n: int = 50, search: int = SEARCH_EXHAUSTIVE, 
     mode = {SEARCH_EXHAUSTIVE: "exhaustive", SEARCH_RAY: f"ray{numrays}", SEARCH_NN: "nn"}[search]
     return Workload(f"sec51grid2d_N40401_M{XX.shape[0]}_n{n}_cand{ncand}_{mode}", X, f_sec51(X), XX, p,
                     f_sec51(XX))
+
+
+def aniso8d(M: int | None = None, N: int = 1_000_000) -> Workload:
+    """N = 1e6 iid uniform design on [0,1]^8 with the anisotropic response,
+    1e4 uniform predictive locations, isotropic d0 = 0.5 (refitted by local
+    MLE), g = 1e-6, n0 = 6, n = 50, 1000 nearest candidates.  Pre-scaling
+    fits global separable lengthscales on the subset ``aniso8d_subset``."""
+    X = _rng(5, 0).random((N, 8))
+    XX = _rng(5, 1).random((10_000, 8))
+    if M is not None:
+        XX = XX[:M]
+    p = Params(n0=6, n=50, ncand=1000, d=(0.5,), g=1e-6, scoring=SCORING_CHOL)
+    return Workload(f"aniso8d_N{N}_M{XX.shape[0]}_n50_cand1000", X, f_aniso8(X), XX, p, f_aniso8(XX))
+
+
+def aniso8d_subset(N: int, ns: int = 256) -> np.ndarray:
+    """Rows of the global fit's subset: ns distinct rows drawn uniformly."""
+    return np.sort(_rng(5, 3).choice(N, size=ns, replace=False))
 
 
 def serving4d(N: int = 2_000_000) -> Workload:

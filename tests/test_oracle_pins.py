@@ -827,3 +827,91 @@ def test_two_stage_with_rays_and_nearest_neighbours(orc, search, numrays):
             near = np.argsort(((w.X - w.XX[m]) ** 2).sum(axis=1), kind="stable")[:prm.n]
             assert set(near) == set(s1) == set(s2)
     assert np.all(np.isfinite(o2["mean"])) and np.all(o2["s2"] > 0)
+
+
+# ------------------------------------------- global separable fit (O9) ---
+
+def _np_sep_loglik(XS, yS, g, theta):
+    D = (XS[:, None, :] - XS[None, :, :]) ** 2
+    K = np.exp(-(D / np.asarray(theta)).sum(axis=2)) + g * np.eye(len(yS))
+    _, logdet = np.linalg.slogdet(K)
+    psi = yS @ np.linalg.solve(K, yS)
+    return -0.5 * logdet - 0.5 * len(yS) * np.log(psi)
+
+
+def _sep_case(seed, n=40, p=3):
+    rng = np.random.default_rng(seed)
+    XS = rng.random((n, p))
+    yS = np.sin(3.0 * XS[:, 0]) + 0.5 * XS[:, 1] ** 2 + (0.1 * XS[:, 2] if p > 2 else 0.0)
+    return XS, yS
+
+
+@pytest.mark.parametrize("seed", [61, 62])
+def test_sep_loglik_matches_numpy(orc, seed):
+    XS, yS = _sep_case(seed)
+    for theta in ([0.3, 1.0, 5.0], [0.05, 0.2, 0.7]):
+        l, _, _ = orc.sep_eval(XS, yS, 1e-4, theta, 0)
+        assert l == pytest.approx(_np_sep_loglik(XS, yS, 1e-4, theta), rel=1e-9, abs=1e-9)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_sep_derivatives_match_finite_differences(orc, k):
+    """dl/dtheta_k against central differences of numpy's log-likelihood,
+    d2l/dtheta_k^2 against central differences of the oracle's own first
+    derivative (a dropped term, a wrong sign or the wrong coordinate fails)."""
+    XS, yS = _sep_case(63)
+    g = 1e-4
+    theta = np.array([0.3, 1.0, 2.0])
+    h = 1e-5 * theta[k]
+    l, d1, d2 = orc.sep_eval(XS, yS, g, theta, k)
+    tp, tm = theta.copy(), theta.copy()
+    tp[k] += h
+    tm[k] -= h
+    fd1 = (_np_sep_loglik(XS, yS, g, tp) - _np_sep_loglik(XS, yS, g, tm)) / (2 * h)
+    assert d1 == pytest.approx(fd1, rel=1e-5, abs=1e-6 * abs(l) / theta[k])
+    fd2 = (orc.sep_eval(XS, yS, g, tp, k)[1] - orc.sep_eval(XS, yS, g, tm, k)[1]) / (2 * h)
+    assert d2 == pytest.approx(fd2, rel=1e-5, abs=1e-6 * abs(d1) / theta[k] + 1e-3)
+
+
+def test_sep_fit_with_one_input_is_the_isotropic_fit(orc):
+    """p = 1: the separable exponent and derivatives are the isotropic ones,
+    so the sweeps reach the isotropic estimate (to the Newton tolerance)."""
+    XS, yS = _mle_case(44, n=30, p=1)
+    t_iso, _, _ = orc.mle_fit(XS, yS, 1e-4, 0.1, 1e-3, 10.0, 1e-10, 200)
+    th, it, fl = orc.sep_fit(XS, yS, 1e-4, 0.1, 1e-3, 10.0, 1e-10, 200, 10)
+    assert fl == 0 and it > 1
+    assert th[0] == pytest.approx(t_iso, rel=1e-8)
+
+
+def test_sep_fit_is_a_maximiser(orc):
+    """An interior estimate is a stationary point of numpy's likelihood in
+    every coordinate, no worse than scipy's L-BFGS-B from the same start, and
+    not improved by perturbing any coordinate."""
+    from scipy.optimize import minimize
+
+    XS, yS = _sep_case(64, n=50, p=2)
+    g, lo, hi = 1e-4, 1e-3, 50.0
+    th, it, fl = orc.sep_fit(XS, yS, g, 0.5, lo, hi, 1e-10, 200, 50)
+    assert fl == 0
+    l0 = _np_sep_loglik(XS, yS, g, th)
+    for k in range(2):
+        _, d1, d2 = orc.sep_eval(XS, yS, g, th, k)
+        assert abs(d1) * th[k] <= 1e-6 * abs(l0) and d2 < 0
+        for f in (1 - 1e-3, 1 + 1e-3):
+            tq = th.copy()
+            tq[k] *= f
+            assert _np_sep_loglik(XS, yS, g, tq) < l0
+    r = minimize(lambda u: -_np_sep_loglik(XS, yS, g, np.exp(u)), np.log([0.5, 0.5]), method="L-BFGS-B",
+                 bounds=[(np.log(lo), np.log(hi))] * 2)
+    assert l0 >= -r.fun - 1e-7 * abs(l0)
+
+
+def test_sep_fit_sends_an_inert_input_to_the_upper_bound(orc):
+    """A response that ignores an input prefers an unbounded lengthscale for
+    it: the estimate sits at dmax and the status says so."""
+    rng = np.random.default_rng(65)
+    XS = rng.random((40, 2))
+    yS = np.sin(4.0 * XS[:, 0])
+    th, _, fl = orc.sep_fit(XS, yS, 1e-4, 0.5, 1e-3, 20.0, 1e-8, 100, 20)
+    assert fl & orc.STATUS_MLE_BOUND
+    assert th[1] == pytest.approx(20.0, rel=1e-6) and th[0] < 5.0
