@@ -217,6 +217,41 @@ int32_t lagp_predict_mle(const lagp_design* design, const double* XX, int64_t M,
                          double* df, double* dhat, int32_t* sel_idx, int32_t* iters, int32_t* status,
                          void* stream);
 
+/* ---- pre-scaling by global separable lengthscales (Sec. 5.3) ------------
+ *
+ * Local designs searched on inputs divided by the square roots of global
+ * lengthscales estimated on a subset of the data align ray searches with
+ * exhaustive ones on anisotropic responses (Sec. 5.3).  The two calls below
+ * give the fit and the scaling; the caller draws the subset, scales the
+ * design and the predictive locations with the same lengthscales, and runs
+ * the local path on the scaled inputs (an isotropic lengthscale, typically
+ * with local MLE). */
+
+/* Global separable lengthscales theta_k of K(x, x') = exp(-sum_k
+ * (x_k - x'_k)^2 / theta_k) + g [x = x'] by maximum likelihood (Eq. gpk on
+ * the n subset points, nugget g fixed), one coordinate at a time: each sweep
+ * runs, for k = 0..p-1, the bracketed Newton iteration of lagp_predict_mle
+ * on theta_k within [dmin, dmax] with the others fixed; sweeps repeat until
+ * one moves no theta_k by more than tol theta_k (tol <= 0: 1e-8), at most
+ * maxsweep times (<= 0: 20), with at most maxit evaluations per coordinate
+ * (<= 0: 100).  XS (device, n x p row-major FP64, 1 <= n <= 1024,
+ * p <= LAGP_MAX_DIM) and yS (device, n) stay the caller's.  theta (host, p)
+ * holds the starting values on entry and the estimates on return; iters
+ * (host, nullable) the likelihood evaluations; status (host, nullable) the
+ * LAGP_STATUS_MLE_* bits (BOUND: some theta_k at a bound; MAXIT: a
+ * coordinate or the sweeps ran out; NOTPD: some K not positive definite).
+ * Runs on the stream and waits for it (the results are host values).
+ * Workspace: 3 n^2 + 7 n doubles, stream-ordered.  LAGP_EINVAL on bad sizes
+ * or bounds. */
+int32_t lagp_fit_separable(const double* XS, const double* yS, int32_t n, int32_t p, double g, double* theta,
+                           double dmin, double dmax, double tol, int32_t maxit, int32_t maxsweep, int32_t* iters,
+                           int32_t* status, void* stream);
+
+/* out[i][k] = X[i][k] / sqrt(theta[k]) for N rows of p coordinates (device,
+ * row-major FP64; out may equal X).  theta: host, p values, each finite and
+ * > 0.  Asynchronous on the stream.  LAGP_EINVAL on bad sizes or values. */
+int32_t lagp_prescale(const double* X, int64_t N, int32_t p, const double* theta, double* out, void* stream);
+
 /* ---- serving: continuous batching over a resident design ---------------
  *
  * A server owns a worker thread and a device stream.  Requests (host

@@ -41,7 +41,8 @@ LAGP_STATUS_MLE_MAXIT = 64
 
 EXPORTED = [
     "lagp_version", "lagp_last_error", "lagp_design_create", "lagp_design_destroy", "lagp_design_info",
-    "lagp_candidates", "lagp_predict", "lagp_predict_candidates", "lagp_predict_mle", "lagp_server_create", "lagp_server_submit", "lagp_server_poll",
+    "lagp_candidates", "lagp_predict", "lagp_predict_candidates", "lagp_predict_mle", "lagp_fit_separable",
+    "lagp_prescale", "lagp_server_create", "lagp_server_submit", "lagp_server_poll",
     "lagp_server_fetch", "lagp_server_stats", "lagp_server_destroy",
 ]
 
@@ -96,6 +97,12 @@ def lib():
         L.lagp_predict_mle.argtypes = [_vp, _vp, i64, _vp, pp, ctypes.POINTER(lagp_mle_params), _vp, _vp, _vp, _vp,
                                        _vp, _vp, _vp, _vp]
         L.lagp_predict_mle.restype = i32
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.lagp_fit_separable.argtypes = [_vp, _vp, i32, i32, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), _vp]
+        L.lagp_fit_separable.restype = i32
+        L.lagp_prescale.argtypes = [_vp, i64, i32, dp, _vp, _vp]
+        L.lagp_prescale.restype = i32
         L.lagp_server_create.argtypes = [_vp, sz, i32, ctypes.POINTER(_vp)]
         L.lagp_server_create.restype = i32
         L.lagp_server_submit.argtypes = [_vp, _vp, i64, pp, ctypes.POINTER(ctypes.c_uint64)]
@@ -212,6 +219,26 @@ def lagp_predict_mle(design, XX, cand_idx, params: lagp_params, mle: lagp_mle_pa
     return _check(lib().lagp_predict_mle(design, _ptr(XX), XX.shape[0], _ptr(cand_idx), ctypes.byref(params),
                                          ctypes.byref(mle), _ptr(mean), _ptr(s2), _ptr(df), _ptr(dhat),
                                          _ptr(sel_idx), _ptr(iters), _ptr(status), _stream(stream)))
+
+
+def lagp_fit_separable(XS, yS, g: float, theta0, dmin: float, dmax: float, tol: float = 0.0, maxit: int = 0,
+                       maxsweep: int = 0, stream=None):
+    """Global separable lengthscales on the subset (XS, yS) (device tensors):
+    returns (theta numpy (p,), evaluations, status bits)."""
+    n, p = XS.shape
+    th = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(np.asarray(theta0, dtype=np.float64)), (p,))).copy()
+    it, st = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lagp_fit_separable(_ptr(XS), _ptr(yS), n, p, g, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    dmin, dmax, tol, maxit, maxsweep, ctypes.byref(it), ctypes.byref(st),
+                                    _stream(stream)))
+    return th, it.value, st.value
+
+
+def lagp_prescale(X, theta, out, stream=None) -> int:
+    """out = X / sqrt(theta) per column (device tensors, N x p)."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    return _check(lib().lagp_prescale(_ptr(X), X.shape[0], X.shape[1],
+                                      th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(out), _stream(stream)))
 
 
 def lagp_server_create(design, hbm_budget_bytes: int, max_inflight: int):

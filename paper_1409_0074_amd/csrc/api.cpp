@@ -523,4 +523,60 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
   return LAGP_OK;
 }
 
+// Global separable lengthscales on a subset (sepfit.hip), synchronous.
+int32_t lagp_fit_separable(const double* XS, const double* yS, int32_t n, int32_t p, double g, double* theta,
+                           double dmin, double dmax, double tol, int32_t maxit, int32_t maxsweep, int32_t* iters,
+                           int32_t* status, void* stream) {
+  if (n < 1 || n > lagp::SEP_NMAX) return fail(LAGP_EINVAL, "n must be in [1, 1024]");
+  if (p < 1 || p > LAGP_MAX_DIM) return fail(LAGP_EINVAL, "p must be in [1, LAGP_MAX_DIM]");
+  if (!XS || !yS || !theta) return fail(LAGP_EINVAL, "XS, yS and theta must not be NULL");
+  if (!(g >= 0.0) || !std::isfinite(g)) return fail(LAGP_EINVAL, "nugget g must be finite and >= 0");
+  if (!(dmin > 0.0) || !(dmin < dmax) || !std::isfinite(dmax)) return fail(LAGP_EINVAL, "need 0 < dmin < dmax (finite)");
+  for (int k = 0; k < p; ++k)
+    if (!(theta[k] > 0.0) || !std::isfinite(theta[k])) return fail(LAGP_EINVAL, "starting lengthscales must be finite and > 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  lagp::SepArgs a{};
+  a.XS = XS;
+  a.y = yS;
+  a.n = n;
+  a.p = p;
+  a.g = g;
+  a.dmin = dmin;
+  a.dmax = dmax;
+  a.tol = tol > 0.0 ? tol : 1e-8;
+  a.maxit = maxit > 0 ? maxit : 100;
+  a.maxsweep = maxsweep > 0 ? maxsweep : 20;
+  // [theta: p][iters, flags][workspace]
+  const size_t head = 256;
+  Workspace ws;
+  ws.s = s;
+  LAGP_HIP(hipMallocAsync(&ws.ptr, head + lagp::sepfit_workspace_bytes(n), s));
+  char* base = reinterpret_cast<char*>(ws.ptr);
+  a.theta = reinterpret_cast<double*>(base);
+  a.iters = reinterpret_cast<int32_t*>(base + 128);
+  a.flags = a.iters + 1;
+  a.ws = reinterpret_cast<double*>(base + head);
+  LAGP_HIP(hipMemcpyAsync(a.theta, theta, sizeof(double) * p, hipMemcpyHostToDevice, s));
+  LAGP_HIP(lagp::launch_sepfit(a, s));
+  int32_t out2[2];
+  LAGP_HIP(hipMemcpyAsync(theta, a.theta, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+  LAGP_HIP(hipMemcpyAsync(out2, a.iters, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+  LAGP_HIP(hipStreamSynchronize(s));
+  if (iters) *iters = out2[0];
+  if (status) *status = out2[1];
+  return LAGP_OK;
+}
+
+// Inputs divided by the square roots of the lengthscales (sepfit.hip).
+int32_t lagp_prescale(const double* X, int64_t N, int32_t p, const double* theta, double* out, void* stream) {
+  if (N < 0) return fail(LAGP_EINVAL, "N must be >= 0");
+  if (p < 1 || p > LAGP_MAX_DIM) return fail(LAGP_EINVAL, "p must be in [1, LAGP_MAX_DIM]");
+  if (!theta) return fail(LAGP_EINVAL, "theta must not be NULL");
+  for (int k = 0; k < p; ++k)
+    if (!(theta[k] > 0.0) || !std::isfinite(theta[k])) return fail(LAGP_EINVAL, "lengthscales must be finite and > 0");
+  if (N > 0 && (!X || !out)) return fail(LAGP_EINVAL, "X and out must not be NULL");
+  LAGP_HIP(lagp::launch_prescale(X, N, p, theta, out, reinterpret_cast<hipStream_t>(stream)));
+  return LAGP_OK;
+}
+
 }  // extern "C"

@@ -125,6 +125,26 @@ size_t mle_lds_bytes(int n, int p);
 bool mle_supported(int n, int p, size_t lds_max);
 hipError_t launch_mle(const MleArgs& a, hipStream_t s);
 
+// Global separable fit on a subset (sepfit.hip): one workgroup, n <= SEP_NMAX.
+constexpr int SEP_NMAX = 1024;
+struct SepArgs {
+  const double* XS;  // n x p subset coordinates
+  const double* y;   // n
+  int32_t n, p;
+  double g, dmin, dmax, tol;
+  int32_t maxit, maxsweep;
+  double* theta;     // p: starting values in, estimates out
+  int32_t* iters;    // 1: likelihood evaluations
+  int32_t* flags;    // 1: LAGP_STATUS_MLE_* bits
+  double* ws;        // sepfit_workspace_bytes(n)
+};
+struct PrescaleScales {
+  double theta[LAGP_MAX_DIM];
+};
+size_t sepfit_workspace_bytes(int n);
+hipError_t launch_sepfit(const SepArgs& a, hipStream_t s);
+hipError_t launch_prescale(const double* X, int64_t N, int p, const double* theta, double* out, hipStream_t s);
+
 hipError_t launch_bbox(const double* X, int64_t N, int p, double* lo, double* hi, hipStream_t s);
 
 // Shared by the C ABI and the server (api.cpp).
