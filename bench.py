@@ -247,6 +247,61 @@ def sec51(steps: int):
     return out
 
 
+def prescale_leg(steps: int, ns: int = 256):
+    """Pre-scaling by global separable lengthscales (Sec. 5.3) on the
+    anisotropic 8-d workload (N = 1e6, M = 1e4): the fit on a subset of ns
+    rows, the scaling of design and locations, then exhaustive and ray
+    (p rays) search with two-stage local MLE on the scaled inputs, beside
+    the same searches on the raw inputs."""
+    import torch
+
+    import paper_1409_0074_amd as lg
+    from paper_1409_0074_amd import workloads as W
+
+    w = W.aniso8d()
+    N, p = w.X.shape
+    M = w.XX.shape[0]
+    X = torch.from_numpy(w.X).cuda()
+    XX = torch.from_numpy(w.XX).cuda()
+    y = torch.from_numpy(w.y).cuda()
+    idx = torch.from_numpy(W.aniso8d_subset(N, ns)).cuda()
+    XS, yS = X[idx].contiguous(), y[idx].contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    theta, evals, st = lg.lagp_fit_separable(XS, yS, w.params.g, 1.0, 1e-3, 100.0, 1e-4, 100, 8)
+    fit_s = time.perf_counter() - t0
+    Xs, XXs = torch.empty_like(X), torch.empty_like(XX)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lg.lagp_prescale(X, theta, Xs)
+    lg.lagp_prescale(XX, theta, XXs)
+    torch.cuda.synchronize()
+    scale_ms = (time.perf_counter() - t0) * 1e3
+    out = {"workload": w.name, "subset_rows": ns, "theta_hat": [round(float(t), 4) for t in theta],
+           "fit_seconds": round(fit_s, 4), "fit_evaluations": evals, "fit_status": st,
+           "prescale_ms": round(scale_ms, 3), "rows": {}}
+    for tag, Xd, XXd, d0 in (("raw", X, XX, 0.5), ("prescaled", Xs, XXs, 1.0)):
+        d = lg.Design(Xd, y)
+        for sname, search, nr in (("exhaustive", W.SEARCH_EXHAUSTIVE, 0), ("rays8", W.SEARCH_RAY, p)):
+            prm = w.params.replace(d=(d0,), search=search, numrays=nr,
+                                   scoring=W.SCORING_CHOL if search == W.SEARCH_EXHAUSTIVE else W.SCORING_PARTINV)
+            d.predict_mle(XXd[:256], prm, 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                o = d.predict_mle(XXd, prm, 2)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            mu = o["mean"].cpu().numpy()
+            out["rows"][f"{tag}_{sname}"] = {
+                "ms": round(dt * 1e3, 3), "pred_per_s": round(M / dt, 1),
+                "rmse": float(np.sqrt(np.mean((mu - w.truth) ** 2))),
+                "dhat_median": float(np.median(o["dhat"].cpu().numpy())),
+                "status_nonzero": int((o["status"] != 0).sum().cpu())}
+        d.close()
+    return out
+
+
 def ray_sweep(w, steps: int, counts):
     """Rays per greedy step R = 1..p on the 8-d workload (fixed d, the same
     candidates): rate of the design search and accuracy against the truth,
@@ -297,6 +352,7 @@ def main() -> int:
     ap.add_argument("--serving-requests", type=int, default=400)
     ap.add_argument("--no-sec51", action="store_true", help="skip the Sec. 5.1 2-d experiment (Table 1 rows)")
     ap.add_argument("--no-ray-sweep", action="store_true", help="skip the rays-per-step sweep R = 1..p")
+    ap.add_argument("--no-prescale", action="store_true", help="skip the pre-scaling leg (anisotropic 8-d)")
     ap.add_argument("--grid", action="store_true", help="also run the 2-d grid workload, FP64 and mixed")
     ap.add_argument("--grid-M", type=int, default=2000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -482,6 +538,8 @@ def main() -> int:
         result["ray_sweep"] = ray_sweep(w, args.ray_steps, [0] + list(range(1, w.X.shape[1] + 1)))
     if not args.no_sec51:
         result["sec51"] = sec51(args.ray_steps)
+    if not args.no_prescale:
+        result["prescale"] = prescale_leg(args.ray_steps)
     if not args.no_serving:
         result["serving"] = serving(args.serving_requests)
     if args.grid:
