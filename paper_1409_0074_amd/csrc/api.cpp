@@ -117,6 +117,7 @@ lagp::Knn2Args knn_args(const lagp_design* d, const double* XX, int32_t M, int n
   k.buf_idx = reinterpret_cast<int32_t*>(b + o_d2 + sizeof(double) * cap * chunk);
   k.X = d->X;
   k.rn = d->rn;
+  k.X32 = d->X32;
   k.rn_max = d->rn_max;
   k.XX = XX;
   k.out_idx = out_idx;
@@ -165,7 +166,8 @@ int32_t lagp_design_create(const double* X, const double* y, int64_t N, int32_t 
   double* rmax = nullptr;
   if (hipMalloc(&d->X, xb) != hipSuccess || hipMalloc(&d->y, yb) != hipSuccess ||
       hipMalloc(&d->lo, sizeof(double) * p) != hipSuccess || hipMalloc(&d->hi, sizeof(double) * p) != hipSuccess ||
-      hipMalloc(&d->rn, yb) != hipSuccess || hipMalloc(&rmax, sizeof(double)) != hipSuccess) {
+      hipMalloc(&d->rn, yb) != hipSuccess || hipMalloc(&d->X32, sizeof(float) * (size_t)N * p) != hipSuccess ||
+      hipMalloc(&rmax, sizeof(double)) != hipSuccess) {
     if (rmax) (void)hipFree(rmax);
     lagp_design_destroy(d);
     return fail(LAGP_ENOMEM, "device allocation of the design failed");
@@ -173,7 +175,7 @@ int32_t lagp_design_create(const double* X, const double* y, int64_t N, int32_t 
   hipError_t e = hipMemcpyAsync(d->X, X, xb, hipMemcpyDefault, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d->y, y, yb, hipMemcpyDefault, s);
   if (e == hipSuccess) e = lagp::launch_bbox(d->X, N, p, d->lo, d->hi, s);
-  if (e == hipSuccess) e = lagp::launch_row_norms(d->X, N, p, d->rn, rmax, s);
+  if (e == hipSuccess) e = lagp::launch_row_norms(d->X, N, p, d->rn, rmax, d->X32, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&d->rn_max, rmax, sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(rmax);
@@ -193,6 +195,7 @@ void lagp_design_destroy(lagp_design* d) {
   if (d->lo) (void)hipFree(d->lo);
   if (d->hi) (void)hipFree(d->hi);
   if (d->rn) (void)hipFree(d->rn);
+  if (d->X32) (void)hipFree(d->X32);
   delete d;
 }
 

@@ -189,6 +189,7 @@ __global__ __launch_bounds__(64) void k_knn_tau_reduce(Knn2Args a, int parts) {
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Scan with an MFMA distance screen.  For 64 locations (four sets of 16) and
 // a tile of 16 design rows, 16x16x4 FP64 MFMAs give the inner products
@@ -322,13 +323,145 @@ __global__ __launch_bounds__(64) void k_knn_scan(Knn2Args a) {
   flush();
 }
 
+// The same scan with the inner products on the FP32 matrix cores (twice the
+// FP64 rate), for designs whose squared norms stay far inside FP32's range.
+// The coordinates are rounded to FP32 (relative error u32 = 2^-24 each) and
+// the p products accumulated in FP32 (at most p + 1 roundings of u32), so the
+// FP32 inner product is within (p + 4) u32 sum_k |x_qk x_ik| <=
+// (p + 4) u32 (||x_q||^2 + ||x_i||^2) / 2 of the exact one and t within
+// (p + 4) u32 (||x_q||^2 + ||x_i||^2) plus the FP64 terms above.  The
+// screen's slack adds 4 (p + 4) u32 (||x_q||^2 + 2 max ||x_i||^2) (four times
+// that bound) and 2^-100 (flushed subnormals) to the FP64 slack, so every
+// row whose defined squared distance is <= tau still passes, and the
+// defined squared distance (FP64, from the FP64 coordinates) still decides.
+// MFMA operands as in the FP64 scan; the FP32 16x16x4 result D[i][n] sits in
+// register i % 4 of lane 16 (i / 4) + n.
+template <int P>
+__global__ __launch_bounds__(64) void k_knn_scan32(Knn2Args a) {
+  constexpr int PD = P > 0 ? P : LAGP_MAX_DIM;
+  constexpr int NCH = (PD + 3) / 4;  // K-chunks of 4 dimensions
+  const int p = P > 0 ? P : a.p;
+  const int lane = threadIdx.x, g = lane >> 4, n = lane & 15;
+  const int q0 = blockIdx.y * 64;
+  float af[4][NCH];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int q = q0 + 16 * s + n, d = 4 * c + g;
+      af[s][c] = (q < a.M && d < p) ? (float)a.XX[(int64_t)q * p + d] : 0.0f;
+    }
+  // screen bounds of this lane's outputs: set s, register r -> location
+  // q0 + 16 s + 4 g + r
+  const double u = 0x1p-53, u32 = 0x1p-24;
+  double th[4][4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = q0 + 16 * s + 4 * g + r;
+      double t = -__builtin_huge_val();
+      if (q < a.M) {
+        const double tau = a.tau[q];
+        double qn = 0.0;
+        for (int k = 0; k < p; ++k) qn = __builtin_fma(a.XX[(int64_t)q * p + k], a.XX[(int64_t)q * p + k], qn);
+        if (tau >= 0.0)
+          t = tau * (1.0 + 2.0 * (p + 2) * u) - qn + 4.0 * (p + 4) * u * (qn + 2.0 * a.rn_max) +
+              4.0 * (p + 4) * u32 * (qn + 2.0 * a.rn_max) + 0x1p-100;
+        if (!(qn <= 1e30)) t = __builtin_huge_val();  // out of FP32's comfort: every row passes
+      }
+      th[s][r] = t;
+    }
+  const int64_t i0 = (int64_t)blockIdx.x * a.slice;
+  const int64_t i1 = i0 + a.slice < a.N ? i0 + a.slice : a.N;
+  constexpr int STG = 2048;
+  __shared__ int32_t st_row[STG];
+  __shared__ uint8_t st_q[STG];
+  __shared__ int st_n;
+  if (lane == 0) st_n = 0;
+  __syncthreads();
+  auto flush = [&]() {
+    __syncthreads();
+    const int tot = st_n;
+    for (int e = lane; e < tot; e += 64) {
+      const int64_t row = st_row[e];
+      const int q = q0 + st_q[e];
+      const double* xq = a.XX + (int64_t)q * p;
+      const double* xr = a.X + row * p;
+      double acc = 0.0;
+      for (int k = 0; k < p; ++k) {
+        const double d = xq[k] - xr[k];
+        acc = __builtin_fma(d, d, acc);
+      }
+      if (acc <= a.tau[q]) {
+        const int pos = atomicAdd(&a.cnt[q], 1);
+        if (pos < a.CAP) {
+          a.buf_d2[(int64_t)q * a.CAP + pos] = acc;
+          a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)row;
+        }
+      }
+    }
+    __syncthreads();
+    if (lane == 0) st_n = 0;
+    __syncthreads();
+  };
+  float bn[NCH];
+  double rnn;
+  auto load_tile = [&](int64_t i, float (&bf)[NCH], double& rn) {
+    const int64_t rr = i + n;
+    const int64_t rl = rr < i1 ? rr : i1 - 1;  // in bounds
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int d = 4 * c + g;
+      bf[c] = d < p ? a.X32[rl * p + d] : 0.0f;
+    }
+    rn = rr < i1 ? a.rn[rl] : __builtin_huge_val();
+  };
+  if (i0 < i1) load_tile(i0, bn, rnn);
+  for (int64_t i = i0; i < i1; i += 16) {
+    const int64_t rr = i + n;
+    const bool valid = rr < i1;
+    float bf[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) bf[c] = bn[c];
+    const double rn = rnn;
+    if (i + 16 < i1) load_tile(i + 16, bn, rnn);
+    unsigned hit = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s][c], bf[c], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (__builtin_fma(-2.0, (double)acc[r], rn) <= th[s][r]) hit |= 1u << (4 * s + r);
+    }
+    if (!valid) hit = 0;
+    if (!__builtin_expect(__any(hit), 0)) continue;
+    const int nh = __builtin_popcount(hit);
+    const int base = nh ? atomicAdd(&st_n, nh) : 0;
+    for (int k = 0; hit; ++k) {
+      const int b = __builtin_ctz(hit);  // b = 4 s + r: location 16 s + 4 g + r
+      hit &= hit - 1;
+      st_row[base + k] = (int32_t)rr;
+      st_q[base + k] = (uint8_t)(16 * (b >> 2) + 4 * g + (b & 3));
+    }
+    __syncthreads();
+    if (st_n > STG - 1024) flush();  // a tile stages at most 64 x 16
+  }
+  flush();
+}
+
 // Squared row norms of the design and their maximum (for the scan's screen).
 __global__ __launch_bounds__(256) void k_row_norms(const double* X, int64_t N, int p, double* rn,
-                                                   unsigned long long* rmax_bits) {
+                                                   unsigned long long* rmax_bits, float* X32) {
   double m = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int k = 0; k < p; ++k) s = __builtin_fma(X[i * p + k], X[i * p + k], s);
+    for (int k = 0; k < p; ++k) {
+      s = __builtin_fma(X[i * p + k], X[i * p + k], s);
+      X32[i * p + k] = (float)X[i * p + k];
+    }
     rn[i] = s;
     m = fmax(m, s);
   }
@@ -337,11 +470,12 @@ __global__ __launch_bounds__(256) void k_row_norms(const double* X, int64_t N, i
   if ((threadIdx.x & 63) == 0) atomicMax(rmax_bits, (unsigned long long)__builtin_bit_cast(long long, m));
 }
 
-hipError_t launch_row_norms(const double* X, int64_t N, int p, double* rn, double* rmax, hipStream_t s) {
+hipError_t launch_row_norms(const double* X, int64_t N, int p, double* rn, double* rmax, float* X32,
+                            hipStream_t s) {
   hipError_t e = hipMemsetAsync(rmax, 0, sizeof(double), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_row_norms, dim3(1024), dim3(256), 0, s, X, N, p, rn,
-                     reinterpret_cast<unsigned long long*>(rmax));
+                     reinterpret_cast<unsigned long long*>(rmax), X32);
   return hipGetLastError();
 }
 
@@ -493,7 +627,11 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   if (nsl > maxsl) nsl = maxsl;
   if (nsl < 1) nsl = 1;
   a.slice = (a.N + nsl - 1) / nsl;
-  hipLaunchKernelGGL(k_knn_scan<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), sgroups), dim3(64), 0, s, a);
+  // the FP32 screen while the design's squared norms stay far inside FP32's range
+  if (a.X32 && a.rn_max <= 1e30)
+    hipLaunchKernelGGL(k_knn_scan32<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), sgroups), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_knn_scan<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), sgroups), dim3(64), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = knn2_merge_lds_bytes(a.S);

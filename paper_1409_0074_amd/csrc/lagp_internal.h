@@ -13,6 +13,7 @@ struct lagp_design {
   double* lo;  // device, p: per-dimension minimum of X
   double* hi;  // device, p: per-dimension maximum of X
   double* rn;  // device, N: squared row norms of X (screening only)
+  float* X32;  // device, N x p: X rounded to FP32 (screening only)
   double rn_max;  // their maximum
   int device;
 };
@@ -86,6 +87,7 @@ struct Knn2Args {
   int32_t* out_idx;   // M x ncand
   double* sub;        // workspace, sub_count x p: the threshold subsample
   const double* rn;   // N squared row norms of X
+  const float* X32;   // nullable, N x p: X rounded to FP32 (the FP32 screen)
   double rn_max;
   double* out_d2;     // nullable, M x ncand
   int64_t N;
@@ -106,7 +108,7 @@ constexpr int LOCAL_THREADS = 256;
 
 int knn_sort_size(int ncand);
 hipError_t launch_knn2(Knn2Args a, hipStream_t s);
-hipError_t launch_row_norms(const double* X, int64_t N, int p, double* rn, double* rmax, hipStream_t s);
+hipError_t launch_row_norms(const double* X, int64_t N, int p, double* rn, double* rmax, float* X32, hipStream_t s);
 int64_t knn2_sub_rows(int64_t N, int ncand);
 size_t knn2_shared_bytes(int64_t N, int p, int ncand);  // per call, beside the per-location buffers
 size_t knn2_bytes_per_location(int ncand);
