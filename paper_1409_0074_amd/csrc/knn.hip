@@ -73,7 +73,7 @@ __device__ void load_and_sort(const double* bd, const int32_t* bi, int count, do
 // Every key and order is exact; the threshold only decides how much work is
 // done, never which rows are returned.
 
-constexpr int KT = 16;    // per-part list length of the threshold pass
+constexpr int KT = 8;    // per-part list length of the threshold pass
 constexpr int KSEL = 64;  // subsample order statistic taken as the threshold
 static_assert(16 * KT <= 256 && KSEL <= 256, "the reduce sorts at most 256 values per location");
 
@@ -604,9 +604,10 @@ size_t knn2_merge_lds_bytes(int S) { return (size_t)S * (sizeof(double) + sizeof
 template <int P>
 static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   const int groups = (a.M + 63) / 64;
-  // enough subsample parts to occupy the chip; KSEL <= KT * parts <= 256 <= CAP
-  int parts = (2048 + groups - 1) / groups;
-  if (parts > 16) parts = 16;
+  // enough subsample parts for about 4096 waves (the pass is latency-bound);
+  // KSEL <= KT * parts <= 256 <= CAP
+  int parts = (4096 + groups - 1) / groups;
+  if (parts > 32) parts = 32;
   if (parts < KSEL / KT) parts = KSEL / KT;
   if ((int64_t)parts > a.sub_count) parts = (int)a.sub_count;
   if (parts < 1) parts = 1;
