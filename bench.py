@@ -27,8 +27,8 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of one launch of each local-design kernel over the uniform 8-d
 # workload (M = 1e4), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)
-# of `bench.py --steps 1 --warmup 0 --no-ray --no-cpu --no-serving
-# --copy-calibration-mb 1024`, each scaled by what the counter read for a
+# of `bench.py --steps 1 --warmup 0 --no-ray --no-cpu --no-serving --no-mle
+# --no-ray-sweep --no-sec51 --no-prescale --copy-calibration-mb 1024`, each scaled by what the counter read for a
 # 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the
 # kernel sources it was taken on (sha256); otherwise reported as null.
 COMMON_SOURCES = ("paper_1409_0074_amd/csrc/dev_math.h", "paper_1409_0074_amd/csrc/lagp_internal.h",
@@ -36,10 +36,10 @@ COMMON_SOURCES = ("paper_1409_0074_amd/csrc/dev_math.h", "paper_1409_0074_amd/cs
 KERNEL_SOURCES = {"k_chol": ("paper_1409_0074_amd/csrc/chol.hip",) + COMMON_SOURCES,
                   "k_local": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES}
 MEASURED_TRAFFIC = {
-    "k_chol": {"sha256": "cacd3c2c861cb153b04418d80833a3187a31a71f5375df0fe53afd35b01dc255",
-               "bytes": 2.296e9, "fetch_kib": 1120560.8, "write_kib": 1257.9},
-    "k_local": {"sha256": "03f296cfa443338131bd0a56d4dd0352ed9009c2bd54fdd52c2b58dbbb2058ee",
-                "bytes": 1.405e11, "fetch_kib": 66299878.6, "write_kib": 4579154.5},
+    "k_chol": {"sha256": "8d30fca6c8ae6c9f2b02b8f0f4c9ca6b06f97fed3f75f1f0553b87270eec767c",
+               "bytes": 2.296e9, "fetch_kib": 1120496.7, "write_kib": 1256.7},
+    "k_local": {"sha256": "efd7c2f521538f64dfb2a0f9206c709ef25f9d845b9fc5ca9ef76632fbd89c5c",
+                "bytes": 1.405e11, "fetch_kib": 66296225.5, "write_kib": 4578795.9},
 }
 
 
