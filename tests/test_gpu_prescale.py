@@ -72,6 +72,16 @@ def test_sepfit_bench_subset(lg):
     assert np.all(th[4:] >= 99.0) and th[0] < 1.0
 
 
+def test_sepfit_largest_subset(lg):
+    """n = 1024 rows (the maximum): one Newton step of one coordinate (the
+    oracle's evaluation at this size takes about ten seconds), bit for bit."""
+    rng = np.random.default_rng(730)
+    XS = rng.random((1024, 2))
+    yS = np.sin(3.0 * XS[:, 0]) + XS[:, 1] ** 2
+    th, it, st = _fit_both(lg, XS, yS, 1e-6, [0.5, 1.0], 1e-3, 100.0, tol=1e-6, maxit=1, maxsweep=1)
+    assert it == 2 and st & lg.LAGP_STATUS_MLE_MAXIT
+
+
 def test_prescale_matches_numpy(lg):
     import torch
 
@@ -128,3 +138,5 @@ def test_sepfit_and_prescale_reject(lg):
         lg.lagp_fit_separable(big, torch.zeros(1025, dtype=torch.float64, device="cuda"), 1e-6, 1.0, 1e-3, 10.0)
     with pytest.raises(lg.LagpError):
         lg.lagp_prescale(XS, np.array([1.0, 0.0]), XS)
+    empty = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    assert lg.lagp_prescale(empty, np.array([1.0, 2.0]), empty) == 0
