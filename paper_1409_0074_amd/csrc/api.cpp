@@ -119,6 +119,7 @@ lagp::Knn2Args knn_args(const lagp_design* d, const double* XX, int32_t M, int n
   k.rn = d->rn;
   k.X32 = d->X32;
   k.rn_max = d->rn_max;
+  k.spread2 = d->spread2;
   k.XX = XX;
   k.out_idx = out_idx;
   k.out_d2 = out_d2;
@@ -177,7 +178,13 @@ int32_t lagp_design_create(const double* X, const double* y, int64_t N, int32_t 
   if (e == hipSuccess) e = lagp::launch_bbox(d->X, N, p, d->lo, d->hi, s);
   if (e == hipSuccess) e = lagp::launch_row_norms(d->X, N, p, d->rn, rmax, d->X32, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&d->rn_max, rmax, sizeof(double), hipMemcpyDeviceToHost, s);
+  double lo[LAGP_MAX_DIM], hi[LAGP_MAX_DIM];
+  if (e == hipSuccess) e = hipMemcpyAsync(lo, d->lo, sizeof(double) * p, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hi, d->hi, sizeof(double) * p, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  d->spread2 = 0.0;
+  if (e == hipSuccess)
+    for (int k = 0; k < p; ++k) d->spread2 += (hi[k] - lo[k]) * (hi[k] - lo[k]);
   (void)hipFree(rmax);
   if (e != hipSuccess) {
     lagp_design_destroy(d);

@@ -628,8 +628,14 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   if (nsl > maxsl) nsl = maxsl;
   if (nsl < 1) nsl = 1;
   a.slice = (a.N + nsl - 1) / nsl;
-  // the FP32 screen while the design's squared norms stay far inside FP32's range
-  if (a.X32 && a.rn_max <= 1e30)
+  // The FP32 screen when its slack (which grows with the squared norms) stays
+  // under 5% of an estimate of the threshold (the squared radius holding
+  // ncand of N points spread over the design's extent); designs far from the
+  // origin relative to their extent keep the FP64 screen, whose slack is
+  // 2^29 times smaller.  Either way the lists are exact.
+  const double slack32 = 12.0 * (a.p + 4) * 0x1p-24 * a.rn_max;
+  const double tau_est = a.spread2 * pow((double)a.ncand / (double)a.N, 2.0 / a.p);
+  if (a.X32 && a.rn_max <= 1e30 && slack32 <= 0.05 * tau_est)
     hipLaunchKernelGGL(k_knn_scan32<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), sgroups), dim3(64), 0, s, a);
   else
     hipLaunchKernelGGL(k_knn_scan<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), sgroups), dim3(64), 0, s, a);

@@ -14,6 +14,7 @@ struct lagp_design {
   double* hi;  // device, p: per-dimension maximum of X
   double* rn;  // device, N: squared row norms of X (screening only)
   float* X32;  // device, N x p: X rounded to FP32 (screening only)
+  double spread2;  // sum over dimensions of (max - min)^2 (chooses the kNN screen's precision)
   double rn_max;  // their maximum
   int device;
 };
@@ -89,6 +90,7 @@ struct Knn2Args {
   const double* rn;   // N squared row norms of X
   const float* X32;   // nullable, N x p: X rounded to FP32 (the FP32 screen)
   double rn_max;
+  double spread2;     // sum over dimensions of the design's squared extent
   double* out_d2;     // nullable, M x ncand
   int64_t N;
   int64_t sub_stride;
