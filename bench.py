@@ -36,10 +36,10 @@ COMMON_SOURCES = ("paper_1409_0074_amd/csrc/dev_math.h", "paper_1409_0074_amd/cs
 KERNEL_SOURCES = {"k_chol": ("paper_1409_0074_amd/csrc/chol.hip",) + COMMON_SOURCES,
                   "k_local": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES}
 MEASURED_TRAFFIC = {
-    "k_chol": {"sha256": "8d30fca6c8ae6c9f2b02b8f0f4c9ca6b06f97fed3f75f1f0553b87270eec767c",
-               "bytes": 2.296e9, "fetch_kib": 1120496.7, "write_kib": 1256.7},
-    "k_local": {"sha256": "efd7c2f521538f64dfb2a0f9206c709ef25f9d845b9fc5ca9ef76632fbd89c5c",
-                "bytes": 1.405e11, "fetch_kib": 66296225.5, "write_kib": 4578795.9},
+    "k_chol": {"sha256": "c1bcaf6daa61c64c2ad2200e7316d022d793db496cfb8d9a8171d46b468e5f01",
+               "bytes": 2.294e9, "fetch_kib": 1119451.2, "write_kib": 1257.2},
+    "k_local": {"sha256": "0e590ed338be25a38d32737b47e255bc2bc7458498a9d0cb266d0fb59c281b09",
+                "bytes": 1.405e11, "fetch_kib": 66299577.2, "write_kib": 4578716.9},
 }
 
 

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(64) void k_knn_scan(Knn2Args a) {
   constexpr int NCH = (PD + 3) / 4;  // K-chunks of 4 dimensions
   const int p = P > 0 ? P : a.p;
   const int lane = threadIdx.x, g = lane >> 4, n = lane & 15;
-  const int q0 = blockIdx.y * 64;
+  const int q0 = blockIdx.x * 64;
   double af[4][NCH];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(64) void k_knn_scan(Knn2Args a) {
       }
       th[s][r] = t;
     }
-  const int64_t i0 = (int64_t)blockIdx.x * a.slice;
+  const int64_t i0 = (int64_t)blockIdx.y * a.slice;
   const int64_t i1 = i0 + a.slice < a.N ? i0 + a.slice : a.N;
   // Screened pairs are staged in LDS and settled in batches (one lane per
   // pair): the defined squared distance, and for d2 <= tau an append to the
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(64) void k_knn_scan32(Knn2Args a) {
   constexpr int NCH = (PD + 3) / 4;  // K-chunks of 4 dimensions
   const int p = P > 0 ? P : a.p;
   const int lane = threadIdx.x, g = lane >> 4, n = lane & 15;
-  const int q0 = blockIdx.y * 64;
+  const int q0 = blockIdx.x * 64;
   float af[4][NCH];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(64) void k_knn_scan32(Knn2Args a) {
       }
       th[s][r] = t;
     }
-  const int64_t i0 = (int64_t)blockIdx.x * a.slice;
+  const int64_t i0 = (int64_t)blockIdx.y * a.slice;
   const int64_t i1 = i0 + a.slice < a.N ? i0 + a.slice : a.N;
   constexpr int STG = 2048;
   __shared__ int32_t st_row[STG];
@@ -621,7 +621,9 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   hipLaunchKernelGGL(k_knn_tau_reduce, dim3(a.M), dim3(64), 0, s, a, parts);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // scan: slices of the design x groups of 64 locations, about 8192 waves
+  // scan: groups of 64 locations x slices of the design, about 8192 waves;
+  // the groups vary fastest, so the waves that read one slice run together
+  // and share it through L2
   const int sgroups = (a.M + 63) / 64;
   int64_t nsl = (8192 + sgroups - 1) / sgroups;
   const int64_t maxsl = (a.N + 1023) / 1024;
@@ -636,9 +638,9 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   const double slack32 = 12.0 * (a.p + 4) * 0x1p-24 * a.rn_max;
   const double tau_est = a.spread2 * pow((double)a.ncand / (double)a.N, 2.0 / a.p);
   if (a.X32 && a.rn_max <= 1e30 && slack32 <= 0.05 * tau_est)
-    hipLaunchKernelGGL(k_knn_scan32<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), sgroups), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_knn_scan32<P>, dim3(sgroups, (unsigned)((a.N + a.slice - 1) / a.slice)), dim3(64), 0, s, a);
   else
-    hipLaunchKernelGGL(k_knn_scan<P>, dim3((unsigned)((a.N + a.slice - 1) / a.slice), sgroups), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_knn_scan<P>, dim3(sgroups, (unsigned)((a.N + a.slice - 1) / a.slice)), dim3(64), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = knn2_merge_lds_bytes(a.S);
