@@ -152,3 +152,41 @@ def test_grid2d_full_size_sampled(lg):
     o = oracle.predict(w.X, w.y, w.XX[idx], prm)
     assert np.array_equal(g["sel"][idx], o["sel"])
     assert np.array_equal(g["mean"][idx], o["mean"]) and np.array_equal(g["s2"][idx], o["s2"])
+
+
+def test_aniso8d_full_size_prescaled_mle_sampled(lg):
+    """The pre-scaling leg as the benchmark runs it: the global fit on the
+    256-row subset of the 1e6-row anisotropic 8-d design (bit for bit as the
+    oracle's), the scaling of design and all 1e4 locations, then exhaustive
+    search with two-stage local MLE on the scaled inputs; 6 sampled
+    locations recomputed by the oracle on numpy's scaled arrays."""
+    import torch
+
+    w = W.aniso8d()
+    N = w.X.shape[0]
+    idx = W.aniso8d_subset(N)
+    X = torch.from_numpy(w.X).cuda()
+    XX = torch.from_numpy(w.XX).cuda()
+    y = torch.from_numpy(w.y).cuda()
+    th, it, st = lg.lagp_fit_separable(X[idx].contiguous(), y[idx].contiguous(), w.params.g, 1.0, 1e-3, 100.0,
+                                       1e-4, 100, 8)
+    th_o, it_o, st_o = oracle.sep_fit(w.X[idx], w.y[idx], w.params.g, 1.0, 1e-3, 100.0, 1e-4, 100, 8)
+    assert np.array_equal(th, th_o) and it == it_o and st == st_o
+    Xs, XXs = torch.empty_like(X), torch.empty_like(XX)
+    lg.lagp_prescale(X, th, Xs)
+    lg.lagp_prescale(XX, th, XXs)
+    prm = w.params.replace(d=(1.0,))
+    d = lg.Design(Xs, y)
+    try:
+        out = d.predict_mle(XXs, prm, 2)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+    finally:
+        d.close()
+    s = np.sqrt(th)
+    Xn, XXn = w.X / s, w.XX / s
+    pick = _sample(w.XX.shape[0], 6, 513)
+    o = oracle.predict_mle(Xn, w.y, XXn[pick], prm, 2)
+    for k in ("sel", "dhat", "iters", "status", "mean", "s2"):
+        assert np.array_equal(g[k][pick], o[k]), k
+    assert np.sqrt(np.mean((g["mean"] - w.truth) ** 2)) < 1e-3
