@@ -531,6 +531,124 @@ __device__ void knn_exact_one(const Knn2Args& a, int q, double* kd, int* ki, dou
   load_and_sort(bd, bi, si[1], kd, ki, S);
 }
 
+// Bitonic sort of S = E * blockDim.x (key, row) pairs held E per thread in
+// registers (thread t holds elements t E .. t E + E - 1), ascending by
+// (key, row): the network of lds_bitonic_sort, with partners in the same
+// thread compared in registers, partners in the same wave exchanged by
+// shuffles, and only partners in other waves exchanged through LDS (kd, ki:
+// S entries).  Same comparisons, same result.
+template <int E, int ST>
+__device__ __forceinline__ void bitonic_in_thread(double (&k)[E], int (&v)[E], int e0, int size) {
+#pragma unroll
+  for (int x = 0; x < E; ++x) {
+    const int y = x ^ ST;
+    if (y > x) {
+      const bool up = ((e0 + x) & size) == 0;
+      const bool sw = up ? key_less(k[y], v[y], k[x], v[x]) : key_less(k[x], v[x], k[y], v[y]);
+      if (sw) {
+        const double tk = k[x];
+        k[x] = k[y];
+        k[y] = tk;
+        const int tv = v[x];
+        v[x] = v[y];
+        v[y] = tv;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void keep_of_pair(double& k, int& v, double pk, int pv, int e, int stride, int size) {
+  const bool lower = (e & stride) == 0;  // e < e ^ stride
+  const bool up = (e & size) == 0;
+  const bool pk_less = key_less(pk, pv, k, v);
+  // the lower position keeps the smaller when ascending, the larger otherwise
+  const bool take = (lower == up) ? pk_less : !pk_less;
+  if (take) {
+    k = pk;
+    v = pv;
+  }
+}
+
+template <int E>
+__device__ void reg_bitonic_sort(double (&k)[E], int (&v)[E], double* kd, int* ki) {
+  const int t = threadIdx.x, S = E * blockDim.x;
+  const int e0 = t * E;
+  for (int size = 2; size <= S; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride < E) {
+        if (stride == 1) bitonic_in_thread<E, 1>(k, v, e0, size);
+        if constexpr (E > 2) if (stride == 2) bitonic_in_thread<E, 2>(k, v, e0, size);
+        if constexpr (E > 4) if (stride == 4) bitonic_in_thread<E, 4>(k, v, e0, size);
+        if constexpr (E > 8) if (stride == 8) bitonic_in_thread<E, 8>(k, v, e0, size);
+      } else if (stride < 64 * E) {
+        const int lx = stride / E;  // partner lane within the wave
+#pragma unroll
+        for (int x = 0; x < E; ++x) {
+          const double pk = __shfl_xor(k[x], lx, 64);
+          const int pv = __shfl_xor(v[x], lx, 64);
+          keep_of_pair(k[x], v[x], pk, pv, e0 + x, stride, size);
+        }
+      } else {
+#pragma unroll
+        for (int x = 0; x < E; ++x) {
+          kd[e0 + x] = k[x];
+          ki[e0 + x] = v[x];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int x = 0; x < E; ++x) {
+          const int pe = (e0 + x) ^ stride;
+          keep_of_pair(k[x], v[x], kd[pe], ki[pe], e0 + x, stride, size);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// The merge with E pairs per thread in registers: sort the first S collected
+// pairs, then stream the rest through positions ncand .. S-1 (as the LDS
+// form below does), and write the ncand smallest.
+template <int E>
+__device__ void merge_regs(const Knn2Args& a, int q, double* kd, int* ki) {
+  const int nc = a.ncand, t = threadIdx.x, e0 = t * E, S = E * blockDim.x;
+  const double* bd = a.buf_d2 + (int64_t)q * a.CAP;
+  const int32_t* bi = a.buf_idx + (int64_t)q * a.CAP;
+  const int c = a.cnt[q];
+  double k[E];
+  int v[E];
+  int taken = c < S ? c : S;
+#pragma unroll
+  for (int x = 0; x < E; ++x) {
+    const int e = e0 + x;
+    k[x] = e < taken ? bd[e] : __builtin_huge_val();
+    v[x] = e < taken ? bi[e] : 0x7fffffff;
+  }
+  reg_bitonic_sort<E>(k, v, kd, ki);
+  while (taken < c) {  // stream the rest through positions nc .. S-1
+    const int add = (c - taken) < (S - nc) ? (c - taken) : (S - nc);
+#pragma unroll
+    for (int x = 0; x < E; ++x) {
+      const int e = e0 + x;
+      if (e >= nc) {
+        const int src = e - nc;
+        k[x] = src < add ? bd[taken + src] : __builtin_huge_val();
+        v[x] = src < add ? bi[taken + src] : 0x7fffffff;
+      }
+    }
+    reg_bitonic_sort<E>(k, v, kd, ki);
+    taken += add;
+  }
+#pragma unroll
+  for (int x = 0; x < E; ++x) {
+    const int e = e0 + x;
+    if (e < nc) {
+      a.out_idx[(int64_t)q * nc + e] = v[x];
+      if (a.out_d2) a.out_d2[(int64_t)q * nc + e] = k[x];
+    }
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(KNN_THREADS) void k_knn_merge(Knn2Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -544,6 +662,10 @@ __global__ __launch_bounds__(KNN_THREADS) void k_knn_merge(Knn2Args a) {
   double* bd = a.buf_d2 + (int64_t)q * a.CAP;
   int32_t* bi = a.buf_idx + (int64_t)q * a.CAP;
   const int c = a.cnt[q];
+  if (c >= nc && c <= a.CAP && S == 8 * KNN_THREADS && blockDim.x == KNN_THREADS) {
+    merge_regs<8>(a, q, kd, ki);
+    return;
+  }
   if (c >= nc && c <= a.CAP) {
     int taken = c < S ? c : S;
     load_and_sort(bd, bi, taken, kd, ki, S);
