@@ -73,9 +73,10 @@ __device__ void load_and_sort(const double* bd, const int32_t* bi, int count, do
 // Every key and order is exact; the threshold only decides how much work is
 // done, never which rows are returned.
 
-constexpr int KT = 8;    // per-part list length of the threshold pass
-constexpr int KSEL = 64;  // subsample order statistic taken as the threshold
-static_assert(16 * KT <= 256 && KSEL <= 256, "the reduce sorts at most 256 values per location");
+constexpr int KT = 4;               // per-part list length of the threshold pass
+constexpr int KSEL = 64;            // subsample order statistic taken as the threshold
+constexpr int KPARTS = 256 / KT;    // most parts: the reduce sorts at most 256 values per location
+static_assert(KSEL <= KT * KPARTS, "the partial lists must hold KSEL values");
 
 // The design never changes while these kernels run: reading it through the
 // constant address space lets wave-uniform row reads become scalar loads
@@ -726,10 +727,11 @@ size_t knn2_merge_lds_bytes(int S) { return (size_t)S * (sizeof(double) + sizeof
 template <int P>
 static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   const int groups = (a.M + 63) / 64;
-  // enough subsample parts for about 4096 waves (the pass is latency-bound);
-  // KSEL <= KT * parts <= 256 <= CAP
-  int parts = (4096 + groups - 1) / groups;
-  if (parts > 32) parts = 32;
+  // enough subsample parts for about 8192 waves (the pass is latency-bound;
+  // short lists keep each wave's insertions cheap); KSEL <= KT * parts <= 256
+  // <= CAP
+  int parts = (8192 + groups - 1) / groups;
+  if (parts > KPARTS) parts = KPARTS;
   if (parts < KSEL / KT) parts = KSEL / KT;
   if ((int64_t)parts > a.sub_count) parts = (int)a.sub_count;
   if (parts < 1) parts = 1;
@@ -777,8 +779,8 @@ hipError_t launch_knn2(Knn2Args a, hipStream_t s) {
   if (a.M <= 0) return hipSuccess;
   a.S = knn_sort_size(a.ncand);
   a.CAP = knn2_capacity(a.ncand);
-  // subsample: r rows per sample so that about r * KT ~ 2 ncand rows fall
-  // under the KT-th smallest sampled distance
+  // subsample: one row in r, r = 2 ncand / KSEL, so that about 2 ncand design
+  // rows fall under the KSEL-th smallest sampled distance
   a.sub_count = knn2_sub_rows(a.N, a.ncand);
   int64_t A = (int64_t)((double)a.N * 0.6180339887498949) | 1;
   if (A >= a.N) A = 1;
