@@ -324,58 +324,70 @@ __global__ __launch_bounds__(64) void k_knn_scan(Knn2Args a) {
   flush();
 }
 
-// The same scan with the inner products on the FP32 matrix cores (twice the
-// FP64 rate), for designs whose squared norms stay far inside FP32's range.
-// The coordinates are rounded to FP32 (relative error u32 = 2^-24 each) and
-// the p products accumulated in FP32 (at most p + 1 roundings of u32), so the
-// FP32 inner product is within (p + 4) u32 sum_k |x_qk x_ik| <=
-// (p + 4) u32 (||x_q||^2 + ||x_i||^2) / 2 of the exact one and t within
-// (p + 4) u32 (||x_q||^2 + ||x_i||^2) plus the FP64 terms above.  The
-// screen's slack adds 4 (p + 4) u32 (||x_q||^2 + 2 max ||x_i||^2) (four times
-// that bound) and 2^-100 (flushed subnormals) to the FP64 slack, so every
-// row whose defined squared distance is <= tau still passes, and the
-// defined squared distance (FP64, from the FP64 coordinates) still decides.
+// The same scan with the screen on the FP32 matrix cores (twice the FP64
+// rate), for designs whose squared norms stay far inside FP32's range.  Two
+// more K dimensions carry the rest of the screen into the product: location
+// q contributes (-2 x_q, 1, -th_q), design row i (x_i, rn_i, 1), so the
+// accumulator is t - th_q itself and a pair passes when its sign bit is set
+// (no per-pair conversion, fma or comparison).
+// Error: operands are rounded to FP32 (u32 = 2^-24; th_q upward, which only
+// widens the screen), and the K = 4 NCH products are summed with at most
+// K + 1 roundings, so the accumulator is within
+// (K + 3) u32 (2 ||x_q||^2 + 3 max ||x_i||^2 + tau) (1 + 1e-3) of
+// t - th_q (the terms: the rounded coordinates, 2 u32 (||x_q||^2 + ||x_i||^2);
+// rn_i, u32 ||x_i||^2; the summation, (K + 1) u32 times the sum of the
+// products' magnitudes, which is at most 2 ||x_q||^2 + 2 ||x_i||^2 + tau).
+// th_q adds 4 (K + 4) u32 (2 ||x_q||^2 + 3 max ||x_i||^2 + tau) + 2^-100
+// (flushed subnormals) to the FP64 bound of the other scan, so every row
+// whose defined squared distance is <= tau gives a negative accumulator, and
+// the defined squared distance (FP64, from the FP64 coordinates) still
+// decides.  Infinite bounds stay exact: th = -inf (no row) gives +inf, th = +inf
+// (every row) -inf, and a row past the slice (rn = +inf) is masked.
 // MFMA operands as in the FP64 scan; the FP32 16x16x4 result D[i][n] sits in
 // register i % 4 of lane 16 (i / 4) + n.
+// Seven waves per SIMD (the scan is latency-bound): registers capped to fit,
+// which also keeps the MFMA results out of the accumulation registers.
 template <int P>
-__global__ __launch_bounds__(64) void k_knn_scan32(Knn2Args a) {
+__global__ __launch_bounds__(64, 7) void k_knn_scan32(Knn2Args a) {
   constexpr int PD = P > 0 ? P : LAGP_MAX_DIM;
-  constexpr int NCH = (PD + 3) / 4;  // K-chunks of 4 dimensions
+  constexpr int NCH = (PD + 2 + 3) / 4;  // K-chunks of 4: coordinates, then (1, rn) and (-th, 1)
+  constexpr int K = 4 * NCH;
   const int p = P > 0 ? P : a.p;
   const int lane = threadIdx.x, g = lane >> 4, n = lane & 15;
   const int q0 = blockIdx.x * 64;
+  const double u = 0x1p-53, u32 = 0x1p-24;
+  // A operand: set s, row n -> location q0 + 16 s + n
   float af[4][NCH];
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int s = 0; s < 4; ++s) {
+    const int q = q0 + 16 * s + n;
+    double th = -__builtin_huge_val();
+    if (q < a.M) {
+      const double tau = a.tau[q];
+      double qn = 0.0;
+      for (int k = 0; k < p; ++k) qn = __builtin_fma(a.XX[(int64_t)q * p + k], a.XX[(int64_t)q * p + k], qn);
+      if (tau >= 0.0)
+        th = tau * (1.0 + 2.0 * (p + 2) * u) - qn + 4.0 * (p + 4) * u * (qn + 2.0 * a.rn_max) +
+             4.0 * (K + 4) * u32 * (2.0 * qn + 3.0 * a.rn_max + tau) + 0x1p-100;
+      if (!(qn <= 1e30)) th = __builtin_huge_val();  // out of FP32's comfort: every row passes
+    }
+    const float nth = -__double2float_ru(th);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-      const int q = q0 + 16 * s + n, d = 4 * c + g;
-      af[s][c] = (q < a.M && d < p) ? (float)a.XX[(int64_t)q * p + d] : 0.0f;
+      const int d = 4 * c + g;
+      float v = 0.0f;
+      if (d < p) v = q < a.M ? -2.0f * (float)a.XX[(int64_t)q * p + d] : 0.0f;
+      else if (d == p) v = 1.0f;
+      else if (d == p + 1) v = nth;
+      af[s][c] = v;
     }
-  // screen bounds of this lane's outputs: set s, register r -> location
-  // q0 + 16 s + 4 g + r
-  const double u = 0x1p-53, u32 = 0x1p-24;
-  double th[4][4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int q = q0 + 16 * s + 4 * g + r;
-      double t = -__builtin_huge_val();
-      if (q < a.M) {
-        const double tau = a.tau[q];
-        double qn = 0.0;
-        for (int k = 0; k < p; ++k) qn = __builtin_fma(a.XX[(int64_t)q * p + k], a.XX[(int64_t)q * p + k], qn);
-        if (tau >= 0.0)
-          t = tau * (1.0 + 2.0 * (p + 2) * u) - qn + 4.0 * (p + 4) * u * (qn + 2.0 * a.rn_max) +
-              4.0 * (p + 4) * u32 * (qn + 2.0 * a.rn_max) + 0x1p-100;
-        if (!(qn <= 1e30)) t = __builtin_huge_val();  // out of FP32's comfort: every row passes
-      }
-      th[s][r] = t;
-    }
+  }
   const int64_t i0 = (int64_t)blockIdx.y * a.slice;
   const int64_t i1 = i0 + a.slice < a.N ? i0 + a.slice : a.N;
-  constexpr int STG = 2048;
+  // a tile stages at most 64 x 16 = 1024 pairs and the buffer is settled
+  // once it holds more than 128: 5.8 KB of LDS per wave, so LDS leaves room
+  // for seven waves per SIMD
+  constexpr int STG = 1152;
   __shared__ int32_t st_row[STG];
   __shared__ uint8_t st_q[STG];
   __shared__ int st_n;
@@ -406,27 +418,37 @@ __global__ __launch_bounds__(64) void k_knn_scan32(Knn2Args a) {
     if (lane == 0) st_n = 0;
     __syncthreads();
   };
-  float bn[NCH];
-  double rnn;
-  auto load_tile = [&](int64_t i, float (&bf)[NCH], double& rn) {
+  // B operand: column n -> design row i + n.  The next tile's loads are
+  // issued one tile ahead into raw registers and converted only when used.
+  float xn[NCH];
+  double rnn = 0.0;
+  auto load_tile = [&](int64_t i) {
     const int64_t rr = i + n;
-    const int64_t rl = rr < i1 ? rr : i1 - 1;  // in bounds
+    const int64_t rl = rr < i1 ? rr : i1 - 1;  // in bounds: every load is unconditional
+    rnn = a.rn[rl];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       const int d = 4 * c + g;
-      bf[c] = d < p ? a.X32[rl * p + d] : 0.0f;
+      xn[c] = (P == 0 || 4 * c < P) ? a.X32[rl * p + (d < p ? d : p - 1)] : 0.0f;
     }
-    rn = rr < i1 ? a.rn[rl] : __builtin_huge_val();
   };
-  if (i0 < i1) load_tile(i0, bn, rnn);
+  if (i0 < i1) load_tile(i0);
   for (int64_t i = i0; i < i1; i += 16) {
     const int64_t rr = i + n;
     const bool valid = rr < i1;
     float bf[NCH];
+    {
+      const float rn = valid ? (float)rnn : __builtin_huge_valf();
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) bf[c] = bn[c];
-    const double rn = rnn;
-    if (i + 16 < i1) load_tile(i + 16, bn, rnn);
+      for (int c = 0; c < NCH; ++c) {
+        const int d = 4 * c + g;
+        float v = xn[c];
+        if (!(P > 0 && 4 * c + 3 < P)) v = d < p ? v : 0.0f;  // chunks that may hold padding
+        if (P == 0 || 4 * c + 3 >= P) v = d == p ? rn : (d == p + 1 ? 1.0f : v);
+        bf[c] = v;
+      }
+    }
+    if (i + 16 < i1) load_tile(i + 16);
     unsigned hit = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -434,8 +456,7 @@ __global__ __launch_bounds__(64) void k_knn_scan32(Knn2Args a) {
 #pragma unroll
       for (int c = 0; c < NCH; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s][c], bf[c], acc, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (__builtin_fma(-2.0, (double)acc[r], rn) <= th[s][r]) hit |= 1u << (4 * s + r);
+      for (int r = 0; r < 4; ++r) hit |= (__float_as_uint(acc[r]) >> 31) << (4 * s + r);
     }
     if (!valid) hit = 0;
     if (!__builtin_expect(__any(hit), 0)) continue;
@@ -745,11 +766,12 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   hipLaunchKernelGGL(k_knn_tau_reduce, dim3(a.M), dim3(64), 0, s, a, parts);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // scan: groups of 64 locations x slices of the design, about 8192 waves;
-  // the groups vary fastest, so the waves that read one slice run together
-  // and share it through L2
+  // scan: groups of 64 locations x slices of the design, about 21504 waves
+  // (three rounds of the FP32 scan's seven resident waves per SIMD; shorter
+  // slices hide the tail of the last round); the groups vary fastest, so the
+  // waves that read one slice run together and share it through L2
   const int sgroups = (a.M + 63) / 64;
-  int64_t nsl = (8192 + sgroups - 1) / sgroups;
+  int64_t nsl = (21504 + sgroups - 1) / sgroups;
   const int64_t maxsl = (a.N + 1023) / 1024;
   if (nsl > maxsl) nsl = maxsl;
   if (nsl < 1) nsl = 1;
@@ -759,8 +781,9 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   // ncand of N points spread over the design's extent); designs far from the
   // origin relative to their extent keep the FP64 screen, whose slack is
   // 2^29 times smaller.  Either way the lists are exact.
-  const double slack32 = 12.0 * (a.p + 4) * 0x1p-24 * a.rn_max;
+  constexpr int K32 = 4 * (((P > 0 ? P : LAGP_MAX_DIM) + 5) / 4);  // k_knn_scan32's product length
   const double tau_est = a.spread2 * pow((double)a.ncand / (double)a.N, 2.0 / a.p);
+  const double slack32 = 4.0 * (K32 + 4) * 0x1p-24 * (5.0 * a.rn_max + tau_est);
   if (a.X32 && a.rn_max <= 1e30 && slack32 <= 0.05 * tau_est)
     hipLaunchKernelGGL(k_knn_scan32<P>, dim3(sgroups, (unsigned)((a.N + a.slice - 1) / a.slice)), dim3(64), 0, s, a);
   else
