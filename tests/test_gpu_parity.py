@@ -35,11 +35,13 @@ def _cands(lg, X, y, XX, ncand):
 # ------------------------------------------------------------------- kNN --
 
 @pytest.mark.parametrize("case", ["uniform2d", "uniform8d", "grid_ties", "ragged", "p5", "p13", "offset3",
-                                  "offset1e4"])
+                                  "offset15", "offset18", "offset1e4"])
 def test_candidates_bit_exact(lg, case):
     """offset3: coordinates in [3, 4]^4, the FP32 screen with norms far from
-    zero; offset1e4: in [1e4, 1e4 + 1]^4, where the FP32 screen's slack would
-    exceed the threshold and the FP64 screen runs instead."""
+    zero; offset15: the FP32 screen with its slack at about 3/4 of the 5% of
+    the estimated threshold it may take (the least margin for a wrong
+    rounding bound); offset18 just past that limit and offset1e4 far past it
+    ([1e4, 1e4 + 1]^4), where the FP64 screen runs instead."""
     rng = np.random.default_rng(101)
     if case == "uniform2d":
         w = W.tiny_2d()
@@ -54,8 +56,8 @@ def test_candidates_bit_exact(lg, case):
         X, XX, nc = rng.random((1237, 3)), rng.random((13, 3)), 37
     elif case == "p5":
         X, XX, nc = rng.random((5000, 5)), rng.random((9, 5)), 64
-    elif case in ("offset3", "offset1e4"):
-        off = 3.0 if case == "offset3" else 1e4
+    elif case.startswith("offset"):
+        off = float(case[len("offset"):])
         X, XX, nc = rng.random((20000, 4)) + off, rng.random((11, 4)) + off, 200
     else:
         X, XX, nc = rng.random((3000, 13)), rng.random((3, 13)), 1
