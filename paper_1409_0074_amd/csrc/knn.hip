@@ -329,7 +329,8 @@ __global__ __launch_bounds__(64) void k_knn_scan(Knn2Args a) {
 // more K dimensions carry the rest of the screen into the product: location
 // q contributes (-2 x_q, 1, -th_q), design row i (x_i, rn_i, 1), so the
 // accumulator is t - th_q itself and a pair passes when its sign bit is set
-// (no per-pair conversion, fma or comparison).
+// (no per-pair conversion, fma or comparison; a byte permute gathers four
+// sign bits at once).
 // Error: operands are rounded to FP32 (u32 = 2^-24; th_q upward, which only
 // widens the screen), and the K = 4 NCH products are summed with at most
 // K + 1 roundings, so the accumulator is within
@@ -382,6 +383,13 @@ __global__ __launch_bounds__(64, 7) void k_knn_scan32(Knn2Args a) {
       af[s][c] = v;
     }
   }
+  // hit-mask bits of real locations: bit 8 r + s <-> location q0 + 16 s + 4 g + r
+  unsigned locmask = 0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (q0 + 16 * s + 4 * g + r < a.M) locmask |= 1u << (8 * r + s);
   const int64_t i0 = (int64_t)blockIdx.y * a.slice;
   const int64_t i1 = i0 + a.slice < a.N ? i0 + a.slice : a.N;
   // a tile stages at most 64 x 16 = 1024 pairs and the buffer is settled
@@ -455,18 +463,21 @@ __global__ __launch_bounds__(64, 7) void k_knn_scan32(Knn2Args a) {
       v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int c = 0; c < NCH; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s][c], bf[c], acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) hit |= (__float_as_uint(acc[r]) >> 31) << (4 * s + r);
+      // the four sign bytes into one word (bits 7, 15, 23, 31), then bits 8 r + s
+      const unsigned lo = __builtin_amdgcn_perm(__float_as_uint(acc[1]), __float_as_uint(acc[0]), 0x0c0c0703u);
+      const unsigned hi = __builtin_amdgcn_perm(__float_as_uint(acc[3]), __float_as_uint(acc[2]), 0x07030c0cu);
+      hit |= ((lo | hi) >> (7 - s)) & (0x01010101u << s);
     }
+    hit &= locmask;
     if (!valid) hit = 0;
     if (!__builtin_expect(__any(hit), 0)) continue;
     const int nh = __builtin_popcount(hit);
     const int base = nh ? atomicAdd(&st_n, nh) : 0;
     for (int k = 0; hit; ++k) {
-      const int b = __builtin_ctz(hit);  // b = 4 s + r: location 16 s + 4 g + r
+      const int b = __builtin_ctz(hit);  // b = 8 r + s: location 16 s + 4 g + r
       hit &= hit - 1;
       st_row[base + k] = (int32_t)rr;
-      st_q[base + k] = (uint8_t)(16 * (b >> 2) + 4 * g + (b & 3));
+      st_q[base + k] = (uint8_t)(16 * (b & 7) + 4 * g + (b >> 3));
     }
     __syncthreads();
     if (st_n > STG - 1024) flush();  // a tile stages at most 64 x 16
