@@ -332,6 +332,11 @@ static double relgap(double a, double b)
  * step before last; no evaluation closer than tol1 = sqrt(eps)|x| + tol/3
  * to the current best point; stop once the bracket half-width about the
  * best point is within 2 tol1 (Sec. 4 names this routine, Brent_fmin).
+ * Direction conventions of that routine: a parabolic step that would land
+ * within 2 tol1 of an end becomes a step of tol1 towards the midpoint, taken
+ * downwards when the best point is at or above the midpoint; a step shorter
+ * than tol1 is lengthened to tol1 in its own direction, downwards when it is
+ * zero.
  * *mingap (if given) receives the smallest relative gap among the decisions
  * the iteration took, so callers can tell near-tie steps apart.
  */
@@ -375,7 +380,7 @@ double orc_brent_min(double (*f)(double, void *), void *arg, double lo, double h
             if (fabs(num) < half && num > den * (a - x) && num < den * (b - x)) {
                 step = num / den;
                 double u = x + step;
-                if (u - a < tol2 || b - u < tol2) step = (mid - x >= 0.0) ? tol1 : -tol1;
+                if (u - a < tol2 || b - u < tol2) step = (x >= mid) ? -tol1 : tol1;
                 parabolic = 1;
             }
         }
@@ -383,7 +388,7 @@ double orc_brent_min(double (*f)(double, void *), void *arg, double lo, double h
             prev = (x >= mid) ? a - x : b - x;
             step = gold * prev;
         }
-        double u = (fabs(step) >= tol1) ? x + step : x + ((step >= 0.0) ? tol1 : -tol1);
+        double u = (fabs(step) >= tol1) ? x + step : ((step > 0.0) ? x + tol1 : x - tol1);
         double fu = f(u, arg);
         evals++;
         gap = fmin(gap, relgap(fu, fx));

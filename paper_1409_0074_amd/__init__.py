@@ -288,6 +288,33 @@ def lagp_server_destroy(server) -> None:
 
 # ------------------------------------------------------------ convenience --
 
+def _torch_stream(stream):
+    """The torch stream object for a stream argument (None: the current one)."""
+    import torch
+
+    if stream is None:
+        return torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return stream
+    return torch.cuda.ExternalStream(int(getattr(stream, "cuda_stream", stream)))
+
+
+def _on_stream(stream, *tensors):
+    """Order work on `stream` after torch's current stream (which produced
+    the converted inputs) and tell the caching allocator that the tensors are
+    in use on `stream`, so that none of them is reused while the library's
+    kernels still read or write it."""
+    import torch
+
+    s = _torch_stream(stream)
+    cur = torch.cuda.current_stream()
+    if s.cuda_stream != cur.cuda_stream:
+        s.wait_stream(cur)
+        for t in tensors:
+            if t is not None:
+                t.record_stream(s)
+    return s
+
 class Design:
     """Owns a lagp_design handle for torch tensors X (N x p), y (N)."""
 
@@ -296,7 +323,7 @@ class Design:
 
         self.X = torch.as_tensor(X, dtype=torch.float64, device="cuda").contiguous()
         self.y = torch.as_tensor(y, dtype=torch.float64, device="cuda").contiguous()
-        self.handle = lagp_design_create(self.X, self.y, stream)
+        self.handle = lagp_design_create(self.X, self.y, _on_stream(stream, self.X, self.y))
         self.N, self.p = self.X.shape
 
     def close(self):
@@ -316,7 +343,8 @@ class Design:
         XX = torch.as_tensor(XX, dtype=torch.float64, device="cuda").contiguous()
         idx = torch.empty((XX.shape[0], ncand), dtype=torch.int32, device="cuda")
         d2 = torch.empty((XX.shape[0], ncand), dtype=torch.float64, device="cuda")
-        lagp_candidates(self.handle, XX, ncand, idx, d2, stream)
+        s = _on_stream(stream, XX, idx, d2)
+        lagp_candidates(self.handle, XX, ncand, idx, d2, s)
         return idx, d2
 
     def predict(self, XX, params, stream=None, sel=True, diag=True):
@@ -332,8 +360,8 @@ class Design:
                    status=torch.empty(M, dtype=torch.int32, device="cuda"))
         out["sel"] = torch.empty((M, P.n), dtype=torch.int32, device="cuda") if sel else None
         out["diag"] = torch.empty((M, P.n - n0, 2), **dev) if diag else None
-        lagp_predict(self.handle, XX, P, out["mean"], out["s2"], out["df"], out["sel"], out["diag"], out["status"],
-                     stream)
+        s = _on_stream(stream, XX, *out.values())
+        lagp_predict(self.handle, XX, P, out["mean"], out["s2"], out["df"], out["sel"], out["diag"], out["status"], s)
         return out
 
     def predict_mle(self, XX, params, mode: int, dmin: float = 0.0, dmax: float = 0.0, tol: float = 0.0,
@@ -351,6 +379,7 @@ class Design:
         out = dict(mean=torch.empty(M, **dev), s2=torch.empty(M, **dev), df=torch.empty(M, **dev),
                    dhat=torch.empty(M, **dev), sel=torch.empty((M, P.n), **i32), iters=torch.empty(M, **i32),
                    status=torch.empty(M, **i32))
+        s = _on_stream(stream, XX, *out.values())
         lagp_predict_mle(self.handle, XX, None, P, Q, out["mean"], out["s2"], out["df"], out["dhat"], out["sel"],
-                         out["iters"], out["status"], stream)
+                         out["iters"], out["status"], s)
         return out

@@ -861,7 +861,11 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
 // shorter than half the step before last; never closer than
 // tol1 = 2^-26 |x| + tol/3 to the best point; a slot stops when its bracket
 // half-width about the best point is within 2 tol1 (or after brent_maxit
-// steps).  Returns the minimiser on lane t, its value in *fbest.
+// steps).  A parabolic step that would land within 2 tol1 of an end becomes
+// tol1 towards the midpoint (downwards when x is at or above it), and a step
+// shorter than tol1 becomes tol1 in its own direction (downwards when zero),
+// the conventions of the Brent_fmin routine Sec. 4 names.  Returns the
+// minimiser on lane t, its value in *fbest.
 template <int P>
 __device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, int LD, int j, const double* xi, int rid,
                                               bool live, double* fbest, int* vflag) {
@@ -900,7 +904,7 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, 
           if (fabs(num) < fabs(0.5 * den * older) && num > den * (lo - x) && num < den * (hi - x)) {
             step = num / den;
             const double uu = x + step;
-            if (uu - lo < tol2 || hi - uu < tol2) step = (mid - x >= 0.0) ? tol1 : -tol1;
+            if (uu - lo < tol2 || hi - uu < tol2) step = (x >= mid) ? -tol1 : tol1;
             para = true;
           }
         }
@@ -908,7 +912,7 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, 
           prev = (x >= mid) ? lo - x : hi - x;
           step = gold * prev;
         }
-        u = (fabs(step) >= tol1) ? x + step : x + ((step >= 0.0) ? tol1 : -tol1);
+        u = (fabs(step) >= tol1) ? x + step : ((step > 0.0) ? x + tol1 : x - tol1);
         ev = true;
       }
     }

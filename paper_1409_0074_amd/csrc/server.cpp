@@ -250,6 +250,7 @@ void worker_main(lagp_server* s) {
     // 2. admit: the head batch first; smaller later batches may bypass a
     //    blocked head a bounded number of times
     bool launched = false;
+    bool head_blocked = false;  // the head batch did not fit on this pass
     for (size_t start = 0; start < s->waiting.size();) {
       int slot = -1;
       for (int k = 0; k < s->max_inflight; ++k)
@@ -264,11 +265,14 @@ void worker_main(lagp_server* s) {
         // look for a later batch with other parameters
         size_t nxt = start + 1;
         while (nxt < s->waiting.size() && same_params(s->waiting[nxt]->P, b.P)) ++nxt;
-        if (start == 0) ++s->head_bypassed;
+        if (start == 0) head_blocked = true;
         start = nxt;
         continue;
       }
+      // a bypass counts only when a later batch is actually launched ahead
+      // of a blocked head
       if (start == 0) s->head_bypassed = 0;
+      else if (head_blocked) ++s->head_bypassed;
       remove_from_waiting(s, b);
       b.slot = slot;
       s->slot_busy[slot] = true;
@@ -286,6 +290,7 @@ void worker_main(lagp_server* s) {
         s->inflight.push_back(b);
       }
       launched = true;
+      head_blocked = false;
       start = 0;
     }
     if (!launched) {
