@@ -193,6 +193,27 @@ int32_t lagp_predict_candidates(const lagp_design* design, const double* XX, int
                                 const lagp_params* params, double* mean, double* s2, double* df, int32_t* sel_idx,
                                 double* diag, int32_t* status, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and outputs as lagp_predict (bit for bit), with every
+ * workspace taken from a fixed per-device scratch area of
+ * LAGP_NOALLOC_SCRATCH_BYTES (64 MiB) that the library holds on each GPU it
+ * runs on until the process ends.  Nothing is allocated or freed by this
+ * call.  Locations run in chunks that fit the scratch (about 1,200 per
+ * chunk at n = 50, N' = 1000 with Cholesky scoring and a 1e6-row design;
+ * about 100 with the partitioned-inverse form, whose kernel rows are kept
+ * in the workspace).  LAGP_ENOMEM when even one location's workspace plus
+ * the per-call candidate-search subsample exceeds the scratch; LAGP_EINVAL
+ * when the current device is not the design's or as lagp_predict.  Every
+ * call on one GPU shares that GPU's scratch and leaves its contents behind
+ * (nothing in it needs to start cleared: every kernel writes what it reads,
+ * counters included): calls that overlap on one GPU, from several threads
+ * or on several streams, race and must be serialised by the caller. */
+#define LAGP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int32_t lagp_predict_noalloc(const lagp_design* design, const double* XX, int64_t M, const lagp_params* params,
+                             double* mean, double* s2, double* df, int32_t* sel_idx, double* diag, int32_t* status,
+                             void* stream);
+
 /* Local GP prediction with local maximum likelihood of the lengthscale
  * (lagp_mle_params).  The estimate maximises the local likelihood
  * l(d) = -1/2 log|K| - n/2 log(y^T K^-1 y) of the n local points (Eq. gpk,

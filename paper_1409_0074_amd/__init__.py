@@ -41,7 +41,8 @@ LAGP_STATUS_MLE_MAXIT = 64
 
 EXPORTED = [
     "lagp_version", "lagp_last_error", "lagp_design_create", "lagp_design_destroy", "lagp_design_info",
-    "lagp_candidates", "lagp_predict", "lagp_predict_candidates", "lagp_predict_mle", "lagp_fit_separable",
+    "lagp_candidates", "lagp_predict", "lagp_predict_candidates", "lagp_predict_noalloc", "lagp_predict_mle",
+    "lagp_fit_separable",
     "lagp_prescale", "lagp_server_create", "lagp_server_submit", "lagp_server_poll",
     "lagp_server_fetch", "lagp_server_stats", "lagp_server_destroy",
 ]
@@ -94,6 +95,8 @@ def lib():
         L.lagp_predict.restype = i32
         L.lagp_predict_candidates.argtypes = [_vp, _vp, i64, _vp, pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.lagp_predict_candidates.restype = i32
+        L.lagp_predict_noalloc.argtypes = [_vp, _vp, i64, pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.lagp_predict_noalloc.restype = i32
         L.lagp_predict_mle.argtypes = [_vp, _vp, i64, _vp, pp, ctypes.POINTER(lagp_mle_params), _vp, _vp, _vp, _vp,
                                        _vp, _vp, _vp, _vp]
         L.lagp_predict_mle.restype = i32
@@ -205,6 +208,13 @@ def lagp_predict_candidates(design, XX, cand_idx, params: lagp_params, mean, s2,
     return _check(lib().lagp_predict_candidates(design, _ptr(XX), XX.shape[0], _ptr(cand_idx), ctypes.byref(params),
                                                 _ptr(mean), _ptr(s2), _ptr(df), _ptr(sel_idx), _ptr(diag),
                                                 _ptr(status), _stream(stream)))
+
+
+def lagp_predict_noalloc(design, XX, params: lagp_params, mean, s2, df, sel_idx=None, diag=None, status=None,
+                         stream=None) -> int:
+    return _check(lib().lagp_predict_noalloc(design, _ptr(XX), XX.shape[0], ctypes.byref(params), _ptr(mean),
+                                             _ptr(s2), _ptr(df), _ptr(sel_idx), _ptr(diag), _ptr(status),
+                                             _stream(stream)))
 
 
 def make_mle_params(mode: int, dmin: float = 0.0, dmax: float = 0.0, tol: float = 0.0,

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -312,7 +313,7 @@ size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool 
 
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
                     const lagp_params* P, double* mean, double* s2, double* df, int32_t* sel_idx, double* diag,
-                    int32_t* status, void* stream, size_t ws_budget) {
+                    int32_t* status, void* stream, size_t ws_budget, void* ext_ws, size_t ext_bytes) {
   if (!d) return fail(LAGP_EINVAL, "design is NULL");
   if (M < 0) return fail(LAGP_EINVAL, "M must be >= 0");
   int rays = 0;
@@ -343,16 +344,31 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const size_t b_kxc = chol ? 0 : sizeof(double) * (size_t)ncs;
   const size_t b_xc = chol ? 0 : sizeof(double) * (size_t)ncs * p;
   const size_t b_chol = chol ? 0 : sizeof(double) * 2 * (size_t)n0 * n0;
-  const int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget);
+  const size_t shared = cand_in ? 0 : knn2_shared_bytes(d->N, p, nc);
+  int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget);
+  if (ext_ws) {  // as many locations as the given workspace holds (9 sections, each aligned)
+    const size_t per = b_knn + b_cand + b_kc + b_kc32 + b_kxc + b_xc + b_chol + sizeof(int32_t);
+    const size_t fixed = shared + 9 * 256;
+    if (ext_bytes < fixed + per)
+      return fail(LAGP_ENOMEM, "the workspace of one location (" + std::to_string(fixed + per) +
+                                   " bytes) exceeds the " + std::to_string(ext_bytes) + "-byte scratch");
+    chunk = std::min<int64_t>(M, (int64_t)((ext_bytes - fixed) / per));
+  }
   Workspace ws;
   ws.s = s;
   const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_kc = o_cand + al(b_cand * chunk),
                o_kc32 = o_kc + al(b_kc * chunk), o_kxc = o_kc32 + al(b_kc32 * chunk),
                o_xc = o_kxc + al(b_kxc * chunk), o_chol = o_xc + al(b_xc * chunk),
                o_st = o_chol + al(b_chol * chunk), o_sub = o_st + al(sizeof(int32_t) * chunk),
-               total = o_sub + (cand_in ? 0 : knn2_shared_bytes(d->N, p, nc));
-  LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
-  char* base = reinterpret_cast<char*>(ws.ptr);
+               total = o_sub + shared;
+  char* base = nullptr;
+  if (ext_ws) {
+    if (total > ext_bytes) return fail(LAGP_ENOMEM, "internal: workspace layout exceeds the scratch");
+    base = reinterpret_cast<char*>(ext_ws);
+  } else {
+    LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
+    base = reinterpret_cast<char*>(ws.ptr);
+  }
   for (int64_t m0 = 0; m0 < M; m0 += chunk) {
     const int32_t mc = (int32_t)std::min<int64_t>(chunk, M - m0);
     const int32_t* cand = cand_in ? cand_in + m0 * nc : reinterpret_cast<const int32_t*>(base + o_cand);
@@ -401,6 +417,53 @@ int32_t lagp_predict_candidates(const lagp_design* d, const double* XX, int64_t 
                                 double* diag, int32_t* status, void* stream) {
   if (M > 0 && !cand_idx) return fail(LAGP_EINVAL, "cand_idx must not be NULL");
   return lagp::run_predict(d, XX, M, cand_idx, P, mean, s2, df, sel_idx, diag, status, stream, workspace_budget());
+}
+
+// ---- the entry point that allocates nothing --------------------------------
+//
+// Its workspace is this file-scope device array.  In host code the name
+// `scratch` is only a host-side stand-in: the array's device address comes
+// from hipGetSymbolAddress, taken once per device (with that device current)
+// and kept; kernels and copies get that address, never the name.
+static __device__ __align__(256) unsigned char scratch[LAGP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of this device's copy of `scratch` (set up on first use).
+int32_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(LAGP_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LAGP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LAGP_OK;
+}
+
+}  // namespace
+
+int32_t lagp_predict_noalloc(const lagp_design* d, const double* XX, int64_t M, const lagp_params* P, double* mean,
+                             double* s2, double* df, int32_t* sel_idx, double* diag, int32_t* status, void* stream) {
+  if (!d) return fail(LAGP_EINVAL, "design is NULL");
+  int dev = -1;
+  LAGP_HIP(hipGetDevice(&dev));
+  if (dev != d->device) return fail(LAGP_EINVAL, "the current device is not the design's device");
+  int32_t rc = lagp::check_predict_params(d, P);
+  if (rc != LAGP_OK) return rc;
+  if (M <= 0) return M < 0 ? fail(LAGP_EINVAL, "M must be >= 0") : LAGP_OK;
+  void* ws = nullptr;
+  rc = scratch_address(dev, &ws);
+  if (rc != LAGP_OK) return rc;
+  return lagp::run_predict(d, XX, M, nullptr, P, mean, s2, df, sel_idx, diag, status, stream, 0, ws,
+                           (size_t)LAGP_NOALLOC_SCRATCH_BYTES);
 }
 
 // Local MLE (mle.hip) around a design search (the Cholesky form of

@@ -155,9 +155,11 @@ hipError_t launch_bbox(const double* X, int64_t N, int p, double* lo, double* hi
 int32_t check_predict_params(const lagp_design* d, const lagp_params* P);
 size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool have_cand, int64_t M,
                                size_t ws_budget);
+// ext_ws (nullable): a caller-provided device workspace of ext_bytes; the
+// locations then run in chunks that fit it and nothing is allocated.
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in, const lagp_params* P,
                     double* mean, double* s2, double* df, int32_t* sel_idx, double* diag, int32_t* status,
-                    void* stream, size_t ws_budget);
+                    void* stream, size_t ws_budget, void* ext_ws = nullptr, size_t ext_bytes = 0);
 const char* set_error(const char* msg);
 
 }  // namespace lagp
