@@ -193,6 +193,23 @@ int32_t lagp_predict_candidates(const lagp_design* design, const double* XX, int
                                 const lagp_params* params, double* mean, double* s2, double* df, int32_t* sel_idx,
                                 double* diag, int32_t* status, void* stream);
 
+/* lagp_predict_candidates (cand_idx nullable: NULL searches the candidates
+ * here) with the work of each greedy step reported, for measurement (the
+ * paper's Sec. 6 notes that ray searches vary in length: the slowest take
+ * about twice the mean evaluations).  counts (device, nullable,
+ * M x (n - n0) x 2 int32), per location and step:
+ *   ray search (Sec. 4): [0] objective evaluations of the Brent line
+ *     searches summed over the step's rays (each search's first evaluation
+ *     included, the s = 0 checks not), [1] the most evaluations of one ray;
+ *   mixed form: [0] candidates whose FP32 upper bound on the FP64 criterion
+ *     reached the threshold (the certified shortlist), [1] 16-candidate
+ *     tiles re-scored in FP64;
+ *   FP64 exhaustive search (Sec. 3.1): [0] candidates scored (N' - j), [1] 0.
+ * Nearest-neighbour search has no greedy step.  Results as lagp_predict. */
+int32_t lagp_predict_counts(const lagp_design* design, const double* XX, int64_t M, const int32_t* cand_idx,
+                            const lagp_params* params, double* mean, double* s2, double* df, int32_t* sel_idx,
+                            double* diag, int32_t* status, int32_t* counts, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation and outputs as lagp_predict (bit for bit), with every

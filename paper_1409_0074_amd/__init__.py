@@ -41,7 +41,8 @@ LAGP_STATUS_MLE_MAXIT = 64
 
 EXPORTED = [
     "lagp_version", "lagp_last_error", "lagp_design_create", "lagp_design_destroy", "lagp_design_info",
-    "lagp_candidates", "lagp_predict", "lagp_predict_candidates", "lagp_predict_noalloc", "lagp_predict_mle",
+    "lagp_candidates", "lagp_predict", "lagp_predict_candidates", "lagp_predict_counts", "lagp_predict_noalloc",
+    "lagp_predict_mle",
     "lagp_fit_separable",
     "lagp_prescale", "lagp_server_create", "lagp_server_submit", "lagp_server_poll",
     "lagp_server_fetch", "lagp_server_stats", "lagp_server_destroy",
@@ -95,6 +96,8 @@ def lib():
         L.lagp_predict.restype = i32
         L.lagp_predict_candidates.argtypes = [_vp, _vp, i64, _vp, pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.lagp_predict_candidates.restype = i32
+        L.lagp_predict_counts.argtypes = [_vp, _vp, i64, _vp, pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.lagp_predict_counts.restype = i32
         L.lagp_predict_noalloc.argtypes = [_vp, _vp, i64, pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.lagp_predict_noalloc.restype = i32
         L.lagp_predict_mle.argtypes = [_vp, _vp, i64, _vp, pp, ctypes.POINTER(lagp_mle_params), _vp, _vp, _vp, _vp,
@@ -208,6 +211,13 @@ def lagp_predict_candidates(design, XX, cand_idx, params: lagp_params, mean, s2,
     return _check(lib().lagp_predict_candidates(design, _ptr(XX), XX.shape[0], _ptr(cand_idx), ctypes.byref(params),
                                                 _ptr(mean), _ptr(s2), _ptr(df), _ptr(sel_idx), _ptr(diag),
                                                 _ptr(status), _stream(stream)))
+
+
+def lagp_predict_counts(design, XX, cand_idx, params: lagp_params, mean, s2, df, sel_idx=None, diag=None,
+                        status=None, counts=None, stream=None) -> int:
+    return _check(lib().lagp_predict_counts(design, _ptr(XX), XX.shape[0], _ptr(cand_idx), ctypes.byref(params),
+                                            _ptr(mean), _ptr(s2), _ptr(df), _ptr(sel_idx), _ptr(diag),
+                                            _ptr(status), _ptr(counts), _stream(stream)))
 
 
 def lagp_predict_noalloc(design, XX, params: lagp_params, mean, s2, df, sel_idx=None, diag=None, status=None,
@@ -357,8 +367,9 @@ class Design:
         lagp_candidates(self.handle, XX, ncand, idx, d2, s)
         return idx, d2
 
-    def predict(self, XX, params, stream=None, sel=True, diag=True):
-        """Returns a dict of device tensors: mean, s2, df, sel, diag, status."""
+    def predict(self, XX, params, stream=None, sel=True, diag=True, counts=False):
+        """Returns a dict of device tensors: mean, s2, df, sel, diag, status
+        (and counts, the per-step search work, when asked for)."""
         import torch
 
         XX = torch.as_tensor(XX, dtype=torch.float64, device="cuda").contiguous()
@@ -370,8 +381,15 @@ class Design:
                    status=torch.empty(M, dtype=torch.int32, device="cuda"))
         out["sel"] = torch.empty((M, P.n), dtype=torch.int32, device="cuda") if sel else None
         out["diag"] = torch.empty((M, P.n - n0, 2), **dev) if diag else None
+        if counts:
+            out["counts"] = torch.empty((M, P.n - n0, 2), dtype=torch.int32, device="cuda")
         s = _on_stream(stream, XX, *out.values())
-        lagp_predict(self.handle, XX, P, out["mean"], out["s2"], out["df"], out["sel"], out["diag"], out["status"], s)
+        if counts:
+            lagp_predict_counts(self.handle, XX, None, P, out["mean"], out["s2"], out["df"], out["sel"], out["diag"],
+                                out["status"], out["counts"], s)
+        else:
+            lagp_predict(self.handle, XX, P, out["mean"], out["s2"], out["df"], out["sel"], out["diag"],
+                         out["status"], s)
         return out
 
     def predict_mle(self, XX, params, mode: int, dmin: float = 0.0, dmax: float = 0.0, tol: float = 0.0,

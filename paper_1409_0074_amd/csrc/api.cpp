@@ -313,7 +313,8 @@ size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool 
 
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
                     const lagp_params* P, double* mean, double* s2, double* df, int32_t* sel_idx, double* diag,
-                    int32_t* status, void* stream, size_t ws_budget, void* ext_ws, size_t ext_bytes) {
+                    int32_t* status, void* stream, size_t ws_budget, void* ext_ws, size_t ext_bytes,
+                    int32_t* counts) {
   if (!d) return fail(LAGP_EINVAL, "design is NULL");
   if (M < 0) return fail(LAGP_EINVAL, "M must be >= 0");
   int rays = 0;
@@ -387,6 +388,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.df = df + m0;
     a.sel = sel_idx ? sel_idx + m0 * n : nullptr;
     a.diag = diag ? diag + m0 * (int64_t)(n - n0) * 2 : nullptr;
+    a.counts = counts ? counts + m0 * (int64_t)(n - n0) * 2 : nullptr;
     a.status = status ? status + m0 : reinterpret_cast<int32_t*>(base + o_st);
     LAGP_HIP(chol ? lagp::launch_chol(a, s) : lagp::launch_local(a, s));
   }
@@ -417,6 +419,13 @@ int32_t lagp_predict_candidates(const lagp_design* d, const double* XX, int64_t 
                                 double* diag, int32_t* status, void* stream) {
   if (M > 0 && !cand_idx) return fail(LAGP_EINVAL, "cand_idx must not be NULL");
   return lagp::run_predict(d, XX, M, cand_idx, P, mean, s2, df, sel_idx, diag, status, stream, workspace_budget());
+}
+
+int32_t lagp_predict_counts(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_idx,
+                            const lagp_params* P, double* mean, double* s2, double* df, int32_t* sel_idx,
+                            double* diag, int32_t* status, int32_t* counts, void* stream) {
+  return lagp::run_predict(d, XX, M, cand_idx, P, mean, s2, df, sel_idx, diag, status, stream, workspace_budget(),
+                           nullptr, 0, counts);
 }
 
 // ---- the entry point that allocates nothing --------------------------------

@@ -327,6 +327,11 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
         dg[0] = b1;
         dg[1] = b2 < 0.0 ? -__builtin_huge_val() : b2;
       }
+      if (j >= n0 && a.counts) {  // every free candidate is scored
+        int32_t* ct = a.counts + (m * (n - n0) + (j - n0)) * 2;
+        ct[0] = a.ncand - j;
+        ct[1] = 0;
+      }
     }
     if (w == c0) S.act[0] = false;
     if (w == c0 + 1) S.act[1] = false;

@@ -53,6 +53,10 @@ struct LocalArgs {
   double w[LAGP_MAX_DIM];  // reciprocal lengthscales 1/d_k
   const double* dloc;      // nullable, M: per-location isotropic lengthscale (Cholesky form;
                            // a location whose entry is not > 0 is skipped, its status set to 0)
+  int32_t* counts;         // nullable, M x (n - n0) x 2: per greedy step, the search's work:
+                           // ray: Brent evaluations summed over the rays, the most of one ray;
+                           // mixed: candidates whose FP32 upper bound reached the threshold,
+                           // 16-candidate tiles re-scored in FP64; else: candidates scored, 0
 };
 
 // Arguments of the local MLE kernel (mle.hip) for one chunk of locations.
@@ -159,7 +163,8 @@ size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool 
 // locations then run in chunks that fit it and nothing is allocated.
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in, const lagp_params* P,
                     double* mean, double* s2, double* df, int32_t* sel_idx, double* diag, int32_t* status,
-                    void* stream, size_t ws_budget, void* ext_ws = nullptr, size_t ext_bytes = 0);
+                    void* stream, size_t ws_budget, void* ext_ws = nullptr, size_t ext_bytes = 0,
+                    int32_t* counts = nullptr);
 const char* set_error(const char* msg);
 
 }  // namespace lagp

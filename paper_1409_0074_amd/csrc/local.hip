@@ -59,13 +59,14 @@ struct Lds {
   double* rdir;  // R x p: clipped segment directions
   double* rval;  // R: best ALC along each ray
   double* rs;    // R: its s*
+  int* rev;      // R: Brent evaluations along each ray
   double* redv;  // 2 NW
   double* scal;  // 8 scalars
   int* redi;     // NW
   int* J;        // NP: ranks of the local design, selection order
   int* starts;   // R
   int* ints;     // 8 scalars
-  int* shortlist;  // 64: mixed form, candidates re-scored in FP64
+  int* shortlist;  // max(64, ncs/16): mixed form, the 16-candidate tiles re-scored in FP64
   int kzs;         // per-slot stride of kzb / wvb
   float* scr;      // ncs: mixed form, FP32 screened scores
   unsigned char* selm;  // ncs: 1 = not available (selected or padding)
@@ -107,13 +108,14 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool m
   take(sizeof(double) * P.R * p);          // rdir
   take(sizeof(double) * P.R);              // rval
   take(sizeof(double) * P.R);              // rs
+  take(sizeof(int) * P.R);                 // rev
   take(sizeof(double) * 2 * NW);           // redv
   take(sizeof(double) * 8);                // scal
   take(sizeof(int) * NW);                  // redi
   take(sizeof(int) * P.NP);                // J
   take(sizeof(int) * P.R);                 // starts
   take(sizeof(int) * 8);                   // ints
-  take(mixed ? sizeof(int) * 64 : 0);      // shortlist
+  take(mixed ? sizeof(int) * (ncs / 16 > 64 ? ncs / 16 : 64) : 0);  // shortlist (tiles)
   take(mixed ? sizeof(float) * ncs : 0);   // scr
   take(ncs);                               // selm
   P.bytes = o;
@@ -127,7 +129,9 @@ __device__ inline Lds carve(unsigned char* s, const LdsPlan& P) {
   L.Ki = D();
   L.kx = D(); L.h = D(); L.col = D(); L.wv = D(); L.gv = D(); L.yJ = D();
   L.x = D(); L.xj = D(); L.kzb = D(); L.wvb = D(); L.ra = D(); L.rdir = D();
-  L.rval = D(); L.rs = D(); L.redv = D(); L.scal = D();
+  L.rval = D(); L.rs = D();
+  L.rev = reinterpret_cast<int*>(s + P.off[k++]);
+  L.redv = D(); L.scal = D();
   L.redi = reinterpret_cast<int*>(s + P.off[k++]);
   L.J = reinterpret_cast<int*>(s + P.off[k++]);
   L.starts = reinterpret_cast<int*>(s + P.off[k++]);
@@ -543,16 +547,41 @@ __device__ __forceinline__ double alc_tile_exact(const LocalArgs& a, const Lds& 
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// One rounding in FP32 or FP64 (u32 + u64): the unit of the screen's bounds.
+constexpr double SCREEN_U = 0x1.00002p-24;
+
+// A float >= x for x >= 0 (finite or +inf): the nearest float, moved up one
+// unit when it fell below x.
+__device__ __forceinline__ float f32_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = __uint_as_float(__float_as_uint(f) + 1u);
+  return f;
+}
+
 // FP32 screen of every candidate at design size j on f32 MFMA (FP32
-// products and accumulation): the same ALC expression, from an FP32 copy of
-// the kernel rows and of Kinv.  Results go to scr[c] (-inf if unavailable).
+// products and accumulation) from FP32 copies of the kernel rows and of
+// K^{-1}: v = (1+g) - k_c^T K^{-1} k_c, cov = K(x_c,x) - h^T k_c (h =
+// K^{-1} k_x), and beside them S_c = sum_i r_i k_c[i] with r_i = sum_l
+// |K^{-1}_il|.  Every kernel value lies in [0, 1], so k^T |K^{-1}| k,
+// |h|^T k and the error terms of the FP64 scoring's own sums are all at most
+// S_c; running-error analysis of the two FP32 contractions (inputs rounded
+// once, at most 2j + 4 further roundings, each at most 2 units to allow for
+// truncating hardware, subnormals flushed) gives
+//   |v_FP32 - v_FP64|     <= (4j + 16) u S_c + 4 u (1 + g) + A
+//   |cov_FP32 - cov_FP64| <= (4j + 16) u S_c + 2 u (|K(x_c,x)| + |cov|) + A
+// with u one rounding of either precision and A = 2^-100 (1 + sum_i r_i)
+// for flushed subnormals.  From these the screen writes an upper bound of the
+// candidate's FP64 criterion to scr[c] (rounded up; +inf when v may be <= 0,
+// -inf if unavailable) and returns, per thread, the two largest lower
+// bounds.  A taken candidate whose v may be <= 0 also gets +inf, so that its
+// tile is re-scored and the FP64 form's VNONPOS flag is reproduced.
 // Lane layout of v_mfma_f32_16x16x4f32 (gfx950): A[i][k] from lane 16k + i,
 // B[k][n] from lane 16k + n, D[i][n] in register i%4 of lane 16(i/4) + n.
 // K-chunk (I', c) holds rows 16I' + 4g + c in lane quarter g, so register r
 // of row block I (rows 16I + 4g + r) pairs with chunk (I, r) in the epilogue.
 template <int NP>
-__device__ __forceinline__ void screen_f32(const LocalArgs& a, const Lds& L, int LD, const float* Kc32, const double* kxc, int j,
-                           float* scr) {
+__device__ __forceinline__ Best screen_f32(const LocalArgs& a, const Lds& L, int LD, const float* Kc32,
+                                           const double* kxc, int j, float* scr) {
   constexpr int RBMAX = NP / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g4 = lane >> 4, cl = lane & 15;
@@ -560,6 +589,9 @@ __device__ __forceinline__ void screen_f32(const LocalArgs& a, const Lds& L, int
   const int ncs = a.ncs;
   const int ntiles = ncs >> 4;
   const float one_g = (float)(1.0 + a.g);
+  const double absl = L.scal[4];
+  const double cterm = (4.0 * j + 16.0) * SCREEN_U;
+  Best lo2 = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
   for (int t = wave; t < ntiles; t += NW) {
     const int c = (t << 4) + cl;
     float b[RBMAX][4];
@@ -570,7 +602,7 @@ __device__ __forceinline__ void screen_f32(const LocalArgs& a, const Lds& L, int
         const int row = 16 * I + 4 * g4 + r;
         b[I][r] = (I < nrb && row < j) ? Kc32[(int64_t)row * ncs + c] : 0.0f;
       }
-    float qf = 0.0f, cv = 0.0f;
+    float qf = 0.0f, cv = 0.0f, sa = 0.0f;
 #pragma unroll
     for (int I = 0; I < RBMAX; ++I) {
       if (I < nrb) {
@@ -584,8 +616,10 @@ __device__ __forceinline__ void screen_f32(const LocalArgs& a, const Lds& L, int
               acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)arow[16 * I2 + r], b[I2][r], acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+          const int row = 16 * I + 4 * g4 + r;
           qf = __builtin_fmaf(b[I][r], acc[r], qf);
-          cv = __builtin_fmaf((float)L.h[16 * I + 4 * g4 + r], b[I][r], cv);
+          cv = __builtin_fmaf((float)L.h[row], b[I][r], cv);
+          sa = __builtin_fmaf((float)L.wv[row], b[I][r], sa);
         }
       }
     }
@@ -593,59 +627,102 @@ __device__ __forceinline__ void screen_f32(const LocalArgs& a, const Lds& L, int
     qf += __shfl_xor(qf, 32, 64);
     cv += __shfl_xor(cv, 16, 64);
     cv += __shfl_xor(cv, 32, 64);
+    sa += __shfl_xor(sa, 16, 64);
+    sa += __shfl_xor(sa, 32, 64);
     if (g4 == 0) {
-      float alc = -__builtin_huge_valf();
-      if (!L.selm[c]) {
-        const float v = one_g - qf;
-        const float cov = (float)kxc[c] - cv;
-        alc = v > 0.0f ? cov * cov / v : 0.0f;
+      float hi_f = -__builtin_huge_valf();
+      if (c < a.ncand) {
+        const double v = (double)(one_g - qf);
+        const double kx = kxc[c];
+        const double cov = (double)((float)kx - cv);
+        // S_c from its FP32 value: at most j + 3 roundings low
+        const double S = (double)sa * (1.0 + 0x1p-15);
+        const double dv = cterm * S + 4.0 * SCREEN_U * (1.0 + a.g) + absl;
+        const double dc = cterm * S + 2.0 * SCREEN_U * (fabs(kx) + fabs(cov)) + absl;
+        const bool vpos = v - dv > 0.0;  // then the FP64 v is > 0 as well
+        if (!L.selm[c]) {
+          double hi = __builtin_huge_val(), lo = 0.0;
+          if (vpos) {
+            const double ch = fabs(cov) + dc, cm = fmax(fabs(cov) - dc, 0.0);
+            hi = ch * ch / (v - dv) * (1.0 + 0x1p-40);
+            lo = cm * cm / (v + dv) * (1.0 - 0x1p-40);
+          }
+          hi_f = hi == hi ? f32_up(hi) : __builtin_huge_valf();
+          best_push(lo2, lo == lo ? lo : 0.0, c);
+        } else if (!vpos) {
+          hi_f = __builtin_huge_valf();
+        }
       }
-      scr[c] = alc;
+      scr[c] = hi_f;
     }
   }
+  return lo2;
 }
 
-// Mixed step: FP32 screen, then the rescore_k best screened candidates
-// re-scored exactly in FP64 (one exact tile per 16), argmax of the exact
-// values (ties to the smaller rank).
+// Mixed step.  The FP32 screen bounds every available candidate's FP64
+// criterion; let T be the second largest lower bound.  The candidates with
+// the best and the runner-up FP64 values both have values >= T (the two
+// candidates holding the two largest lower bounds reach T), hence upper
+// bounds >= T, so re-scoring in FP64 every 16-candidate tile that holds an
+// upper bound >= T finds the FP64 argmax (ties to the smaller rank among
+// equal values, which are all re-scored) and the FP64 runner-up value; the
+// other candidates of those tiles, pushed too, cannot displace either.  When
+// half the tiles or more qualify, all are re-scored by the FP64 form's own
+// loop (the same values).  L.ints[5] / L.ints[6] receive the candidates
+// whose upper bound reached T and the tiles re-scored.
 template <int NP>
 __device__ __forceinline__ Best score_mixed(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const float* Kc32,
                             const double* kxc, int j, int* vflag) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   float* scr = L.scr;
-  // h = Kinv k_x for the screen's covariance term
+  // h = K^{-1} k_x for the screen's covariance term, r = row sums of |K^{-1}|
   for (int i = tid; i < j; i += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < j; ++k) s = __builtin_fma(L.Ki[k * LD + i], L.kx[k], s);
+    double s = 0.0, r = 0.0;
+    for (int k = 0; k < j; ++k) {
+      const double kik = L.Ki[k * LD + i];
+      s = __builtin_fma(kik, L.kx[k], s);
+      r += fabs(kik);
+    }
     L.h[i] = s;
+    L.wv[i] = r * (1.0 + 0x1p-40);  // (j < 2^11 additions of non-negative terms)
   }
   __syncthreads();
-  screen_f32<NP>(a, L, LD, Kc32, kxc, j, scr);
-  __syncthreads();
-  // shortlist: K rounds of a block-wide argmax over the screened values
-  const int K = a.rescore_k;
-  for (int k = 0; k < K; ++k) {
-    Best b = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
-    for (int c = tid; c < a.ncs; c += blockDim.x) {
-      const float v = scr[c];
-      if (v != -__builtin_huge_valf()) best_push(b, (double)v, c);
-    }
-    block_best(L, b);
-    if (tid == 0) {
-      const int w = L.ints[0];
-      L.shortlist[k] = (w >= 0 && w < a.ncs) ? w : -1;
-      if (w >= 0 && w < a.ncs) scr[w] = -__builtin_huge_valf();
-    }
-    __syncthreads();
+  if (tid == 0) {
+    double r1 = 0.0;
+    for (int i = 0; i < j; ++i) r1 += L.wv[i];
+    L.scal[4] = 0x1p-100 * (1.0 + 2.0 * r1);
+    L.ints[5] = 0;
+    L.ints[7] = 0;
   }
-  // exact FP64 rescore of the shortlist, one tile of 16 per wave
+  __syncthreads();
+  const Best lo2 = screen_f32<NP>(a, L, LD, Kc32, kxc, j, scr);
+  block_best(L, lo2);  // L.scal[2]: the second largest lower bound
+  const double T = L.scal[2];
+  const int ntiles = a.ncs >> 4;
+  for (int t = tid; t < ntiles; t += blockDim.x) {
+    int hits = 0;
+    bool flag = false;
+    for (int u = 0; u < 16; ++u) {
+      const float h = scr[16 * t + u];
+      const bool in = h > -__builtin_huge_valf() && (double)h >= T;
+      flag |= in;
+      hits += (in && !L.selm[16 * t + u]) ? 1 : 0;
+    }
+    if (flag) L.shortlist[atomicAdd(&L.ints[7], 1)] = t;
+    if (hits) atomicAdd(&L.ints[5], hits);
+  }
+  __syncthreads();
+  const int nlist = L.ints[7];
+  const bool all = 2 * nlist >= ntiles;
+  if (tid == 0) L.ints[6] = all ? ntiles : nlist;
+  if (all) return score_exact<NP>(a, L, LD, Kc, kxc, j, vflag);
+  // the listed tiles in FP64, one per wave at a time (any order: the
+  // arg-max merge orders by value, then rank)
   Best best = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};
-  const int ntl = (K + 15) >> 4;
-  for (int t = wave; t < ntl; t += NW) {
-    const int slot = (t << 4) + (lane & 15);
-    const int c = slot < K ? L.shortlist[slot] : -1;
-    const double alc = alc_tile_exact<NP>(a, L, LD, Kc, kxc, j, c >= 0 ? c : 0, vflag);
-    if (lane < 16 && c >= 0) best_push(best, alc, c);
+  for (int t = wave; t < nlist; t += NW) {
+    const int c = (L.shortlist[t] << 4) + (lane & 15);
+    const double alc = alc_tile_exact<NP>(a, L, LD, Kc, kxc, j, c, vflag);
+    if (lane < 16 && !L.selm[c]) best_push(best, alc, c);
   }
   return best;
 }
@@ -868,7 +945,7 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
 // minimiser on lane t, its value in *fbest.
 template <int P>
 __device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, int LD, int j, const double* xi, int rid,
-                                              bool live, double* fbest, int* vflag) {
+                                              bool live, double* fbest, int* nev, int* vflag) {
   const double gold = 0x1.8722191a02d60p-2;  // (3 - sqrt 5)/2
   const double sqeps = 0x1p-26;              // sqrt(2^-52)
   const double tol = a.brent_tol;
@@ -937,6 +1014,7 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, 
     }
   }
   *fbest = fx;
+  *nev = (live && lane < RB) ? it + 1 : 0;  // objective evaluations, the first included
   return x;
 }
 
@@ -1022,8 +1100,10 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
     const double a0 = ray_alc_lanes<P>(a, L, LD, j, xi, my_rid, 0.0, my_valid, true, vflag);
     my_live = my_valid && my_tau > 0.0;
     double fb = 0.0;
-    const double xb = brent_lanes<P>(a, L, LD, j, xi, my_rid, my_live, &fb, vflag);
+    int nev = 0;
+    const double xb = brent_lanes<P>(a, L, LD, j, xi, my_rid, my_live, &fb, &nev, vflag);
     if (my_valid) {
+      L.rev[my_rid] = nev;
       double sst = 0.0, val = a0;
       if (my_live) {
         sst = xb;
@@ -1041,8 +1121,10 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
   __syncthreads();
   if (tid == 0) {
     double bv = -__builtin_huge_val(), sv = -__builtin_huge_val();
-    int br = 0;
+    int br = 0, esum = 0, emax = 0;
     for (int r = 0; r < ns; ++r) {
+      esum += L.rev[r];
+      emax = L.rev[r] > emax ? L.rev[r] : emax;
       const double vr = L.rval[r];
       if (vr > bv) {
         sv = bv; bv = vr; br = r;
@@ -1051,6 +1133,8 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
       }
     }
     L.ints[3] = br;
+    L.ints[5] = esum;
+    L.ints[6] = emax;
     L.scal[1] = bv;
     L.scal[2] = sv;
     L.scal[3] = L.rs[br];
@@ -1190,6 +1274,12 @@ void k_local(LocalArgs a) {
         double* dg = a.diag + ((int64_t)m * (n - a.n0) + (j - n0)) * 2;
         dg[0] = b1;
         dg[1] = b2;
+      }
+      if (tid == 0 && a.counts) {  // the step's search work (see LocalArgs::counts)
+        int32_t* ct = a.counts + ((int64_t)m * (n - a.n0) + (j - n0)) * 2;
+        const bool kept = MODE == MODE_RAY || MODE == MODE_MIXED;
+        ct[0] = kept ? L.ints[5] : nc - j;
+        ct[1] = kept ? L.ints[6] : 0;
       }
     }
   }
