@@ -71,8 +71,11 @@ extern "C" {
 #define LAGP_SCORING_CHOL 1    /* incremental Cholesky columns: u_c = L^{-1} k_J(x_c) grows by one
                                   entry per step, so a step costs O(j) per candidate instead of
                                   O(j^2); the same criterion and prediction to rounding (not bit
-                                  for bit).  Needs precision FP64, n <= 50 and ncand <= 1024
-                                  (ncand <= 512 when p > 8). */
+                                  for bit), with smaller FP64 error at small nuggets.  Needs
+                                  precision FP64 and exhaustive search.  Up to n = 50 and
+                                  ncand = 1024 (512 when p > 8) the columns stay on chip; larger
+                                  shapes keep them in a device workspace of about
+                                  8 (n + p) ncand bytes per resident workgroup. */
 
 /* per-location status bits */
 #define LAGP_STATUS_VNONPOS 1   /* a Schur complement v <= 0 was met; scored as 0 */

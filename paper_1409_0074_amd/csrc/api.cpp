@@ -90,8 +90,6 @@ int32_t check_params(const lagp_design* d, const lagp_params* P, int* rays) {
     if (P->brent_tol < 0.0 || !std::isfinite(P->brent_tol)) return fail(LAGP_EINVAL, "brent_tol must be finite");
     *rays = R;
   }
-  if (P->scoring == LAGP_SCORING_CHOL && !lagp::chol_supported(P->n, P->ncand, p, (size_t)max_lds_per_block()))
-    return fail(LAGP_EINVAL, "Cholesky scoring needs n <= 50 and ncand <= 1024 (ncand <= 512 when p > 8)");
   return LAGP_OK;
 }
 
@@ -279,6 +277,23 @@ lagp::LocalArgs local_args(const lagp_design* d, const lagp_params* P, int rays,
   return a;
 }
 
+// Cholesky scoring: the on-chip kernel where the columns fit in registers and
+// LDS, else the streaming kernel, whose workspace is a fixed number of slots
+// (one per resident workgroup of its persistent grid, at most half the
+// budget) rather than a per-location size.  Returns the slots' bytes.
+bool chol_onchip(const lagp_design* d, const lagp_params* P) {
+  return chol_supported(P->n, P->ncand, d->p, (size_t)max_lds_per_block()) && !chol_stream_forced();
+}
+
+size_t chol_stream_fixed(const lagp_design* d, const lagp_params* P, size_t budget, int* slots) {
+  *slots = 0;
+  if (P->scoring != LAGP_SCORING_CHOL || chol_onchip(d, P)) return 0;
+  const size_t sb = chol_stream_slot_bytes(P->n, P->ncand, d->p);
+  const int64_t k = std::min<int64_t>(chol_stream_max_slots(P->ncand), std::max<int64_t>(1, (int64_t)(budget / 2 / sb)));
+  *slots = (int)k;
+  return (sb * (size_t)k + 255) & ~size_t(255);
+}
+
 // Bytes run_predict allocates for M locations under a workspace cap, and the
 // per-location figure (kNN buffers when candidates are not given, the kernel
 // rows, k(x_c, x), the candidates' coordinates, the starting-inverse scratch
@@ -307,8 +322,11 @@ size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool 
                                size_t ws_budget) {
   if (M <= 0) return 0;
   const size_t shared = have_cand ? 0 : knn2_shared_bytes(d->N, d->p, P->ncand);
-  return predict_per_location_bytes(d, P, have_cand) * (size_t)predict_chunk(d, P, have_cand, M, ws_budget) +
-         shared + 9 * 256;  // 9 aligned sections
+  int slots = 0;
+  const size_t fixed = chol_stream_fixed(d, P, ws_budget, &slots);
+  return predict_per_location_bytes(d, P, have_cand) *
+             (size_t)predict_chunk(d, P, have_cand, M, ws_budget > fixed ? ws_budget - fixed : 0) +
+         shared + fixed + 10 * 256;  // 10 aligned sections
 }
 
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
@@ -346,10 +364,12 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const size_t b_xc = chol ? 0 : sizeof(double) * (size_t)ncs * p;
   const size_t b_chol = chol ? 0 : sizeof(double) * 2 * (size_t)n0 * n0;
   const size_t shared = cand_in ? 0 : knn2_shared_bytes(d->N, p, nc);
-  int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget);
-  if (ext_ws) {  // as many locations as the given workspace holds (9 sections, each aligned)
+  int cw_slots = 0;
+  const size_t b_cw = chol_stream_fixed(d, P, ext_ws ? ext_bytes : ws_budget, &cw_slots);
+  int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget > b_cw ? ws_budget - b_cw : 0);
+  if (ext_ws) {  // as many locations as the given workspace holds (10 sections, each aligned)
     const size_t per = b_knn + b_cand + b_kc + b_kc32 + b_kxc + b_xc + b_chol + sizeof(int32_t);
-    const size_t fixed = shared + 9 * 256;
+    const size_t fixed = shared + b_cw + 10 * 256;
     if (ext_bytes < fixed + per)
       return fail(LAGP_ENOMEM, "the workspace of one location (" + std::to_string(fixed + per) +
                                    " bytes) exceeds the " + std::to_string(ext_bytes) + "-byte scratch");
@@ -361,7 +381,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
                o_kc32 = o_kc + al(b_kc * chunk), o_kxc = o_kc32 + al(b_kc32 * chunk),
                o_xc = o_kxc + al(b_kxc * chunk), o_chol = o_xc + al(b_xc * chunk),
                o_st = o_chol + al(b_chol * chunk), o_sub = o_st + al(sizeof(int32_t) * chunk),
-               total = o_sub + shared;
+               o_cw = o_sub + al(shared), total = o_cw + b_cw;
   char* base = nullptr;
   if (ext_ws) {
     if (total > ext_bytes) return fail(LAGP_ENOMEM, "internal: workspace layout exceeds the scratch");
@@ -383,6 +403,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.kxc = reinterpret_cast<double*>(base + o_kxc);
     a.Xc = reinterpret_cast<double*>(base + o_xc);
     a.chol = reinterpret_cast<double*>(base + o_chol);
+    a.cw = reinterpret_cast<double*>(base + o_cw);
     a.mean = mean + m0;
     a.s2 = s2 + m0;
     a.df = df + m0;
@@ -390,7 +411,8 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.diag = diag ? diag + m0 * (int64_t)(n - n0) * 2 : nullptr;
     a.counts = counts ? counts + m0 * (int64_t)(n - n0) * 2 : nullptr;
     a.status = status ? status + m0 : reinterpret_cast<int32_t*>(base + o_st);
-    LAGP_HIP(chol ? lagp::launch_chol(a, s) : lagp::launch_local(a, s));
+    LAGP_HIP(!chol ? lagp::launch_local(a, s)
+                   : cw_slots ? lagp::launch_chol_stream(a, cw_slots, s) : lagp::launch_chol(a, s));
   }
   return LAGP_OK;
 }
@@ -518,13 +540,16 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
   // starting-inverse scratch, status) for the ray and nearest-neighbour searches
   const size_t b_loc = chol ? 0 : lagp::predict_per_location_bytes(d, P, true);
   const size_t per = b_knn + b_cand + b_sel + b_st + b_th + b_loc;
-  const int64_t chunk = std::min<int64_t>(M, std::max<int64_t>(lagp::KNN_QB, (int64_t)(workspace_budget() / per)));
+  int cw_slots = 0;  // Cholesky scoring past the on-chip sizes: the streaming kernel's slots
+  const size_t b_cw = lagp::chol_stream_fixed(d, P, workspace_budget(), &cw_slots);
+  const size_t budget = workspace_budget() > b_cw ? workspace_budget() - b_cw : 0;
+  const int64_t chunk = std::min<int64_t>(M, std::max<int64_t>(lagp::KNN_QB, (int64_t)(budget / per)));
   Workspace ws;
   ws.s = s;
   const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_sel = o_cand + al(b_cand * chunk),
                o_st = o_sel + al(b_sel * chunk), o_th = o_st + al(b_st * chunk), o_loc = o_th + al(b_th * chunk),
                o_sub = o_loc + al(b_loc * chunk) + 4 * 256,
-               total = o_sub + (cand_in ? 0 : lagp::knn2_shared_bytes(d->N, p, nc));
+               o_cw = o_sub + al(cand_in ? 0 : lagp::knn2_shared_bytes(d->N, p, nc)), total = o_cw + b_cw;
   LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
   char* base = reinterpret_cast<char*>(ws.ptr);
   for (int64_t m0 = 0; m0 < M; m0 += chunk) {
@@ -554,7 +579,10 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
     a.df = df + m0;
     a.sel = sel;
     a.status = st1;
-    auto search = [&]() { return chol ? lagp::launch_chol(a, s) : lagp::launch_local(a, s); };
+    a.cw = reinterpret_cast<double*>(base + o_cw);
+    auto search = [&]() {
+      return !chol ? lagp::launch_local(a, s) : cw_slots ? lagp::launch_chol_stream(a, cw_slots, s) : lagp::launch_chol(a, s);
+    };
     LAGP_HIP(search());
     lagp::MleArgs e{};
     e.X = d->X;

@@ -53,6 +53,7 @@ struct LocalArgs {
   double w[LAGP_MAX_DIM];  // reciprocal lengthscales 1/d_k
   const double* dloc;      // nullable, M: per-location isotropic lengthscale (Cholesky form;
                            // a location whose entry is not > 0 is skipped, its status set to 0)
+  double* cw;              // Cholesky form past the on-chip sizes: slots x chol_stream_slot_bytes
   int32_t* counts;         // nullable, M x (n - n0) x 2: per greedy step, the search's work:
                            // ray: Brent evaluations summed over the rays, the most of one ray;
                            // mixed: candidates whose FP32 upper bound reached the threshold,
@@ -127,6 +128,13 @@ hipError_t launch_local(const LocalArgs& a, hipStream_t s);
 // shape fits its kernels, and the launch (no workspace beyond the arguments).
 bool chol_supported(int n, int ncand, int p, size_t lds_max);
 hipError_t launch_chol(const LocalArgs& a, hipStream_t s);
+// The same search with the columns in a device workspace (cholws.hip), any
+// n <= LAGP_MAX_N and ncand <= LAGP_MAX_NCAND: a persistent grid of at most
+// `slots` workgroups, each owning chol_stream_slot_bytes of a.cw.
+size_t chol_stream_slot_bytes(int n, int ncand, int p);
+int chol_stream_max_slots(int ncand);
+bool chol_stream_forced();  // test hook: LAGP_CHOL_FORCE_STREAM=1
+hipError_t launch_chol_stream(const LocalArgs& a, int slots, hipStream_t s);
 
 // Local MLE of the lengthscale and the prediction under it (mle.hip).
 size_t mle_lds_bytes(int n, int p);

@@ -669,12 +669,23 @@ __device__ __forceinline__ Best screen_f32(const LocalArgs& a, const Lds& L, int
 // other candidates of those tiles, pushed too, cannot displace either.  When
 // half the tiles or more qualify, all are re-scored by the FP64 form's own
 // loop (the same values).  L.ints[5] / L.ints[6] receive the candidates
-// whose upper bound reached T and the tiles re-scored.
+// whose upper bound reached T and the tiles re-scored.  Conditioning only
+// worsens as the design grows, so once the screen has failed to rule out
+// half the tiles the caller passes screen = false for the location's later
+// steps, which are then scored in FP64 directly (the same values again):
+// `screen` is cleared here for every thread alike.
 template <int NP>
 __device__ __forceinline__ Best score_mixed(const LocalArgs& a, const Lds& L, int LD, const double* Kc, const float* Kc32,
-                            const double* kxc, int j, int* vflag) {
+                            const double* kxc, int j, bool& screen, int* vflag) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   float* scr = L.scr;
+  if (!screen) {  // the screen ruled out too little at an earlier step: FP64 scoring of every tile
+    if (tid == 0) {
+      L.ints[5] = a.ncand - j;
+      L.ints[6] = a.ncs >> 4;
+    }
+    return score_exact<NP>(a, L, LD, Kc, kxc, j, vflag);
+  }
   // h = K^{-1} k_x for the screen's covariance term, r = row sums of |K^{-1}|
   for (int i = tid; i < j; i += blockDim.x) {
     double s = 0.0, r = 0.0;
@@ -712,8 +723,9 @@ __device__ __forceinline__ Best score_mixed(const LocalArgs& a, const Lds& L, in
     if (hits) atomicAdd(&L.ints[5], hits);
   }
   __syncthreads();
-  const int nlist = L.ints[7];
+  const int nlist = L.ints[7];  // (read by every thread after the barrier)
   const bool all = 2 * nlist >= ntiles;
+  screen = !all;
   if (tid == 0) L.ints[6] = all ? ntiles : nlist;
   if (all) return score_exact<NP>(a, L, LD, Kc, kxc, j, vflag);
   // the listed tiles in FP64, one per wave at a time (any order: the
@@ -1246,6 +1258,7 @@ void k_local(LocalArgs a) {
 
   int vflag = 0;
   int done = n0;  // design size reached
+  bool screen = true;  // mixed form: the FP32 screen still rules out candidates
   if (pd) {
     for (int j = n0; j < n; ++j) {
       int cs;
@@ -1257,9 +1270,9 @@ void k_local(LocalArgs a) {
         b1 = b2 = 0.0;
       } else {
         Best b;
-        if constexpr (MODE == MODE_MIXED)
-          b = score_mixed<NP>(a, L, LD, Kc, Kc32, kxc, j, &vflag);
-        else
+        if constexpr (MODE == MODE_MIXED) {
+          b = score_mixed<NP>(a, L, LD, Kc, Kc32, kxc, j, screen, &vflag);
+        } else
           b = score_exact<NP>(a, L, LD, Kc, kxc, j, &vflag);
         block_best(L, b);
         cs = L.ints[0];

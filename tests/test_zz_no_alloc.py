@@ -47,6 +47,7 @@ def _call(lg, d, fn, XX, prm):
 
 @pytest.mark.parametrize("case,M1,M2", [
     ("chol", 1700, 300),     # Cholesky scoring: about 1,150 locations per scratch chunk here
+    ("chol_stream", 700, 60),  # n = 100: columns streamed from slots in the scratch, ~550 per chunk
     ("partinv", 260, 37),    # partitioned inverse: about 115 per chunk (kernel rows in the workspace)
     ("ray", 150, 20),
     ("mixed", 120, 9),
@@ -56,6 +57,8 @@ def test_noalloc_equals_predict_twice(env, case, M1, M2):
     prm = W.Params(n0=6, n=50, ncand=1000, d=(0.5,) * 8, g=1e-6)
     if case == "chol":
         prm = prm.replace(scoring=W.SCORING_CHOL)
+    elif case == "chol_stream":
+        prm = prm.replace(scoring=W.SCORING_CHOL, n=100)
     elif case == "ray":
         prm = prm.replace(search=W.SEARCH_RAY, numrays=8)
     elif case == "mixed":
