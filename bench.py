@@ -88,6 +88,32 @@ def chol_flops(n0: int, n: int, ncand: int, p: int) -> float:
     return float(upd + score)
 
 
+def chol_alg_flops(n0: int, n: int, ncand: int, p: int) -> float:
+    """Algorithmic FLOPs of the Cholesky-column search per location: after
+    design point j is taken, each of the ncand - j - 1 free candidates needs
+    the length-j inner product u_t^T u_c (2 j) and the kernel value's
+    weighted squared distance (3 p); exp is not counted."""
+    return float(sum((ncand - j - 1) * (2.0 * j + 3.0 * p) for j in range(n - 1)))
+
+
+def chol_stream_bytes(n: int, ncand: int) -> float:
+    """Algorithmic device-memory bytes of the streamed Cholesky columns per
+    location: after design point j is taken, each of the ncand - j - 1 free
+    columns is read (j entries) and gains one entry, 8 (j + 1) bytes."""
+    return float(sum(8.0 * (j + 1) * (ncand - j - 1) for j in range(n - 1)))
+
+
+def ray_flops(evals, n0: int, ncand: int, p: int) -> float:
+    """Work of the ray search from the Brent evaluations each step actually
+    made (evals: locations x steps, summed over the step's rays): an
+    evaluation at design size j costs j kernel values (3 p + 20: distance and
+    exp), K^{-1} k_z (2 j^2) and the two inner products (4 j); each step adds
+    the snap's 3 p N' distance FLOPs."""
+    j = n0 + np.arange(evals.shape[1], dtype=np.float64)
+    per_eval = 2.0 * j * j + j * (3.0 * p + 20.0) + 4.0 * j
+    return float((evals * per_eval[None, :]).sum() + evals.size * 3.0 * p * ncand)
+
+
 def time_steps(fn, steps: int, events_per_step: int):
     """Run fn(ev) steps times; fn records events_per_step+1 torch events on the
     current stream.  Returns per-phase mean ms and total wall ms."""
@@ -152,41 +178,106 @@ def serving(nreq: int):
             "arrivals": "open-loop Poisson at half the burst throughput", "budget_bytes": budget, "slots": slots}
 
 
-def grid(M: int):
-    """2-d grid workload (N = 1e6 grid, n = 100, 4000 candidates, d = 0.05) on
-    the first M locations: FP64 and mixed rates, and the mixed form's
-    agreement with FP64."""
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 (matrix)
+
+
+def grid_leg(M_chol: int, M_sub: int, steps: int):
+    """The grid workload: a 1000 x 1000 grid design on [0,1]^2 (N = 1e6) with
+    the 2-d bump response, n = 100, N' = 4000, d = 0.05, g = 1e-6,
+    exhaustive search.  FP64 by Cholesky columns streamed from a device
+    workspace over M_chol locations (1e5: the whole predictive set); the
+    partitioned-inverse FP64 form and the mixed form (certified FP32 screen,
+    FP64 re-score) over the first M_sub of them.  Each with the roofline of
+    its search kernel (time from events around the search alone)."""
     import torch
 
     import paper_1409_0074_amd as lg
     from paper_1409_0074_amd import workloads as W
 
-    w = W.grid2d(M=M)
-    d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
-    XX = torch.from_numpy(w.XX).cuda()
-    out = {"workload": w.name, "M": M}
+    w = W.grid2d(M=M_chol)
+    prm = w.params
+    n0, n, nc = prm.n0, prm.n, prm.ncand
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(w.X).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    XX = torch.from_numpy(w.XX).to(dev)
+    design = lg.lagp_design_create(X, y)
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = {"workload": f"grid2d_N1000000_n100_cand4000", "M_cholesky": M_chol, "M_partitioned_and_mixed": M_sub,
+           "rows": {}}
     res = {}
-    for tag, prec in (("fp64", W.PREC_FP64), ("mixed", W.PREC_MIXED)):
-        P = lg.make_params(w.params, precision=prec)
-        d.predict(XX[:64], P)
+    for tag, M, kw in (("fp64_cholesky", M_chol, dict(scoring=W.SCORING_CHOL)),
+                       ("fp64_partitioned_inverse", M_sub, {}),
+                       ("mixed", M_sub, dict(precision=W.PREC_MIXED))):
+        P = lg.make_params(prm, **kw)
+        XXm = XX[:M]
+        cand = torch.empty((M, nc), dtype=torch.int32, device=dev)
+        mean, s2, df = torch.empty(M, **f64), torch.empty(M, **f64), torch.empty(M, **f64)
+        status = torch.empty(M, dtype=torch.int32, device=dev)
+        sel = torch.empty((M, n), dtype=torch.int32, device=dev)
+        counts = torch.empty((M, n - n0, 2), dtype=torch.int32, device=dev)
+
+        def gstep(ev):
+            ev[0].record()
+            lg.lagp_candidates(design, XXm, nc, cand)
+            ev[1].record()
+            lg.lagp_predict_counts(design, XXm, cand, P, mean, s2, df, sel, None, status, counts)
+            ev[2].record()
+
+        lg.lagp_predict(design, XXm[:64], P, mean[:64], s2[:64], df[:64])  # warm-up
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        o = d.predict(XX, P, diag=False)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res[tag] = {k: v.cpu().numpy() for k, v in o.items() if v is not None}
-        out[tag] = {"pred_per_s": round(M / dt, 2), "seconds": round(dt, 3)}
-    d.close()
-    f, m = res["fp64"], res["mixed"]
+        (tk, tl), wall = time_steps(gstep, steps, 2)
+        ms = wall / steps
+        row = {"M": M, "pred_per_s": round(M / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+               "phases_ms": {"knn": round(float(tk), 3), "local_design": round(float(tl), 3)},
+               "status_nonzero": int((status != 0).sum().cpu())}
+        if tag == "fp64_cholesky":
+            b = chol_stream_bytes(n, nc) * M
+            gbs = b / (tl / 1e3) / 1e9
+            row["roofline"] = {"bound": "hbm", "kernel": "k_cholw (Cholesky columns streamed from a workspace)",
+                               "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                               "work": f"sum_j 8 (j + 1)(ncand - j - 1) = {chol_stream_bytes(n, nc):.4g} "
+                                       f"B/location x {M} locations per launch"}
+        else:
+            fl = scoring_flops(n0, n, nc) * M
+            tf = fl / (tl / 1e3) / 1e12
+            if tag == "mixed":
+                ct = counts.cpu().numpy()
+                tiles = (nc + 15) // 16
+                free = nc - (n0 + np.arange(n - n0))
+                row["certified_shortlist"] = {
+                    "candidates_mean": round(float(ct[:, :, 0].mean()), 1),
+                    "candidates_max": int(ct[:, :, 0].max()),
+                    "fraction_of_free_candidates": round(float((ct[:, :, 0] / free[None, :]).mean()), 4),
+                    "tiles_rescored_fraction": round(float(ct[:, :, 1].mean() / tiles), 4)}
+                row["roofline"] = {"bound": "mfma", "kernel": "k_local (mixed: FP32 screen + FP64 re-score)",
+                                   "achieved": round(tf, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                                   "work": f"sum_j 2 j^2 (ncand - j) = {scoring_flops(n0, n, nc):.4g} FLOP/location "
+                                           f"(the screen's contraction) x {M} locations per launch"}
+            else:
+                row["roofline"] = {"bound": "mfma", "kernel": "k_local (exhaustive, partitioned inverse)",
+                                   "achieved": round(tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(tf / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                                   "work": f"sum_j 2 j^2 (ncand - j) = {scoring_flops(n0, n, nc):.4g} FLOP/location "
+                                           f"x {M} locations per launch (16.6 FLOP/B: above the FP64 ridge)"}
+        out["rows"][tag] = row
+        res[tag] = {"sel": sel[:M_sub].cpu().numpy(), "mean": mean[:M_sub].cpu().numpy(),
+                    "s2": s2[:M_sub].cpu().numpy()}
+        del cand, counts
+    lg.lagp_design_destroy(design)
     floor = 1e-6 * np.sqrt(np.mean(w.y ** 2))
-    e_mu = np.abs(m["mean"] - f["mean"]) / np.maximum(np.abs(f["mean"]), floor)
-    e_s2 = np.abs(m["s2"] - f["s2"]) / np.abs(f["s2"])
-    out["mixed_vs_fp64"] = {"identical_designs": float(np.mean(np.all(m["sel"] == f["sel"], axis=1))),
-                            "mean_relerr_max": float(e_mu.max()), "s2_relerr_max": float(e_s2.max()),
-                            "mean_within_1e-5": float(np.mean(e_mu <= 1e-5)),
-                            "s2_within_1e-5": float(np.mean(e_s2 <= 1e-5))}
-    scoring = scoring_flops(w.params.n0, w.params.n, w.params.ncand) * M
-    out["fp64"]["scoring_tflops"] = round(scoring / out["fp64"]["seconds"] / 1e12, 3)
+
+    def agree(a, b):
+        e_mu = np.abs(a["mean"] - b["mean"]) / np.maximum(np.abs(b["mean"]), floor)
+        e_s2 = np.abs(a["s2"] - b["s2"]) / np.abs(b["s2"])
+        return {"identical_designs": float(np.mean(np.all(a["sel"] == b["sel"], axis=1))),
+                "mean_relerr_max": float(e_mu.max()), "s2_relerr_max": float(e_s2.max()),
+                "mean_within_1e-5": float(np.mean(e_mu <= 1e-5)), "s2_within_1e-5": float(np.mean(e_s2 <= 1e-5))}
+
+    out["mixed_vs_fp64_partitioned"] = agree(res["mixed"], res["fp64_partitioned_inverse"])
+    out["fp64_partitioned_vs_cholesky"] = agree(res["fp64_partitioned_inverse"], res["fp64_cholesky"])
     return out
 
 
@@ -353,8 +444,10 @@ def main() -> int:
     ap.add_argument("--no-sec51", action="store_true", help="skip the Sec. 5.1 2-d experiment (Table 1 rows)")
     ap.add_argument("--no-ray-sweep", action="store_true", help="skip the rays-per-step sweep R = 1..p")
     ap.add_argument("--no-prescale", action="store_true", help="skip the pre-scaling leg (anisotropic 8-d)")
-    ap.add_argument("--grid", action="store_true", help="also run the 2-d grid workload, FP64 and mixed")
-    ap.add_argument("--grid-M", type=int, default=2000)
+    ap.add_argument("--no-grid", action="store_true", help="skip the 2-d grid workload (n = 100, N' = 4000)")
+    ap.add_argument("--grid-M", type=int, default=100000, help="grid locations for the Cholesky FP64 form")
+    ap.add_argument("--grid-M-sub", type=int, default=10000,
+                    help="grid locations for the partitioned-inverse FP64 and mixed forms")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run 3 plain device-to-device copies of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -415,7 +508,9 @@ def main() -> int:
 
     p = int(w.X.shape[1])
     cflops = chol_flops(prm.n0, prm.n, nc, p)
-    achieved = cflops * M / (t_local / 1e3) / 1e12
+    aflops = chol_alg_flops(prm.n0, prm.n, nc, p)
+    achieved = aflops * M / (t_local / 1e3) / 1e12
+    impl_tf = cflops * M / (t_local / 1e3) / 1e12
     result = {
         "metric": "local-GP predictions/sec at N=1e6, n=50 (exhaustive vs ray); p99 latency",
         "value": round(value, 2),
@@ -440,8 +535,11 @@ def main() -> int:
         "roofline": {"bound": "alu", "kernel": "k_chol (exhaustive search, Cholesky scoring)",
                      "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic("k_chol", M),
-                     "work": f"{cflops:.4g} FLOP/location (inner products, kernel values, updates, scores) "
-                             f"x {M} locations per launch"},
+                     "work": f"sum_j (ncand - j - 1)(2 j + 3 p) = {aflops:.4g} FLOP/location (the inner products "
+                             f"u_t^T u_c and the kernel values' squared distances) x {M} locations per launch",
+                     "implementation": {"achieved": round(impl_tf, 3), "frac": round(impl_tf / FP64_PEAK_TFLOPS, 4),
+                                        "work": f"{cflops:.4g} FLOP/location (also exp as 34 FLOP, the new "
+                                                f"entry, the updates of v, cov, q and the scores)"}},
         "status_nonzero": int((st != 0).sum()),
     }
     if calib is not None:
@@ -516,21 +614,46 @@ def main() -> int:
             "rmse_vs_truth": rmse(mm), "fixed_d_rmse_vs_truth": rmse(ex_mean)}
 
     if not args.no_ray:
-        Pr = lg.make_params(prm, search=W.SEARCH_RAY, numrays=10)
+        R = 10
+        Pr = lg.make_params(prm, search=W.SEARCH_RAY, numrays=R)
+        counts = torch.empty((M, prm.n - prm.n0, 2), dtype=torch.int32, device=dev)
 
         def rstep(ev):
-            step(ev, P=Pr)
+            ev[0].record()
+            lg.lagp_candidates(design, XX, nc, cand)
+            ev[1].record()
+            lg.lagp_predict_counts(design, XX, cand, Pr, mean, s2, df, None, None, status, counts)
+            ev[2].record()
 
         rstep(dummy)
         torch.cuda.synchronize()
         (rk, rl), rwall = time_steps(rstep, args.ray_steps, 2)
         rms = rwall / args.ray_steps
         ry_mean = mean.cpu().numpy()
+        ct = counts.cpu().numpy()
+        ev_step, ev_ray_max = ct[:, :, 0].astype(np.float64), ct[:, :, 1]
+        rflops = ray_flops(ev_step, prm.n0, nc, p)
+        r_tf = rflops / (rl / 1e3) / 1e12
         rmse = lambda a: float(np.sqrt(np.mean((a - w.truth) ** 2)))  # noqa: E731
-        result["ray"] = {"value": round(M / (rms / 1e3), 2), "unit": "predictions/s", "ms_per_step": round(rms, 3),
-                         "numrays": 10, "phases_ms": {"knn": round(float(rk), 3), "local_design": round(float(rl), 3)},
-                         "rmse_vs_truth": rmse(ry_mean), "exhaustive_rmse_vs_truth": rmse(ex_mean),
-                         "rmse_ray_vs_exhaustive": float(np.sqrt(np.mean((ry_mean - ex_mean) ** 2)))}
+        result["ray"] = {
+            "value": round(M / (rms / 1e3), 2), "unit": "predictions/s", "ms_per_step": round(rms, 3),
+            "numrays": R, "phases_ms": {"knn": round(float(rk), 3), "local_design": round(float(rl), 3)},
+            "rmse_vs_truth": rmse(ry_mean), "exhaustive_rmse_vs_truth": rmse(ex_mean),
+            "rmse_ray_vs_exhaustive": float(np.sqrt(np.mean((ry_mean - ex_mean) ** 2))),
+            "brent_evaluations": {"per_step_mean": round(float(ev_step.mean()), 2),
+                                  "per_step_max": int(ev_step.max()),
+                                  "per_ray_mean": round(float(ev_step.mean()) / R, 2),
+                                  "per_ray_max": int(ev_ray_max.max()),
+                                  "slowest_ray_over_mean_per_step": round(float((ev_ray_max / np.maximum(
+                                      ev_step / R, 1e-9)).mean()), 3)},
+            # Brent's iterations are short dependent chains of FP64 vector
+            # work (kernel values, K^{-1} k_z, inner products): FP64 VALU bound
+            "roofline": {"bound": "alu", "kernel": "k_local (ray search, 10 rays)", "achieved": round(r_tf, 3),
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(r_tf / FP64_PEAK_TFLOPS, 4),
+                         "traffic": None,
+                         "work": f"sum over steps of E_j (2 j^2 + j (3 p + 20) + 4 j) + 3 p N' with E_j the "
+                                 f"kernel's own Brent evaluations: {rflops / M:.4g} FLOP/location x {M} "
+                                 f"locations per launch"}}
 
     lg.lagp_design_destroy(design)
     del X, y, XX, cand
@@ -542,8 +665,8 @@ def main() -> int:
         result["prescale"] = prescale_leg(args.ray_steps)
     if not args.no_serving:
         result["serving"] = serving(args.serving_requests)
-    if args.grid:
-        result["grid"] = grid(args.grid_M)
+    if not args.no_grid:
+        result["grid"] = grid_leg(args.grid_M, min(args.grid_M, args.grid_M_sub), 1)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w, prm.replace(scoring=W.SCORING_CHOL))
     print(json.dumps(result), flush=True)
