@@ -20,6 +20,8 @@
 // The kernel rows K(x_{J_i}, x_c) live in a per-location workspace (one row
 // appended per step).  Everything except the MFMA scoring contraction uses
 // index-order fma sums, so those values are reproducible bit for bit.
+#include <cstdlib>
+
 #include "dev_math.h"
 #include "lagp_internal.h"
 
@@ -84,17 +86,20 @@ struct LdsPlan {
   size_t bytes;
 };
 
-// R > 0: ray scratch for R rays; mixed: screened scores and shortlist.
-__host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool mixed) {
+// R > 0: ray scratch for R rays (tile: all rays of a step on one wave, no
+// per-wave vectors); mixed: screened scores and shortlist.
+__host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool mixed, bool tile = false) {
   LdsPlan P;
   P.NP = n <= 64 ? 64 : 128;
   // exact scoring and rays read rows below 4 ceil(j/4); the FP32 screen
   // reads whole 16-row blocks
   P.NR = mixed ? (n + 15) & ~15 : (n + 3) & ~3;
   P.KZS = P.NP + 2;
-  P.LD = P.NP + 1;  // odd: the 16 rows of an MFMA operand fall in distinct banks
+  // odd: the 16 rows of an MFMA operand fall in distinct banks (the tile ray
+  // form, short of LDS, strides by the rows it uses)
+  P.LD = (tile ? P.NR : P.NP) + 1;
   P.R = R < 1 ? 0 : R;
-  const bool ray = R > 0;
+  const bool ray = R > 0 && !tile;
   size_t o = 0;
   int k = 0;
   auto take = [&](size_t b) { P.off[k++] = o; o = align16(o + b); };
@@ -102,7 +107,8 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool m
   for (int i = 0; i < 6; ++i) take(sizeof(double) * P.NP);  // kx h col wv gv yJ
   take(sizeof(double) * LAGP_MAX_DIM);     // x
   take(sizeof(double) * n * p);            // xj
-  take(ray ? sizeof(double) * NW * RB * P.KZS : 0);  // kzb
+  // kzb: per-wave ray vectors, or the tile form's kernel columns (16 chunks x 64 lanes)
+  take(ray ? sizeof(double) * NW * RB * P.KZS : (tile && R > 0 ? sizeof(double) * 64 * ((n + 3) / 4) : 0));
   take(ray ? sizeof(double) * NW * RB * P.KZS : 0);  // wvb
   take(sizeof(double) * P.R * p);          // ra
   take(sizeof(double) * P.R * p);          // rdir
@@ -344,7 +350,8 @@ __device__ __forceinline__ void block_best(const Lds& L, Best b) {
   __syncthreads();
   if (threadIdx.x == 0) {
     Best r = {L.redv[0], L.redv[1], L.redi[0]};
-    for (int w = 1; w < NW; ++w) {
+    const int nw = blockDim.x >> 6;
+    for (int w = 1; w < nw; ++w) {
       Best o = {L.redv[2 * w], L.redv[2 * w + 1], L.redi[w]};
       r = best_merge(r, o);
     }
@@ -953,11 +960,13 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
 // steps).  A parabolic step that would land within 2 tol1 of an end becomes
 // tol1 towards the midpoint (downwards when x is at or above it), and a step
 // shorter than tol1 becomes tol1 in its own direction (downwards when zero),
-// the conventions of the Brent_fmin routine Sec. 4 names.  Returns the
-// minimiser on lane t, its value in *fbest.
-template <int P>
-__device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, int LD, int j, const double* xi, int rid,
-                                              bool live, double* fbest, int* nev, int* vflag) {
+// the conventions of the Brent_fmin routine Sec. 4 names.  eval(s, ev)
+// returns, on every lane t < nl with ev set, the objective's ALC at lane
+// t's parameter s (one call serves every lane).  Returns the minimiser on
+// lane t, its value in *fbest.
+template <class Eval>
+__device__ __forceinline__ double brent_lanes(const LocalArgs& a, int nl, bool live, const Eval& eval, double* fbest,
+                                              int* nev) {
   const double gold = 0x1.8722191a02d60p-2;  // (3 - sqrt 5)/2
   const double sqeps = 0x1p-26;              // sqrt(2^-52)
   const double tol = a.brent_tol;
@@ -965,8 +974,8 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, 
   double lo = 0.0, hi = 1.0;
   double x = lo + gold * (hi - lo);
   double w = x, v = x;
-  bool run = live && lane < RB;
-  const double f0 = ray_alc_lanes<P>(a, L, LD, j, xi, rid, x, run, false, vflag);
+  bool run = live && lane < nl;
+  const double f0 = eval(x, run);
   double fx = -f0, fw = fx, fv = fx;
   double step = 0.0, prev = 0.0;
   int it = 0;
@@ -1006,7 +1015,7 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, 
       }
     }
     if (!__any(ev)) break;
-    const double fu = -ray_alc_lanes<P>(a, L, LD, j, xi, rid, u, ev, false, vflag);
+    const double fu = -eval(u, ev);
     if (ev) {
       ++it;
       if (fu <= fx) {
@@ -1026,110 +1035,69 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, const Lds& L, 
     }
   }
   *fbest = fx;
-  *nev = (live && lane < RB) ? it + 1 : 0;  // objective evaluations, the first included
+  *nev = (live && lane < nl) ? it + 1 : 0;  // objective evaluations, the first included
   return x;
 }
 
-// One ray-search step at design size j: returns the chosen candidate rank,
-// the best and runner-up ray values in *b1, *b2.
-template <int P>
-__device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, const double* Xc, int j,
-                                       int n0, double* b1, double* b2, int* vflag) {
-  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int p = a.p;
-  const int R = a.numrays;
-  if (tid == 0) {
+// Round-robin starts of a ray step (Sec. 4): the R remaining candidates from
+// rank k0 = t mod floor(sqrt t) on, t = j - n0 + 1.  Leaves their number in
+// L.ints[2] (fewer than R only when the list runs out).
+__device__ __forceinline__ int ray_starts(const LocalArgs& a, const Lds& L, int j, int n0) {
+  if (threadIdx.x == 0) {
     const int t = j - n0 + 1;
     int rt = 0;
     while ((rt + 1) * (rt + 1) <= t) ++rt;
     const int k0 = rt > 0 ? t % rt : 0;
     int seen = 0, got = 0;
-    for (int c = 0; c < a.ncand && got < R; ++c) {
+    for (int c = 0; c < a.ncand && got < a.numrays; ++c) {
       if (L.selm[c]) continue;
       if (seen++ >= k0) L.starts[got++] = c;
     }
     L.ints[2] = got;
   }
   __syncthreads();
-  const int ns = L.ints[2];
-  double xi[PM];
+  return L.ints[2];
+}
+
+// Segment of ray r (Sec. 4): from its start a, away from x, ten times
+// |a - x| long, cut at the design's bounding box; returns the cut fraction
+// tau, and writes a and the clipped direction to L.ra, L.rdir when `write`.
+template <int P>
+__device__ __forceinline__ double ray_segment(const LocalArgs& a, const Lds& L, const int32_t* C, int r, bool write) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
+  const int p = a.p;
+  const double* src = a.X + (int64_t)C[L.starts[r]] * p;
+  double ak[PM], dk[PM];
+  double tt = 1.0;
 #pragma unroll
-  for (int k = 0; k < PM; ++k) xi[k] = ((P > 0 || k < p) && lane < j) ? L.xj[lane * p + k] : 0.0;
-  // wave w takes rays w, w + NW, ...: RB of them at a time
-  for (int r0 = wave; r0 < ns; r0 += NW * RB) {
-    int rid[RB];
-    bool valid[RB];
-    double tau[RB];
-#pragma unroll
-    for (int t = 0; t < RB; ++t) {
-      rid[t] = r0 + NW * t;
-      valid[t] = rid[t] < ns;
-      tau[t] = 0.0;
-      if (!valid[t]) {
-        rid[t] = r0;  // a valid index; the slot is never evaluated
-        continue;
-      }
-      // segment from the start, away from x, ten times |a - x| long, cut at
-      // the design's bounding box (every lane computes the same values)
-      const double* src = a.X + (int64_t)C[L.starts[rid[t]]] * p;
-      double ak[PM], dk[PM];
-      double tt = 1.0;
-#pragma unroll
-      for (int k = 0; k < PM; ++k) {
-        ak[k] = 0.0;
-        dk[k] = 0.0;
-        if (P > 0 || k < p) {
-          ak[k] = src[k];
-          dk[k] = 10.0 * (ak[k] - L.x[k]);
-          if (dk[k] > 0.0) tt = fmin(tt, (a.hi[k] - ak[k]) / dk[k]);
-          else if (dk[k] < 0.0) tt = fmin(tt, (a.lo[k] - ak[k]) / dk[k]);
-        }
-      }
-      if (tt < 0.0) tt = 0.0;
-      tau[t] = tt;
-      if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < PM; ++k)
-          if (P > 0 || k < p) {
-            L.ra[rid[t] * p + k] = ak[k];
-            L.rdir[rid[t] * p + k] = tt * dk[k];
-          }
+  for (int k = 0; k < PM; ++k) {
+    ak[k] = 0.0;
+    dk[k] = 0.0;
+    if (P > 0 || k < p) {
+      ak[k] = src[k];
+      dk[k] = 10.0 * (ak[k] - L.x[k]);
+      if (dk[k] > 0.0) tt = fmin(tt, (a.hi[k] - ak[k]) / dk[k]);
+      else if (dk[k] < 0.0) tt = fmin(tt, (a.lo[k] - ak[k]) / dk[k]);
     }
-    wave_sync();
-    // slot t on lane t from here on
-    int my_rid = rid[0];
-    bool my_valid = valid[0], my_live;
-    double my_tau = tau[0];
-#pragma unroll
-    for (int t = 1; t < RB; ++t)
-      if (lane == t) {
-        my_rid = rid[t];
-        my_valid = valid[t];
-        my_tau = tau[t];
-      }
-    my_valid = my_valid && lane < RB;
-    const double a0 = ray_alc_lanes<P>(a, L, LD, j, xi, my_rid, 0.0, my_valid, true, vflag);
-    my_live = my_valid && my_tau > 0.0;
-    double fb = 0.0;
-    int nev = 0;
-    const double xb = brent_lanes<P>(a, L, LD, j, xi, my_rid, my_live, &fb, &nev, vflag);
-    if (my_valid) {
-      L.rev[my_rid] = nev;
-      double sst = 0.0, val = a0;
-      if (my_live) {
-        sst = xb;
-        val = -fb;
-        if (a0 >= val) {
-          sst = 0.0;
-          val = a0;
-        }
-      }
-      L.rval[my_rid] = val;
-      L.rs[my_rid] = sst;
-    }
-    wave_sync();
   }
+  if (tt < 0.0) tt = 0.0;
+  if (write)
+#pragma unroll
+    for (int k = 0; k < PM; ++k)
+      if (P > 0 || k < p) {
+        L.ra[r * p + k] = ak[k];
+        L.rdir[r * p + k] = tt * dk[k];
+      }
+  return tt;
+}
+
+// The end of a ray step, once every ray's value and s* are in L.rval, L.rs:
+// the best ray (lowest on ties), its start when s* = 0, else its optimum
+// snapped to the nearest candidate outside the design and the starts.
+// Returns the chosen rank; *b1, *b2 the best and runner-up ray values.
+__device__ __forceinline__ int ray_finish(const LocalArgs& a, const Lds& L, const double* Xc, int ns, double* b1,
+                                          double* b2) {
+  const int tid = threadIdx.x, p = a.p;
   __syncthreads();
   if (tid == 0) {
     double bv = -__builtin_huge_val(), sv = -__builtin_huge_val();
@@ -1179,11 +1147,178 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
   return L.ints[0];
 }
 
+// One ray-search step at design size j: returns the chosen candidate rank,
+// the best and runner-up ray values in *b1, *b2.
+template <int P>
+__device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, const double* Xc, int j,
+                                       int n0, double* b1, double* b2, int* vflag) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = a.p;
+  const int ns = ray_starts(a, L, j, n0);
+  double xi[PM];
+#pragma unroll
+  for (int k = 0; k < PM; ++k) xi[k] = ((P > 0 || k < p) && lane < j) ? L.xj[lane * p + k] : 0.0;
+  // wave w takes rays w, w + NW, ...: RB of them at a time
+  for (int r0 = wave; r0 < ns; r0 += NW * RB) {
+    int rid[RB];
+    bool valid[RB];
+    double tau[RB];
+#pragma unroll
+    for (int t = 0; t < RB; ++t) {
+      rid[t] = r0 + NW * t;
+      valid[t] = rid[t] < ns;
+      tau[t] = 0.0;
+      if (!valid[t]) {
+        rid[t] = r0;  // a valid index; the slot is never evaluated
+        continue;
+      }
+      // (every lane computes the same values; lane 0 writes them)
+      tau[t] = ray_segment<P>(a, L, C, rid[t], lane == 0);
+    }
+    wave_sync();
+    // slot t on lane t from here on
+    int my_rid = rid[0];
+    bool my_valid = valid[0], my_live;
+    double my_tau = tau[0];
+#pragma unroll
+    for (int t = 1; t < RB; ++t)
+      if (lane == t) {
+        my_rid = rid[t];
+        my_valid = valid[t];
+        my_tau = tau[t];
+      }
+    my_valid = my_valid && lane < RB;
+    const double a0 = ray_alc_lanes<P>(a, L, LD, j, xi, my_rid, 0.0, my_valid, true, vflag);
+    my_live = my_valid && my_tau > 0.0;
+    double fb = 0.0;
+    int nev = 0;
+    const auto eval = [&](double s, bool e) { return ray_alc_lanes<P>(a, L, LD, j, xi, my_rid, s, e, false, vflag); };
+    const double xb = brent_lanes(a, RB, my_live, eval, &fb, &nev);
+    if (my_valid) {
+      L.rev[my_rid] = nev;
+      double sst = 0.0, val = a0;
+      if (my_live) {
+        sst = xb;
+        val = -fb;
+        if (a0 >= val) {
+          sst = 0.0;
+          val = a0;
+        }
+      }
+      L.rval[my_rid] = val;
+      L.rs[my_rid] = sst;
+    }
+    wave_sync();
+  }
+  return ray_finish(a, L, Xc, ns, b1, b2);
+}
+
+// ------------------------------------------------ ray search on one tile --
+//
+// All rays of a step (R <= 16) searched by one wave in lockstep: ray t's
+// Brent recurrence runs on lane t, and each round evaluates the objective at
+// every live ray's current point as one 16-column tile of the exact scoring
+// above.  Column t of the tile is ray t's point z_t: its kernel column
+// K(x_J, z_t) is computed straight into the MFMA B layout (lane 16k + t
+// holds K(x_{4q+k}, z_t) for chunk q, zero past j) and K(z_t, x) beside it,
+// and alc_tile_exact_q gives (K(z_t,x) - k_t^T K^{-1} k_x)^2 /
+// ((1+g) - k_t^T K^{-1} k_t) with every sum in index order: the same value,
+// bit for bit, as the per-ray form above.  Columns past R, and rays not
+// evaluated this round, hold zero kernel columns (v = 1 + g, no flag).
+
+// Kernel columns of the round's ray points into the B layout in LDS: lane
+// 16k + t writes K(x_{4q+k}, z_t) to kcol[64 q + lane] for q < nq (zero past
+// j, or when ray t is not evaluated), and returns K(z_t, x) (zero likewise).
+template <int P>
+__device__ __forceinline__ double ray_columns(const LocalArgs& a, const Lds& L, int j, int nq, int R, double s, bool ev,
+                                              bool at_start, double* kcol) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
+  const int lane = threadIdx.x & 63;
+  const int g4 = lane >> 4, t = lane & 15;
+  const int p = a.p;
+  const double st = __shfl(s, t, 64);
+  const bool et = (__shfl(ev ? 1 : 0, t, 64) != 0) && t < R;
+  double z[PM];
+  ray_point<P>(L, p, et ? t : 0, st, at_start, z);
+  for (int q = 0; q < nq; ++q) {
+    const int i = 4 * q + g4;
+    kcol[64 * q + lane] = (et && i < j) ? corr_regs<P>(L.xj + i * p, z, p, L.w0, a.w, a.dlen) : 0.0;
+  }
+  return et ? corr_regs<P>(z, L.x, p, L.w0, a.w, a.dlen) : 0.0;
+}
+
+template <int NP, int NQ>
+__device__ __forceinline__ double ray_tile_q(const LocalArgs& a, const Lds& L, int LD, const double* kcol, double kxcol,
+                                             int* vflag) {
+  const int lane = threadIdx.x & 63;
+  double b[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) b[q] = kcol[64 * q + lane];
+  return alc_tile_exact_q<NP, NQ>(a, L, LD, b, kxcol, vflag);
+}
+
+// The objective at every evaluated ray's point, as one tile of the exact
+// scoring: lane t < R receives ray t's value (0 if it is not evaluated).
+template <int NP, int P>
+__device__ __forceinline__ double ray_tile(const LocalArgs& a, const Lds& L, int LD, int j, int R, double s, bool ev,
+                                           bool at_start, int* vflag) {
+  const int lane = threadIdx.x & 63;
+  const int nq = (j + 3) >> 2;
+  double* kcol = L.kzb;
+  const double kxcol = ray_columns<P>(a, L, j, nq, R, s, ev, at_start, kcol);
+  wave_sync();
+  double out = 0.0;
+#define LAGP_RAY_CASE(Q) \
+  case Q:                \
+    if constexpr (Q <= NP / 4) out = ray_tile_q<NP, Q>(a, L, LD, kcol, kxcol, vflag); \
+    break;
+  switch (nq) { LAGP_CASES_16(LAGP_RAY_CASE) default: break; }
+#undef LAGP_RAY_CASE
+  wave_sync();  // kcol is rewritten by the next round
+  return lane < R && ev ? out : 0.0;
+}
+
+// One ray-search step with every ray on one lane of a single wave.
+template <int NP, int P>
+__device__ __forceinline__ int ray_step_tile(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, const double* Xc,
+                                            int j, int n0, double* b1, double* b2, int* vflag) {
+  const int lane = threadIdx.x & 63;
+  const int ns = ray_starts(a, L, j, n0);
+  const bool valid = lane < ns;
+  const double tau = valid ? ray_segment<P>(a, L, C, lane, true) : 0.0;
+  wave_sync();
+  const double a0 = ray_tile<NP, P>(a, L, LD, j, ns, 0.0, valid, true, vflag);
+  const bool live = valid && tau > 0.0;
+  double fb = 0.0;
+  int nev = 0;
+  const auto eval = [&](double s, bool e) { return ray_tile<NP, P>(a, L, LD, j, ns, s, e, false, vflag); };
+  const double xb = brent_lanes(a, ns, live, eval, &fb, &nev);
+  if (valid) {
+    L.rev[lane] = nev;
+    double sst = 0.0, val = a0;
+    if (live) {
+      sst = xb;
+      val = -fb;
+      if (a0 >= val) {
+        sst = 0.0;
+        val = a0;
+      }
+    }
+    L.rval[lane] = val;
+    L.rs[lane] = sst;
+  }
+  return ray_finish(a, L, Xc, ns, b1, b2);
+}
+
 // ------------------------------------------------------------ kernel -----
 
 // Kernel variants: one instantiation per search / scoring form so each
 // carries only its own register footprint.
-enum Mode { MODE_EXACT = 0, MODE_MIXED = 1, MODE_RAY = 3, MODE_NN = 4 };
+// MODE_RAY spreads the rays over the workgroup's four waves (any n, up to
+// LAGP_MAX_RAYS rays); MODE_RAY_TILE searches them all on one wave of a
+// 64-thread workgroup (n <= 64, at most 16 rays).
+enum Mode { MODE_EXACT = 0, MODE_MIXED = 1, MODE_RAY = 3, MODE_NN = 4, MODE_RAY_TILE = 5 };
 
 // Register budget per form: the ray form is held to three waves per SIMD
 // (its LDS admits three workgroups per CU); the exhaustive forms schedule
@@ -1192,12 +1327,16 @@ enum Mode { MODE_EXACT = 0, MODE_MIXED = 1, MODE_RAY = 3, MODE_NN = 4 };
 template <int NP, int MODE>
 constexpr int local_waves_per_eu() { return MODE == MODE_RAY ? 3 : 2; }
 
+// One wave per location in the tile ray form (its search is one wave's
+// work; the per-step phases loop over the workgroup).
+constexpr bool local_tile_rays(int n, int R) { return n <= 64 && R >= 1 && R <= 16; }
+
 template <int NP, int MODE, int P>
 __global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(local_waves_per_eu<NP, MODE>())))
 void k_local(LocalArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 0;
-  const LdsPlan plan = plan_lds(a.n, a.ncs, a.p, R, MODE == MODE_MIXED);
+  const LdsPlan plan = plan_lds(a.n, a.ncs, a.p, R, MODE == MODE_MIXED, MODE == MODE_RAY_TILE);
   Lds L = carve(smem, plan);
   const int LD = plan.LD;
   const int tid = threadIdx.x;
@@ -1265,6 +1404,8 @@ void k_local(LocalArgs a) {
       double b1, b2;
       if constexpr (MODE == MODE_RAY) {
         cs = ray_step<P>(a, L, LD, C, Xc, j, n0, &b1, &b2, &vflag);
+      } else if constexpr (MODE == MODE_RAY_TILE) {
+        cs = ray_step_tile<NP, P>(a, L, LD, C, Xc, j, n0, &b1, &b2, &vflag);
       } else if constexpr (MODE == MODE_NN) {
         cs = -1;  // (the nearest neighbours fill the design: no step runs)
         b1 = b2 = 0.0;
@@ -1290,7 +1431,7 @@ void k_local(LocalArgs a) {
       }
       if (tid == 0 && a.counts) {  // the step's search work (see LocalArgs::counts)
         int32_t* ct = a.counts + ((int64_t)m * (n - a.n0) + (j - n0)) * 2;
-        const bool kept = MODE == MODE_RAY || MODE == MODE_MIXED;
+        const bool kept = MODE == MODE_RAY || MODE == MODE_RAY_TILE || MODE == MODE_MIXED;
         ct[0] = kept ? L.ints[5] : nc - j;
         ct[1] = kept ? L.ints[6] : 0;
       }
@@ -1342,12 +1483,18 @@ size_t local_lds_bytes(int n, int ncs, int p, int numrays, bool mixed) {
   return plan_lds(n, ncs, p, numrays, mixed).bytes;
 }
 
+// Test hook: LAGP_RAY_FORCE_WAVES=1 keeps every ray search on the four-wave form.
+static bool ray_force_waves() {
+  const char* s = std::getenv("LAGP_RAY_FORCE_WAVES");
+  return s && s[0] == '1';
+}
+
 template <int NP, int MODE, int P = 0>
-static hipError_t launch_mode(const LocalArgs& a, size_t lds, hipStream_t s) {
+static hipError_t launch_mode(const LocalArgs& a, size_t lds, hipStream_t s, int threads = LOCAL_THREADS) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_local<NP, MODE, P>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_local<NP, MODE, P>), dim3(a.M), dim3(LOCAL_THREADS), lds, s, a);
+  hipLaunchKernelGGL((k_local<NP, MODE, P>), dim3(a.M), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1364,6 +1511,17 @@ hipError_t launch_local(const LocalArgs& a, hipStream_t s) {
   if (a.M <= 0) return hipSuccess;
   const int R = a.search == LAGP_SEARCH_RAY ? a.numrays : 0;
   const size_t lds = local_lds_bytes(a.n, a.ncs, a.p, R, a.precision == LAGP_PREC_MIXED);
+  if (a.search == LAGP_SEARCH_RAY && local_tile_rays(a.n, a.numrays) && !ray_force_waves()) {
+    const size_t lt = plan_lds(a.n, a.ncs, a.p, R, false, true).bytes;
+    switch (a.p) {
+      case 1: return launch_mode<64, MODE_RAY_TILE, 1>(a, lt, s, 64);
+      case 2: return launch_mode<64, MODE_RAY_TILE, 2>(a, lt, s, 64);
+      case 3: return launch_mode<64, MODE_RAY_TILE, 3>(a, lt, s, 64);
+      case 4: return launch_mode<64, MODE_RAY_TILE, 4>(a, lt, s, 64);
+      case 8: return launch_mode<64, MODE_RAY_TILE, 8>(a, lt, s, 64);
+      default: return launch_mode<64, MODE_RAY_TILE, 0>(a, lt, s, 64);
+    }
+  }
   if (a.search == LAGP_SEARCH_RAY) {
     switch (a.p) {
       case 1: return launch_mode<64, MODE_RAY, 1>(a, lds, s);

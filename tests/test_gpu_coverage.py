@@ -136,3 +136,32 @@ def test_served_requests_equal_the_oracle(lg):
     for k, ((XX, prm), r) in enumerate(zip(reqs, res)):
         o = oracle.predict(X, y, XX, prm.replace(precision=W.PREC_FP64))
         _same(r, o, f"request {k}")
+
+
+@pytest.mark.parametrize("p,R,n", [(8, 1, 50), (8, 7, 50), (2, 16, 64), (3, 17, 40), (8, 10, 64)])
+def test_ray_tile_and_wave_forms_bit_exact(lg, monkeypatch, p, R, n):
+    """Up to 16 rays at n <= 64 run on one wave per location (every ray on a
+    lane, each round one tile of the exact scoring); LAGP_RAY_FORCE_WAVES=1
+    keeps the four-wave form.  Both equal the oracle bit for bit, Brent
+    evaluation counts included (R = 17 takes the four-wave form either way)."""
+    import torch
+
+    w = _uniform(540 + p + R, 20000, p, 6, n0=6, n=n, ncand=600, search=W.SEARCH_RAY, numrays=R, d=(0.15 * p,),
+                 g=1e-6)
+    o = oracle.predict(w.X, w.y, w.XX, w.params)
+    runs = []
+    for force in ("0", "1"):
+        monkeypatch.setenv("LAGP_RAY_FORCE_WAVES", force)
+        d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
+        try:
+            out = d.predict(torch.from_numpy(w.XX), w.params, counts=True)
+            torch.cuda.synchronize()
+            g = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+        finally:
+            d.close()
+        _same(g, o, f"rays p={p} R={R} n={n} force_waves={force}")
+        assert np.array_equal(g["diag"][:, :, 0], o["diag"][:, :, 1])
+        assert np.array_equal(g["counts"][:, :, 0], o["diag"][:, :, 5].astype(np.int32))
+        runs.append(g)
+    for k in ("sel", "mean", "s2", "diag", "counts"):
+        assert np.array_equal(runs[0][k], runs[1][k]), k
