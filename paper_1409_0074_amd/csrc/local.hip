@@ -108,7 +108,7 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool m
   take(sizeof(double) * LAGP_MAX_DIM);     // x
   take(sizeof(double) * n * p);            // xj
   // kzb: per-wave ray vectors, or the tile form's kernel columns (16 chunks x 64 lanes)
-  take(ray ? sizeof(double) * NW * RB * P.KZS : (tile && R > 0 ? sizeof(double) * 64 * ((n + 3) / 4) : 0));
+  take(ray ? sizeof(double) * NW * RB * P.KZS : (tile && R > 0 ? sizeof(double) * 64 * (((n + 3) / 4 + 3) & ~3) : 0));
   take(ray ? sizeof(double) * NW * RB * P.KZS : 0);  // wvb
   take(sizeof(double) * P.R * p);          // ra
   take(sizeof(double) * P.R * p);          // rdir
@@ -1095,8 +1095,11 @@ __device__ __forceinline__ double ray_segment(const LocalArgs& a, const Lds& L, 
 // the best ray (lowest on ties), its start when s* = 0, else its optimum
 // snapped to the nearest candidate outside the design and the starts.
 // Returns the chosen rank; *b1, *b2 the best and runner-up ray values.
+template <int P>
 __device__ __forceinline__ int ray_finish(const LocalArgs& a, const Lds& L, const double* Xc, int ns, double* b1,
                                           double* b2) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
+  constexpr int G = PM <= 8 ? 4 : 1;  // candidates whose coordinates are loaded together
   const int tid = threadIdx.x, p = a.p;
   __syncthreads();
   if (tid == 0) {
@@ -1126,24 +1129,44 @@ __device__ __forceinline__ int ray_finish(const LocalArgs& a, const Lds& L, cons
   *b2 = L.scal[2];
   if (sw == 0.0) return L.starts[br];
   // snap z* = a + s* dir to the nearest candidate outside J and the starts
+  // (the starts are flagged unavailable for the scan, 2 = start, and
+  // released after it)
   const double* ar = L.ra + br * p;
   const double* dr = L.rdir + br * p;
+  for (int r = tid; r < ns; r += blockDim.x) L.selm[L.starts[r]] = 2;
+  __syncthreads();
+  double zs[PM];
+#pragma unroll
+  for (int k = 0; k < PM; ++k) zs[k] = (P > 0 || k < p) ? __builtin_fma(sw, dr[k], ar[k]) : 0.0;
   Best nb = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};  // maximise -d2
-  for (int c = tid; c < a.ncand; c += blockDim.x) {
-    if (L.selm[c]) continue;
-    bool start = false;
-    for (int r = 0; r < ns; ++r) start |= (L.starts[r] == c);
-    if (start) continue;
-    const double* xc = Xc + (int64_t)c * p;  // gathered by this thread in the prologue
-    double acc = 0.0;
-    for (int k = 0; k < p; ++k) {
-      const double zk = __builtin_fma(sw, dr[k], ar[k]);
-      const double t = xc[k] - zk;
-      acc = __builtin_fma(t, t, acc);
+  const int nt = blockDim.x;
+  for (int c0 = tid; c0 < a.ncand; c0 += G * nt) {
+    // the coordinates of G candidates (gathered by this thread in the
+    // prologue) are loaded before the first is used
+    double xc[G][PM];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int c = c0 + u * nt < a.ncand ? c0 + u * nt : c0;
+#pragma unroll
+      for (int k = 0; k < PM; ++k) xc[u][k] = (P > 0 || k < p) ? Xc[(int64_t)c * p + k] : 0.0;
     }
-    best_push(nb, -acc, c);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int c = c0 + u * nt;
+      if (c >= a.ncand || L.selm[c]) continue;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < PM; ++k)
+        if (P > 0 || k < p) {
+          const double t = xc[u][k] - zs[k];
+          acc = __builtin_fma(t, t, acc);
+        }
+      best_push(nb, -acc, c);
+    }
   }
-  block_best(L, nb);
+  block_best(L, nb);  // (its barriers order the scan before the release)
+  for (int r = tid; r < ns; r += blockDim.x) L.selm[L.starts[r]] = 0;
+  __syncthreads();
   return L.ints[0];
 }
 
@@ -1211,7 +1234,7 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
     }
     wave_sync();
   }
-  return ray_finish(a, L, Xc, ns, b1, b2);
+  return ray_finish<P>(a, L, Xc, ns, b1, b2);
 }
 
 // ------------------------------------------------ ray search on one tile --
@@ -1227,25 +1250,81 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
 // bit for bit, as the per-ray form above.  Columns past R, and rays not
 // evaluated this round, hold zero kernel columns (v = 1 + g, no flag).
 
+// corr_regs with the straight-line exp (gexp_with: the same values, no
+// branches), so that independent evaluations interleave.
+template <int P>
+__device__ __forceinline__ double corr_regs_bf(const double* u, const double* v, int p, double w0, const double* w,
+                                               int dlen) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
+  double acc = 0.0;
+  if (dlen == 1) {
+#pragma unroll
+    for (int k = 0; k < PM; ++k)
+      if (P > 0 || k < p) {
+        const double t = u[k] - v[k];
+        acc = __builtin_fma(t, t, acc);
+      }
+    return gexp_with(-(acc * w0), gexp_coef);
+  }
+#pragma unroll
+  for (int k = 0; k < PM; ++k)
+    if (P > 0 || k < p) {
+      const double t = u[k] - v[k];
+      acc = __builtin_fma(t * t, w[k], acc);
+    }
+  return gexp_with(-acc, gexp_coef);
+}
+
 // Kernel columns of the round's ray points into the B layout in LDS: lane
 // 16k + t writes K(x_{4q+k}, z_t) to kcol[64 q + lane] for q < nq (zero past
 // j, or when ray t is not evaluated), and returns K(z_t, x) (zero likewise).
+// Four chunks at a time, every lane alike (rows past j read a valid row and
+// are masked after), their exps in lockstep: the arithmetic of corr() per
+// value (ISO: the isotropic form).
+template <int P, bool ISO>
+__device__ __forceinline__ double ray_columns_t(const LocalArgs& a, const Lds& L, int j, int nq, bool et,
+                                                const double* z, double* kcol) {
+  constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
+  const int lane = threadIdx.x & 63;
+  const int g4 = lane >> 4;
+  const int p = a.p;
+  const double kx = corr_regs_bf<P>(z, L.x, p, L.w0, a.w, a.dlen);
+  for (int q0 = 0; q0 < nq; q0 += 4) {
+    double e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = 4 * (q0 + u) + g4;
+      const double* xi = L.xj + (i < j ? i : 0) * p;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < PM; ++k)
+        if (P > 0 || k < p) {
+          const double t = xi[k] - z[k];
+          acc = ISO ? __builtin_fma(t, t, acc) : __builtin_fma(t * t, a.w[k], acc);
+        }
+      e[u] = ISO ? -(acc * L.w0) : -acc;
+    }
+    gexp4(e);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // (kcol holds whole groups of four chunks)
+      const int i = 4 * (q0 + u) + g4;
+      kcol[64 * (q0 + u) + lane] = (et && i < j) ? e[u] : 0.0;
+    }
+  }
+  return et ? kx : 0.0;
+}
+
 template <int P>
 __device__ __forceinline__ double ray_columns(const LocalArgs& a, const Lds& L, int j, int nq, int R, double s, bool ev,
                                               bool at_start, double* kcol) {
   constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
-  const int lane = threadIdx.x & 63;
-  const int g4 = lane >> 4, t = lane & 15;
-  const int p = a.p;
+  const int t = threadIdx.x & 15;
   const double st = __shfl(s, t, 64);
   const bool et = (__shfl(ev ? 1 : 0, t, 64) != 0) && t < R;
   double z[PM];
-  ray_point<P>(L, p, et ? t : 0, st, at_start, z);
-  for (int q = 0; q < nq; ++q) {
-    const int i = 4 * q + g4;
-    kcol[64 * q + lane] = (et && i < j) ? corr_regs<P>(L.xj + i * p, z, p, L.w0, a.w, a.dlen) : 0.0;
-  }
-  return et ? corr_regs<P>(z, L.x, p, L.w0, a.w, a.dlen) : 0.0;
+  ray_point<P>(L, a.p, et ? t : 0, st, at_start, z);
+  return a.dlen == 1 ? ray_columns_t<P, true>(a, L, j, nq, et, z, kcol)
+                     : ray_columns_t<P, false>(a, L, j, nq, et, z, kcol);
 }
 
 template <int NP, int NQ>
@@ -1308,7 +1387,7 @@ __device__ __forceinline__ int ray_step_tile(const LocalArgs& a, const Lds& L, i
     L.rval[lane] = val;
     L.rs[lane] = sst;
   }
-  return ray_finish(a, L, Xc, ns, b1, b2);
+  return ray_finish<P>(a, L, Xc, ns, b1, b2);
 }
 
 // ------------------------------------------------------------ kernel -----
