@@ -69,6 +69,8 @@ struct Lds {
   int* starts;   // R
   int* ints;     // 8 scalars
   int* shortlist;  // max(64, ncs/16): mixed form, the 16-candidate tiles re-scored in FP64
+  double* tps;     // 16: tile ray form, each ray's parameter this round
+  int* tpe;        // 16: tile ray form, whether the ray is evaluated this round
   int kzs;         // per-slot stride of kzb / wvb
   float* scr;      // ncs: mixed form, FP32 screened scores
   unsigned char* selm;  // ncs: 1 = not available (selected or padding)
@@ -122,6 +124,8 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool m
   take(sizeof(int) * P.R);                 // starts
   take(sizeof(int) * 8);                   // ints
   take(mixed ? sizeof(int) * (ncs / 16 > 64 ? ncs / 16 : 64) : 0);  // shortlist (tiles)
+  take(tile ? sizeof(double) * 16 : 0);   // tps
+  take(tile ? sizeof(int) * 16 : 0);      // tpe
   take(mixed ? sizeof(float) * ncs : 0);   // scr
   take(ncs);                               // selm
   P.bytes = o;
@@ -143,6 +147,8 @@ __device__ inline Lds carve(unsigned char* s, const LdsPlan& P) {
   L.starts = reinterpret_cast<int*>(s + P.off[k++]);
   L.ints = reinterpret_cast<int*>(s + P.off[k++]);
   L.shortlist = reinterpret_cast<int*>(s + P.off[k++]);
+  L.tps = reinterpret_cast<double*>(s + P.off[k++]);
+  L.tpe = reinterpret_cast<int*>(s + P.off[k++]);
   L.scr = reinterpret_cast<float*>(s + P.off[k++]);
   L.selm = s + P.off[k++];
   L.kzs = P.KZS;
@@ -964,7 +970,7 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
 // returns, on every lane t < nl with ev set, the objective's ALC at lane
 // t's parameter s (one call serves every lane).  Returns the minimiser on
 // lane t, its value in *fbest.
-template <class Eval>
+template <bool BLOCK, class Eval>
 __device__ __forceinline__ double brent_lanes(const LocalArgs& a, int nl, bool live, const Eval& eval, double* fbest,
                                               int* nev) {
   const double gold = 0x1.8722191a02d60p-2;  // (3 - sqrt 5)/2
@@ -1014,7 +1020,8 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, int nl, bool l
         ev = true;
       }
     }
-    if (!__any(ev)) break;
+    // (BLOCK: the evaluations span the workgroup, so every wave leaves together)
+    if (BLOCK ? !__syncthreads_or(ev) : !__any(ev)) break;
     const double fu = -eval(u, ev);
     if (ev) {
       ++it;
@@ -1217,7 +1224,7 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
     double fb = 0.0;
     int nev = 0;
     const auto eval = [&](double s, bool e) { return ray_alc_lanes<P>(a, L, LD, j, xi, my_rid, s, e, false, vflag); };
-    const double xb = brent_lanes(a, RB, my_live, eval, &fb, &nev);
+    const double xb = brent_lanes<false>(a, RB, my_live, eval, &fb, &nev);
     if (my_valid) {
       L.rev[my_rid] = nev;
       double sst = 0.0, val = a0;
@@ -1288,8 +1295,9 @@ __device__ __forceinline__ double ray_columns_t(const LocalArgs& a, const Lds& L
   const int lane = threadIdx.x & 63;
   const int g4 = lane >> 4;
   const int p = a.p;
-  const double kx = corr_regs_bf<P>(z, L.x, p, L.w0, a.w, a.dlen);
-  for (int q0 = 0; q0 < nq; q0 += 4) {
+  const int wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const double kx = wv == 0 ? corr_regs_bf<P>(z, L.x, p, L.w0, a.w, a.dlen) : 0.0;  // (wave 0 scores)
+  for (int q0 = 4 * wv; q0 < nq; q0 += 4 * nwv) {  // groups of four chunks, round robin over the waves
     double e[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -1315,12 +1323,12 @@ __device__ __forceinline__ double ray_columns_t(const LocalArgs& a, const Lds& L
 }
 
 template <int P>
-__device__ __forceinline__ double ray_columns(const LocalArgs& a, const Lds& L, int j, int nq, int R, double s, bool ev,
-                                              bool at_start, double* kcol) {
+__device__ __forceinline__ double ray_columns(const LocalArgs& a, const Lds& L, int j, int nq, int R, bool at_start,
+                                              double* kcol) {
   constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
   const int t = threadIdx.x & 15;
-  const double st = __shfl(s, t, 64);
-  const bool et = (__shfl(ev ? 1 : 0, t, 64) != 0) && t < R;
+  const double st = L.tps[t];
+  const bool et = L.tpe[t] != 0 && t < R;
   double z[PM];
   ray_point<P>(L, a.p, et ? t : 0, st, at_start, z);
   return a.dlen == 1 ? ray_columns_t<P, true>(a, L, j, nq, et, z, kcol)
@@ -1342,37 +1350,44 @@ __device__ __forceinline__ double ray_tile_q(const LocalArgs& a, const Lds& L, i
 template <int NP, int P>
 __device__ __forceinline__ double ray_tile(const LocalArgs& a, const Lds& L, int LD, int j, int R, double s, bool ev,
                                            bool at_start, int* vflag) {
-  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
   const int nq = (j + 3) >> 2;
   double* kcol = L.kzb;
-  const double kxcol = ray_columns<P>(a, L, j, nq, R, s, ev, at_start, kcol);
-  wave_sync();
+  if (tid < 16) {  // ray t's parameter, from lane t of wave 0, for every wave
+    L.tps[tid] = s;
+    L.tpe[tid] = ev ? 1 : 0;
+  }
+  __syncthreads();
+  const double kxcol = ray_columns<P>(a, L, j, nq, R, at_start, kcol);
+  __syncthreads();
   double out = 0.0;
+  if (tid < 64) {
 #define LAGP_RAY_CASE(Q) \
   case Q:                \
     if constexpr (Q <= NP / 4) out = ray_tile_q<NP, Q>(a, L, LD, kcol, kxcol, vflag); \
     break;
-  switch (nq) { LAGP_CASES_16(LAGP_RAY_CASE) default: break; }
+    switch (nq) { LAGP_CASES_16(LAGP_RAY_CASE) default: break; }
 #undef LAGP_RAY_CASE
-  wave_sync();  // kcol is rewritten by the next round
-  return lane < R && ev ? out : 0.0;
+  }
+  __syncthreads();  // kcol and the parameters are rewritten by the next round
+  return tid < R && ev ? out : 0.0;
 }
 
 // One ray-search step with every ray on one lane of a single wave.
 template <int NP, int P>
 __device__ __forceinline__ int ray_step_tile(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, const double* Xc,
                                             int j, int n0, double* b1, double* b2, int* vflag) {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x;  // (rays live on the lanes of wave 0)
   const int ns = ray_starts(a, L, j, n0);
   const bool valid = lane < ns;
   const double tau = valid ? ray_segment<P>(a, L, C, lane, true) : 0.0;
-  wave_sync();
+  __syncthreads();
   const double a0 = ray_tile<NP, P>(a, L, LD, j, ns, 0.0, valid, true, vflag);
   const bool live = valid && tau > 0.0;
   double fb = 0.0;
   int nev = 0;
   const auto eval = [&](double s, bool e) { return ray_tile<NP, P>(a, L, LD, j, ns, s, e, false, vflag); };
-  const double xb = brent_lanes(a, ns, live, eval, &fb, &nev);
+  const double xb = brent_lanes<true>(a, ns, live, eval, &fb, &nev);
   if (valid) {
     L.rev[lane] = nev;
     double sst = 0.0, val = a0;
@@ -1409,6 +1424,9 @@ constexpr int local_waves_per_eu() { return MODE == MODE_RAY ? 3 : 2; }
 // One wave per location in the tile ray form (its search is one wave's
 // work; the per-step phases loop over the workgroup).
 constexpr bool local_tile_rays(int n, int R) { return n <= 64 && R >= 1 && R <= 16; }
+// Its workgroup: wave 0 holds the rays' Brent recurrences and scores the
+// tile; both waves compute the tile's kernel columns.
+constexpr int TILE_THREADS = 128;
 
 template <int NP, int MODE, int P>
 __global__ __launch_bounds__(LOCAL_THREADS) __attribute__((amdgpu_waves_per_eu(local_waves_per_eu<NP, MODE>())))
@@ -1593,12 +1611,12 @@ hipError_t launch_local(const LocalArgs& a, hipStream_t s) {
   if (a.search == LAGP_SEARCH_RAY && local_tile_rays(a.n, a.numrays) && !ray_force_waves()) {
     const size_t lt = plan_lds(a.n, a.ncs, a.p, R, false, true).bytes;
     switch (a.p) {
-      case 1: return launch_mode<64, MODE_RAY_TILE, 1>(a, lt, s, 64);
-      case 2: return launch_mode<64, MODE_RAY_TILE, 2>(a, lt, s, 64);
-      case 3: return launch_mode<64, MODE_RAY_TILE, 3>(a, lt, s, 64);
-      case 4: return launch_mode<64, MODE_RAY_TILE, 4>(a, lt, s, 64);
-      case 8: return launch_mode<64, MODE_RAY_TILE, 8>(a, lt, s, 64);
-      default: return launch_mode<64, MODE_RAY_TILE, 0>(a, lt, s, 64);
+      case 1: return launch_mode<64, MODE_RAY_TILE, 1>(a, lt, s, TILE_THREADS);
+      case 2: return launch_mode<64, MODE_RAY_TILE, 2>(a, lt, s, TILE_THREADS);
+      case 3: return launch_mode<64, MODE_RAY_TILE, 3>(a, lt, s, TILE_THREADS);
+      case 4: return launch_mode<64, MODE_RAY_TILE, 4>(a, lt, s, TILE_THREADS);
+      case 8: return launch_mode<64, MODE_RAY_TILE, 8>(a, lt, s, TILE_THREADS);
+      default: return launch_mode<64, MODE_RAY_TILE, 0>(a, lt, s, TILE_THREADS);
     }
   }
   if (a.search == LAGP_SEARCH_RAY) {
