@@ -151,9 +151,9 @@ def cpu_baseline(w, params, target_s: float = 15.0):
 
 def serving(nreq: int):
     """Serving workload: resident 4-d design (N = 2e6), requests of 1..1000
-    locations (log-uniform), n from {30, 50, 100}, exhaustive or ray search;
-    saturation throughput from a burst, then open-loop Poisson arrivals at
-    half of it."""
+    locations (log-uniform), n from {30, 50, 100}, exhaustive or ray search,
+    a quarter of the exhaustive ones in the mixed form; saturation
+    throughput from a burst, then open-loop Poisson arrivals at half of it."""
     import torch
 
     import paper_1409_0074_amd as lg
@@ -164,7 +164,7 @@ def serving(nreq: int):
     d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
     base = w.params
     budget, slots = 16 << 30, 8
-    reqs = W.serving_requests(nreq, qps=1.0)
+    reqs = W.serving_requests(nreq, qps=1.0, precision_mix=0.25)
     mean_m = float(np.mean([r.XX.shape[0] for r in reqs]))
     loadgen.run(d.handle, reqs[:20], base, budget, slots, burst=True)  # warm-up
     sat = loadgen.run(d.handle, reqs, base, budget, slots, burst=True)
@@ -175,7 +175,8 @@ def serving(nreq: int):
             "saturation_pred_per_s": round(sat["pred_per_s"], 1), "qps": round(qps, 2),
             "p50_ms": round(op["p50_ms"], 3), "p99_ms": round(op["p99_ms"], 3),
             "pred_per_s": round(op["pred_per_s"], 1), "errors": len(op["errors"]) + len(sat["errors"]),
-            "arrivals": "open-loop Poisson at half the burst throughput", "budget_bytes": budget, "slots": slots}
+            "arrivals": "open-loop Poisson at half the burst throughput", "mixed_share_of_exhaustive": 0.25,
+            "budget_bytes": budget, "slots": slots}
 
 
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 (matrix)
@@ -310,7 +311,7 @@ def sec51(steps: int):
             ("ray_n50_stage1", W.SEARCH_RAY, 1, 1000, W.SCORING_PARTINV),
             ("ext_n50_stage1", W.SEARCH_EXHAUSTIVE, 1, 1000, W.SCORING_CHOL),
             ("nn_n50", W.SEARCH_NN, 1, 1000, W.SCORING_PARTINV),
-            ("ext_n50_cand2000_stage1", W.SEARCH_EXHAUSTIVE, 1, 2000, W.SCORING_PARTINV)]
+            ("ext_n50_cand2000_stage1", W.SEARCH_EXHAUSTIVE, 1, 2000, W.SCORING_CHOL)]
     out = {"workload": w.name.replace("_exhaustive", ""), "M": int(w.XX.shape[0]), "d0": w.params.d[0],
            "g": w.params.g, "numrays": 1, "paper_secs_context": SEC51_PAPER_SECS,
            "paper_right_table_secs_context": SEC51_PAPER_RIGHT, "rows": {}}

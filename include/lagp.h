@@ -295,14 +295,19 @@ int32_t lagp_prescale(const double* X, int64_t N, int32_t p, const double* theta
 
 /* ---- serving: continuous batching over a resident design ---------------
  *
- * A server owns a worker thread and a device stream.  Requests (host
- * location arrays plus parameters) are admitted as long as the device
- * memory they need fits the budget; admitted requests run concurrently on
- * the device, results stay in server memory until fetched. */
+ * A server owns a worker thread and one device stream per in-flight slot.
+ * Requests (host location arrays plus parameters) are admitted as long as
+ * the device memory they need fits the budget; admitted requests run
+ * concurrently on the device, results stay in server memory until fetched.
+ * Each slot holds pinned host staging for its largest batch (4096 locations
+ * at n = 128: about (540 + 8 p) x 4096 bytes), allocated at creation and
+ * released by lagp_server_destroy; submits and batches allocate no pinned
+ * memory. */
 
 /* Create a server on a design.  hbm_budget_bytes bounds the device memory
  * the admitted requests may hold at once; max_inflight bounds how many run
- * together (>= 1). */
+ * together (1 ..= 64).  LAGP_EDEVICE when a stream or the pinned staging
+ * cannot be created. */
 int32_t lagp_server_create(const lagp_design* design, size_t hbm_budget_bytes, int32_t max_inflight,
                            lagp_server** out);
 

@@ -24,6 +24,7 @@
 // over locations), so the workspace does not grow with the number of
 // locations.  Sums, the exp and the order of every operation are those of
 // the on-chip kernel: results are the same bit for bit.
+#include <atomic>
 #include <cstdlib>
 
 #include "dev_math.h"
@@ -354,13 +355,19 @@ size_t chol_stream_slot_bytes(int n, int ncand, int p) {
 }
 
 int chol_stream_max_slots(int ncand) {
+  // resident workgroups per device, per kernel variant (cached: admission
+  // control asks for it per request)
+  static std::atomic<int> cached[2][64] = {};
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
+  const int v = cw_cpt(ncand) == 4 ? 0 : 1;
+  if (dev >= 0 && dev < 64 && cached[v][dev].load() > 0) return cached[v][dev].load();
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
   const void* fn = cw_cpt(ncand) == 4 ? reinterpret_cast<const void*>(&k_cholw<4, true>)
                                       : reinterpret_cast<const void*>(&k_cholw<8, true>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, cw_threads(ncand), 0) != hipSuccess || per < 1)
     per = 1;
+  if (dev >= 0 && dev < 64) cached[v][dev].store(cus * per);
   return cus * per;
 }
 

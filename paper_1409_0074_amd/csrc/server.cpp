@@ -5,7 +5,9 @@
 // to a location cap), admits the batch when the device memory it needs (its
 // inputs, outputs and prediction workspace) fits under the HBM budget and a
 // stream slot is free, and launches it: upload, candidate search, local
-// designs, download, all asynchronous on the slot's stream.  Batches on
+// designs, download, all asynchronous on the slot's stream (through pinned
+// staging that each slot owns from creation, so no pinned allocation happens
+// per request or batch).  Batches on
 // different slots overlap on the device; a request that arrives while others
 // run is admitted as soon as memory and a slot free up.  A head batch that
 // does not fit may be bypassed by smaller batches a bounded number of times,
@@ -43,7 +45,7 @@ struct Request {
   lagp_params P{};
   int64_t M = 0;
   int p = 0;
-  double* xx = nullptr;  // pinned host, M x p
+  std::vector<double> xx;  // host copy, M x p
   // results (pinned host), filled by the batch that ran the request
   double* mean = nullptr;
   double* s2 = nullptr;
@@ -63,20 +65,20 @@ struct Batch {
   size_t bytes = 0;  // device bytes held while in flight
   int slot = -1;
   void* dev = nullptr;
-  char* host = nullptr;  // pinned staging: xx in, results out
+  char* host = nullptr;  // the slot's pinned staging: xx in, results out
   hipEvent_t ev = nullptr;
 };
 
 bool same_params(const lagp_params& a, const lagp_params& b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
 
-void free_host(Request& r) {
-  if (r.xx) (void)hipHostFree(r.xx);
-  r.xx = nullptr;
-}
+void free_host(Request& r) { std::vector<double>().swap(r.xx); }
 
 size_t io_bytes(int64_t M, int p, int n) {
   return (size_t)M * (sizeof(double) * p + 3 * sizeof(double) + sizeof(int32_t) * n + sizeof(int32_t));
 }
+
+// Pinned staging of one slot: the largest batch's locations and results.
+size_t stage_bytes(int p) { return io_bytes(BATCH_MAX_LOCATIONS, p, LAGP_MAX_N) + 256; }
 
 }  // namespace
 
@@ -87,6 +89,7 @@ struct lagp_server {
   int max_inflight = 1;
   std::vector<hipStream_t> streams;
   std::vector<bool> slot_busy;
+  std::vector<char*> stage;  // pinned host staging per slot
 
   std::mutex mu;
   std::condition_variable cv_work;  // worker wake-up
@@ -152,14 +155,12 @@ int32_t launch_batch(lagp_server* s, Batch& b) {
   hipStream_t st = s->streams[b.slot];
   const size_t xb = sizeof(double) * (size_t)M * p, db = sizeof(double) * (size_t)M,
                sb = sizeof(int32_t) * (size_t)M * n, tb = sizeof(int32_t) * (size_t)M;
-  const size_t host_bytes = xb + 3 * db + sb + tb;
-  if (hipHostMalloc(reinterpret_cast<void**>(&b.host), host_bytes, hipHostMallocDefault) != hipSuccess)
-    return LAGP_ENOMEM;
+  b.host = s->stage[b.slot];  // (xb + 3 db + sb + tb <= stage_bytes: M <= BATCH_MAX_LOCATIONS, n <= LAGP_MAX_N)
   char* h = b.host;
   double* hx = reinterpret_cast<double*>(h);
   int64_t off = 0;
   for (auto& r : b.reqs) {
-    std::memcpy(hx + off * p, r->xx, sizeof(double) * r->M * p);
+    std::memcpy(hx + off * p, r->xx.data(), sizeof(double) * r->M * p);
     off += r->M;
   }
   if (hipMallocAsync(&b.dev, xb + 3 * db + sb + tb, st) != hipSuccess) return LAGP_ENOMEM;
@@ -223,8 +224,7 @@ void finish_batch(lagp_server* s, Batch& b, int32_t rc) {
     s->t_last = now;
   }
   (void)p;
-  if (b.host) (void)hipHostFree(b.host);
-  b.host = nullptr;
+  b.host = nullptr;  // (the slot's staging, kept for its next batch)
   if (b.ev) (void)hipEventDestroy(b.ev);
   b.ev = nullptr;
   s->bytes_in_use -= b.bytes;
@@ -281,7 +281,8 @@ void worker_main(lagp_server* s) {
       const int32_t rc = launch_batch(s, b);
       lk.lock();
       if (rc != LAGP_OK) {
-        if (b.ev == nullptr) (void)hipStreamSynchronize(s->streams[slot]);
+        // drain what was queued: the slot's staging is reused by its next batch
+        (void)hipStreamSynchronize(s->streams[slot]);
         if (b.dev) (void)hipFree(b.dev);
         b.dev = nullptr;
         finish_batch(s, b, rc);
@@ -330,12 +331,17 @@ int32_t lagp_server_create(const lagp_design* design, size_t hbm_budget_bytes, i
   }
   s->streams.resize(max_inflight, nullptr);
   s->slot_busy.assign(max_inflight, false);
+  s->stage.assign(max_inflight, nullptr);
   for (int k = 0; k < max_inflight; ++k) {
-    if (hipStreamCreateWithFlags(&s->streams[k], hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&s->streams[k], hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&s->stage[k]), stage_bytes(design->p), hipHostMallocDefault) !=
+            hipSuccess) {
       for (auto st : s->streams)
         if (st) (void)hipStreamDestroy(st);
+      for (auto h : s->stage)
+        if (h) (void)hipHostFree(h);
       delete s;
-      return server_fail(LAGP_EDEVICE, "stream creation failed");
+      return server_fail(LAGP_EDEVICE, "stream or pinned staging creation failed");
     }
   }
   s->worker = std::thread(worker_main, s);
@@ -357,10 +363,7 @@ int32_t lagp_server_submit(lagp_server* s, const double* XX_host, int64_t M, con
   r->P = *P;
   r->M = M;
   r->p = s->design->p;
-  const size_t xb = sizeof(double) * (size_t)M * r->p;
-  if (hipHostMalloc(reinterpret_cast<void**>(&r->xx), xb, hipHostMallocDefault) != hipSuccess)
-    return server_fail(LAGP_ENOMEM, "pinned staging allocation failed");
-  std::memcpy(r->xx, XX_host, xb);
+  r->xx.assign(XX_host, XX_host + (size_t)M * r->p);
   r->t_submit = clk::now();
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -470,6 +473,8 @@ void lagp_server_destroy(lagp_server* s) {
   }
   for (auto st : s->streams)
     if (st) (void)hipStreamDestroy(st);
+  for (auto h : s->stage)
+    if (h) (void)hipHostFree(h);
   delete s;
 }
 

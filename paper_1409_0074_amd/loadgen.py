@@ -18,11 +18,12 @@ from . import workloads as W
 
 
 def request_params(base: W.Params, req: W.Request) -> W.Params:
-    """A request's method parameters: exhaustive FP64 requests whose shape
-    the Cholesky-column kernel holds (n <= 50, N' <= 1024) are scored that
-    way, the rest by the partitioned-inverse form."""
+    """A request's method parameters: exhaustive FP64 requests are scored by
+    Cholesky columns (on chip up to n = 50 and N' = 1024, streamed from a
+    workspace beyond), mixed-form requests by the partitioned-inverse form
+    the mixed screen applies to."""
     ncand = max(base.ncand, req.n + 64)
-    chol = req.search == W.SEARCH_EXHAUSTIVE and req.precision == W.PREC_FP64 and req.n <= 50 and ncand <= 1024
+    chol = req.search == W.SEARCH_EXHAUSTIVE and req.precision == W.PREC_FP64
     return base.replace(n=req.n, search=req.search, precision=req.precision, ncand=ncand,
                         scoring=W.SCORING_CHOL if chol else W.SCORING_PARTINV)
 

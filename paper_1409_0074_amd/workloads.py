@@ -225,8 +225,9 @@ class Request:
 def serving_requests(count: int, qps: float, precision_mix: float = 0.0, p: int = 4) -> list[Request]:
     """Open-loop Poisson arrivals at rate ``qps``; each request carries
     floor(10**U(0,3)) locations (1..1000, log-uniform), n from {30, 50, 100},
-    exhaustive or ray search at 50/50, and the mixed form with probability
-    ``precision_mix``."""
+    exhaustive or ray search at 50/50, and an exhaustive request in the
+    mixed form with probability ``precision_mix`` (the mixed screen scores
+    exhaustive searches only)."""
     rng = _rng(4, 2)
     t = 0.0
     out = []
@@ -237,7 +238,8 @@ def serving_requests(count: int, qps: float, precision_mix: float = 0.0, p: int 
         XX = rng.random((m, p))
         n = int(rng.choice([30, 50, 100]))
         search = SEARCH_RAY if rng.random() < 0.5 else SEARCH_EXHAUSTIVE
-        prec = PREC_MIXED if rng.random() < precision_mix else PREC_FP64
+        mixed = rng.random() < precision_mix
+        prec = PREC_MIXED if mixed and search == SEARCH_EXHAUSTIVE else PREC_FP64
         out.append(Request(t, XX, n, search, prec))
     return out
 
