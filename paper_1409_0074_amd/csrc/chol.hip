@@ -51,7 +51,7 @@ struct ChCfg {
   static constexpr int UL = BL * CH_CHUNK;
   static constexpr int NR = NB - BL;
   static constexpr int NUP = NB * CH_CHUNK;
-  static constexpr int SS = NUP + 4;  // slot: u, then v, 1/sqrt(v), cov/sqrt(v), q/sqrt(v)
+  static constexpr int SS = NUP + 4;  // slot: u, then v, cov, q (and one unused word)
   static constexpr int NCH = NB + 1;  // step blocks: j = 0 .. 8 NB + 1
   static constexpr int NT = CS / 2;   // largest workgroup
   static constexpr int NWV = NT / 64;
@@ -175,31 +175,54 @@ struct ChRun {
 
 // Gaussian correlation between the winner w and candidate c in the rounding
 // of corr(): dimension order, one fused multiply-add per term (the zero rows
-// past p add exact zeros).  The coordinates of c come in a (c, c+1) pair.
-template <int PM>
-__device__ __forceinline__ void ch_corr2(const double* xs, int CS, int w, int c0, const double* ec, const LocalArgs& A,
-                                         double w0, double& k0, double& k1) {
-  const auto coef = [ec](int i) { return ec[i]; };
-  double s0 = 0.0, s1 = 0.0;
+// past p add exact zeros).  The coordinates of c come in a (c, c+1) pair;
+// every coordinate is loaded before any is used, and the two exps run in
+// lockstep.
+template <int PM, bool ISO, int G>
+__device__ __forceinline__ void ch_dist2(const double* xs, int CS, int w, int c0, const LocalArgs& A, double (&e)[2]) {
 #pragma unroll
-  for (int k = 0; k < PM; ++k) {
-    const double xw = xs[k * CS + w];
-    const double2 xc = *reinterpret_cast<const double2*>(xs + k * CS + c0);
-    const double t0 = xw - xc.x, t1 = xw - xc.y;
-    if (A.dlen == 1) {
-      s0 = __builtin_fma(t0, t0, s0);
-      s1 = __builtin_fma(t1, t1, s1);
-    } else {
-      s0 = __builtin_fma(t0 * t0, A.w[k], s0);
-      s1 = __builtin_fma(t1 * t1, A.w[k], s1);
+  for (int k0 = 0; k0 < PM; k0 += G) {
+    double xw[G];
+    double2 xc[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      xw[k] = xs[(k0 + k) * CS + w];
+      xc[k] = *reinterpret_cast<const double2*>(xs + (k0 + k) * CS + c0);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const double t0 = xw[k] - xc[k].x, t1 = xw[k] - xc[k].y;
+      if constexpr (ISO) {
+        e[0] = __builtin_fma(t0, t0, e[0]);
+        e[1] = __builtin_fma(t1, t1, e[1]);
+      } else {
+        e[0] = __builtin_fma(t0 * t0, A.w[k0 + k], e[0]);
+        e[1] = __builtin_fma(t1 * t1, A.w[k0 + k], e[1]);
+      }
     }
   }
+}
+
+template <int PM>
+__device__ __forceinline__ void ch_corr2(const double* xs, int CS, int w, int c0, const double* ec,
+                                         const LocalArgs& A, double w0, double& k0, double& k1) {
+  // dimensions whose coordinates are in flight together (fewer where the
+  // wide coordinate rows leave fewer registers)
+  constexpr int G = PM > 8 ? 2 : 4;
+  static_assert(PM % G == 0, "coordinate rows come in whole groups");
+  double e[2] = {0.0, 0.0};
   if (A.dlen == 1) {
-    s0 = s0 * w0;
-    s1 = s1 * w0;
+    ch_dist2<PM, true, G>(xs, CS, w, c0, A, e);
+    e[0] = -(e[0] * w0);
+    e[1] = -(e[1] * w0);
+  } else {
+    ch_dist2<PM, false, G>(xs, CS, w, c0, A, e);
+    e[0] = -e[0];
+    e[1] = -e[1];
   }
-  k0 = gexp_with(-s0, coef);
-  k1 = gexp_with(-s1, coef);
+  gexp_lockstep_with(e, [ec](int i) { return ec[i]; });
+  k0 = e[0];
+  k1 = e[1];
 }
 
 // u entries in use during step block B (whole blocks; entries not yet
@@ -224,25 +247,40 @@ __device__ __forceinline__ void ch_write_slot(double* sl, const ChPair<ChCfg<NB,
       sl[k] = W == 0 ? S.r0[b][k % CH_CHUNK] : S.r1[b][k % CH_CHUNK];
     }
   }
-  // the quantities every candidate needs from the winner, computed here by
-  // the candidate's own lane, before the barrier
-  const double v = S.v[W], li = 1.0 / __builtin_sqrt(v);
-  sl[C::NUP] = v;
-  sl[C::NUP + 1] = li;
-  sl[C::NUP + 2] = S.cov[W] * li;
-  sl[C::NUP + 3] = S.q[W] * li;
+  sl[C::NUP] = S.v[W];
+  sl[C::NUP + 1] = S.cov[W];
+  sl[C::NUP + 2] = S.q[W];
 }
 
+// The criterion of an available candidate (-1 for a taken one, never
+// chosen; v <= 0 scores 0 and raises the flag; NaN scores -1).  Straight
+// line: the quotient is formed whatever v is and selected afterwards.
 __device__ __forceinline__ double ch_score(const double v, const double cov, bool act, int& vflag) {
-  if (!act) return -1.0;
-  double sc;
-  if (v > 0.0) {
-    sc = cov * cov / v;
-  } else {
-    sc = 0.0;
-    vflag = 1;
-  }
-  return sc >= 0.0 ? sc : -1.0;  // NaN: never chosen
+  const double qt = (cov * cov) / v;
+  const bool pos = v > 0.0;
+  const double sc = pos ? qt : 0.0;
+  vflag |= (act && !pos) ? 1 : 0;
+  return (act && sc >= 0.0) ? sc : -1.0;
+}
+
+// Maximum of a 32-bit key over lanes 0 .. 7 (the other lanes hold 0): quad
+// swaps and the half-row mirror leave it in lane 0.
+__device__ __forceinline__ uint32_t ch_max8_u(uint32_t v) {
+  v = max(v, ch_dpp_u<0xB1, 0xF>(v));
+  v = max(v, ch_dpp_u<0x4E, 0xF>(v));
+  v = max(v, ch_dpp_u<0x141, 0xF>(v));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+}
+
+// ch_wave_argmax for criteria held by lanes 0 .. 7 only (-1 elsewhere).
+__device__ __forceinline__ uint64_t ch_argmax8(double sc) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, sc);
+  const bool ok = sc >= 0.0;
+  const uint32_t hi = ok ? (uint32_t)(b >> 32) | 0x80000000u : 0u;
+  const uint32_t lo = (uint32_t)b;
+  const uint32_t mhi = ch_max8_u(hi);
+  const uint32_t mlo = ch_max8_u(hi == mhi ? lo : 0u);
+  return __ballot(ok && hi == mhi && lo == mlo);
 }
 
 // Steps j = B*CH_CHUNK .. B*CH_CHUNK + CH_CHUNK - 1: choose design point j
@@ -296,10 +334,12 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
       int ci = -1;
       if (lane < nwv) {
         ci = L.redi[par * NWV + lane];
-        cv = ci >= 0 ? L.redv[par * NWV + lane] : -1.0;
+        const double rv = L.redv[par * NWV + lane];
+        cv = ci >= 0 ? rv : -1.0;
         if constexpr (DIAG) c2 = L.red2[par * NWV + lane];
       }
-      const uint64_t gh = ch_wave_argmax(cv);
+      static_assert(NWV <= 8, "the cross-wave reduction covers eight waves");
+      const uint64_t gh = ch_argmax8(cv);
       if (!gh) {  // no finite criterion anywhere: give up on x
         R.stop = true;
         return;
@@ -310,7 +350,10 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
       if constexpr (DIAG) b2 = ch_wave_max(lane == ql ? c2 : fmax(cv, c2));
     }
     const double* ws = sl + (w >> 7) * SS;
-    const double vw = ws[NUP], li = ws[NUP + 1], wxj = ws[NUP + 2], zj = ws[NUP + 3];
+    const double vw = ws[NUP];
+    // the winner's new diagonal entry sqrt(v) and the new entries of w_x
+    // and z, formed by every wave (off the path to the next scores)
+    const double li = 1.0 / __builtin_sqrt(vw), wxj = ws[NUP + 1] * li, zj = ws[NUP + 2] * li;
     if (j < n0 && !(vw > 0.0)) {  // the starting covariance is not positive definite
       R.pd = false;
       R.stop = true;

@@ -67,46 +67,57 @@ __device__ __forceinline__ double gexp_with(double x, const Coef& coef) {
   return x < -708.0 ? 0.0 : (x > 709.0 ? __builtin_huge_val() : e);
 }
 
-// gexp_with on four arguments in lockstep: the same operations on each (the
-// same values), interleaved so that the four dependent chains overlap.
-__device__ __forceinline__ void gexp4(double (&x)[4]) {
+// gexp_with on U arguments in lockstep: the same operations on each (the
+// same values), interleaved so that the U dependent chains overlap.
+// coef(i) supplies gexp_coef(i) as in gexp_with.
+template <int U, class Coef>
+__device__ __forceinline__ void gexp_lockstep_with(double (&x)[U], const Coef& coef) {
   const double L2H = 0x1.62e42fefa39efp-1;
   const double L2L = 0x1.abc9e3b39803fp-56;
   const double IL2 = 0x1.71547652b82fep+0;
-  double xc[4], k[4], r[4], t[4];
+  double xc[U], k[U], r[U], t[U];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
     // (in range: x itself; outside it, and for NaN, the polynomial's value
     // is replaced below, so the clamp only keeps the scaling finite)
     xc[u] = __builtin_fmax(__builtin_fmin(x[u], 709.0), -708.0);
     k[u] = __builtin_rint(xc[u] * IL2);
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) r[u] = __builtin_fma(-k[u], L2H, xc[u]);
+  for (int u = 0; u < U; ++u) r[u] = __builtin_fma(-k[u], L2H, xc[u]);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
     r[u] = __builtin_fma(-k[u], L2L, r[u]);
-    t[u] = gexp_coef(0);
+    t[u] = coef(0);
   }
 #pragma unroll
-  for (int i = 1; i < 12; ++i)
+  for (int i = 1; i < 12; ++i) {
+    const double ci = coef(i);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) t[u] = __builtin_fma(t[u], r[u], gexp_coef(i));
+    for (int u = 0; u < U; ++u) t[u] = __builtin_fma(t[u], r[u], ci);
+  }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) t[u] = __builtin_fma(t[u], r[u], 1.0);
+  for (int u = 0; u < U; ++u) t[u] = __builtin_fma(t[u], r[u], 1.0);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) t[u] = __builtin_fma(t[u], r[u], 1.0);
+  for (int u = 0; u < U; ++u) t[u] = __builtin_fma(t[u], r[u], 1.0);
   // the final choice as arithmetic, so that the polynomial is always used
   // (no branch around it): fma(e, 1, 0) = e in range; fma(e, 0, c) = c with
   // c = 0 below it, +inf above it and x itself for NaN (e is finite)
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
     const double e = __builtin_ldexp(t[u], (int)k[u]);
     const bool in = x[u] >= -708.0 && x[u] <= 709.0;
     const double c = x[u] != x[u] ? x[u] : (x[u] > 709.0 ? __builtin_huge_val() : 0.0);
     x[u] = __builtin_fma(e, in ? 1.0 : 0.0, c);
   }
 }
+
+template <int U>
+__device__ __forceinline__ void gexp_lockstep(double (&x)[U]) {
+  gexp_lockstep_with(x, gexp_coef);
+}
+
+__device__ __forceinline__ void gexp4(double (&x)[4]) { gexp_lockstep<4>(x); }
 
 // The same function with the out-of-range cases as early returns and the
 // coefficients as constants (the form the partitioned-inverse kernels were
