@@ -44,12 +44,14 @@ typedef double v8d __attribute__((ext_vector_type(8)));
 // slots, the LDS row stride (N' <= CS), two per thread.
 template <int NB, int PM, int CS>
 struct ChCfg {
-  // the first BL blocks of every u_c live in LDS (ul[k * CS + c]), the other
-  // NR in registers, one 8-vector each (an entry is appended at a run-time
-  // position with one indexed register move)
+  // the first NR blocks of every u_c live in registers, one 8-vector each
+  // (an entry is appended at a run-time position with one indexed register
+  // move), the last BL in LDS (entry RE + k of candidate c at ul[k * CS + c]):
+  // the steps before entry RE is appended read no u entry from LDS
   static constexpr int BL = NB > 4 ? 1 : 0;
   static constexpr int UL = BL * CH_CHUNK;
   static constexpr int NR = NB - BL;
+  static constexpr int RE = NR * CH_CHUNK;
   static constexpr int NUP = NB * CH_CHUNK;
   static constexpr int SS = NUP + 4;  // slot: u, then v, cov, q (and one unused word)
   static constexpr int NCH = NB + 1;  // step blocks: j = 0 .. 8 NB + 1
@@ -57,7 +59,7 @@ struct ChCfg {
   static constexpr int NWV = NT / 64;
 };
 
-// LDS: coordinates by dimension (PM x CS), the leading u entries (UL x CS),
+// LDS: coordinates by dimension (PM x CS), the trailing u entries (UL x CS),
 // two parities of per-wave slots and reduction words, the location, the exp
 // coefficients, the design ranks.
 struct ChLds {
@@ -156,8 +158,8 @@ __device__ __forceinline__ uint64_t ch_wave_argmax(double sc) {
   return __ballot(ok && hi == mhi && lo == mlo);
 }
 
-// Per-thread state of the candidate pair (2t, 2t+1); u blocks below BL are
-// in LDS, block BL + i in r0[i] / r1[i].
+// Per-thread state of the candidate pair (2t, 2t+1); u block i < NR in
+// r0[i] / r1[i], the later ones in LDS.
 template <int NR>
 struct ChPair {
   v8d r0[NR > 0 ? NR : 1], r1[NR > 0 ? NR : 1];
@@ -240,11 +242,10 @@ __device__ __forceinline__ void ch_write_slot(double* sl, const ChPair<ChCfg<NB,
   const int c = 2 * threadIdx.x + W;
 #pragma unroll
   for (int k = 0; k < KE; ++k) {
-    if (k < C::UL) {
-      sl[k] = L.ul[k * CS + c];
+    if (k >= C::RE) {
+      sl[k] = L.ul[(k - C::RE) * CS + c];
     } else {
-      const int b = k / CH_CHUNK - C::BL < 0 ? 0 : k / CH_CHUNK - C::BL;
-      sl[k] = W == 0 ? S.r0[b][k % CH_CHUNK] : S.r1[b][k % CH_CHUNK];
+      sl[k] = W == 0 ? S.r0[k / CH_CHUNK][k % CH_CHUNK] : S.r1[k / CH_CHUNK][k % CH_CHUNK];
     }
   }
   sl[C::NUP] = S.v[W];
@@ -290,7 +291,7 @@ template <int NB, int PM, int CS, bool DIAG, int B>
 __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChPair<ChCfg<NB, PM, CS>::NR>& S,
                                          ChRun& R, int64_t m, double w0) {
   using C = ChCfg<NB, PM, CS>;
-  constexpr int NUP = C::NUP, SS = C::SS, UL = C::UL, NWV = C::NWV, BL = C::BL;
+  constexpr int NUP = C::NUP, SS = C::SS, NWV = C::NWV, NR = C::NR, RE = C::RE;
   constexpr int KE = ch_ke<NB, B>();
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nwv = blockDim.x >> 6;
@@ -387,22 +388,22 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
 #pragma unroll
       for (int k = 0; k < KE; ++k) {
         const double wk = ws[k];
-        if (k < UL) {
-          const double2 uu = *reinterpret_cast<const double2*>(L.ul + k * CS + c0);
+        if (k >= RE) {
+          const double2 uu = *reinterpret_cast<const double2*>(L.ul + (k - RE) * CS + c0);
           d0 = __builtin_fma(wk, uu.x, d0);
           d1 = __builtin_fma(wk, uu.y, d1);
         } else {
-          d0 = __builtin_fma(wk, S.r0[k / CH_CHUNK - BL < 0 ? 0 : k / CH_CHUNK - BL][k % CH_CHUNK], d0);
-          d1 = __builtin_fma(wk, S.r1[k / CH_CHUNK - BL < 0 ? 0 : k / CH_CHUNK - BL][k % CH_CHUNK], d1);
+          d0 = __builtin_fma(wk, S.r0[k / CH_CHUNK][k % CH_CHUNK], d0);
+          d1 = __builtin_fma(wk, S.r1[k / CH_CHUNK][k % CH_CHUNK], d1);
         }
       }
       const double e0 = (kv0 - d0) * li, e1 = (kv1 - d1) * li;
       // append u[j] (the entry of the last update, j = 8 NB, is never read)
-      if constexpr (B < BL) {
-        *reinterpret_cast<double2*>(L.ul + j * CS + c0) = make_double2(e0, e1);
+      if constexpr (B < NR) {
+        S.r0[B][jj] = e0;
+        S.r1[B][jj] = e1;
       } else if constexpr (B < NB) {
-        S.r0[B - BL][jj] = e0;
-        S.r1[B - BL][jj] = e1;
+        *reinterpret_cast<double2*>(L.ul + (j - RE) * CS + c0) = make_double2(e0, e1);
       }
       S.v[0] = __builtin_fma(-e0, e0, S.v[0]);
       S.v[1] = __builtin_fma(-e1, e1, S.v[1]);
