@@ -77,6 +77,13 @@ extern "C" {
                                   shapes keep them in a device workspace of about
                                   8 (n + p) ncand bytes per resident workgroup. */
 
+/* snap scope of ray search (Sec. 4: the continuous optimum is snapped to a
+ * design point; Sec. 5: ray searches are not restricted to the N' nearest) */
+#define LAGP_SNAP_CANDIDATES 0 /* the nearest of the ncand candidates */
+#define LAGP_SNAP_DESIGN 1     /* the nearest of the whole design, through a cell grid of the design
+                                  built on first use (lagp_design_build_grid); ncand then only has to
+                                  hold the ray starts */
+
 /* per-location status bits */
 #define LAGP_STATUS_VNONPOS 1   /* a Schur complement v <= 0 was met; scored as 0 */
 #define LAGP_STATUS_NONFINITE 2 /* non-finite mean or scale */
@@ -101,7 +108,8 @@ typedef struct lagp_server lagp_server;
  *   rescore_k: size of the FP64 re-scored shortlist in the mixed form (1..64);
  *   scoring: LAGP_SCORING_* (exhaustive search only; 0 otherwise);
  *   brent_maxit, brent_tol: Brent line-search budget (<= 0: 100) and
- *     tolerance (<= 0: 2^-13). */
+ *     tolerance (<= 0: 2^-13);
+ *   snap: LAGP_SNAP_* (ray search only; 0 otherwise); reserved: 0. */
 typedef struct {
   int32_t n0;
   int32_t n;
@@ -116,6 +124,8 @@ typedef struct {
   int32_t brent_maxit;
   int32_t scoring;
   double brent_tol;
+  int32_t snap;
+  int32_t reserved;
 } lagp_params;
 
 /* Local maximum likelihood of an isotropic lengthscale (Sec. 5: every
@@ -155,6 +165,17 @@ int32_t lagp_design_create(const double* X, const double* y, int64_t N, int32_t 
 
 /* Release a design handle (NULL is ignored).  Synchronises the device. */
 void lagp_design_destroy(lagp_design* design);
+
+/* Build the design's cell grid for snaps over the whole design (ray search
+ * with snap = LAGP_SNAP_DESIGN, Sec. 5) if it is not built yet: the first
+ * min(p, 3) coordinates cut into about N / 2 cells (at most 2^22) between
+ * their minimum and maximum, each row and its coordinates grouped by cell.
+ * Device memory N (8 p + 4) + 4 (cells + 1) bytes, owned by the handle and
+ * freed with it.  Synchronous (the stream is synchronised before return);
+ * thread-safe.  The predict calls build it themselves on first use; callers
+ * that must not allocate during them (lagp_predict_noalloc) call this
+ * first.  LAGP_EINVAL on a NULL design, LAGP_ENOMEM, LAGP_EDEVICE. */
+int32_t lagp_design_build_grid(const lagp_design* design, void* stream);
 
 /* Dimensions of a design handle. */
 int32_t lagp_design_info(const lagp_design* design, int64_t* N, int32_t* p);

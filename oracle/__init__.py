@@ -125,9 +125,16 @@ def knn(X, XX, ncand: int, nthreads: int | None = None):
     return idx, d2
 
 
-def _par(params, p):
+def _ncand(params, N):
+    """N' as the search sees it: a ray search that snaps over the whole design
+    (Sec. 5 places no N' limit on ray searches) is the same search with every
+    design row a candidate, nearest first."""
+    return N if getattr(params, "snap", 0) == 1 else params.ncand
+
+
+def _par(params, p, N):
     d = _f64(np.atleast_1d(params.d))
-    return d, [params.n0, params.n, params.ncand, params.search, params.numrays, _p(d), len(d), params.g,
+    return d, [params.n0, params.n, _ncand(params, N), params.search, params.numrays, _p(d), len(d), params.g,
                params.brent_maxit, params.brent_tol, getattr(params, "scoring", 0)]
 
 
@@ -140,7 +147,7 @@ def predict(X, y, XX, params, forced=None, nthreads: int | None = None):
     M = XX.shape[0]
     n, n0 = params.n, params.n0
     nd = 0 if params.search == 2 else n - n0
-    d, par = _par(params, p)
+    d, par = _par(params, p, N)
     out = dict(mean=np.empty(M), s2=np.empty(M), df=np.empty(M), sel=np.empty((M, n), np.int32),
                diag=np.empty((M, nd, NDIAG)), status=np.empty(M, np.int32))
     fz = None if forced is None else np.ascontiguousarray(forced, dtype=np.int32)
@@ -157,9 +164,9 @@ def trace(X, y, x, params, forced=None):
     the final inverse and the candidate list (for brute-force checks)."""
     X, y, x = _f64(X), _f64(y), _f64(np.ravel(x))
     N, p = X.shape
-    n, n0, nc = params.n, params.n0, params.ncand
+    n, n0, nc = params.n, params.n0, _ncand(params, N)
     nd = 0 if params.search == 2 else n - n0
-    d, par = _par(params, p)
+    d, par = _par(params, p, N)
     mean, s2, df = (ctypes.c_double(), ctypes.c_double(), ctypes.c_double())
     out = dict(sel=np.empty(n, np.int32), diag=np.empty((nd, NDIAG)), alc=np.empty((nd, nc)),
                Ki=np.empty((n, n)), cand=np.empty(nc, np.int64))
@@ -186,7 +193,7 @@ def predict_mle(X, y, XX, params, mode: int, dmin: float = 0.0, dmax: float = 0.
     d0 = float(np.atleast_1d(params.d)[0])
     out = dict(mean=np.empty(M), s2=np.empty(M), df=np.empty(M), sel=np.empty((M, n), np.int32),
                dhat=np.empty(M), iters=np.empty(M, np.int32), status=np.empty(M, np.int32))
-    rc = lib().orc_predict_mle(_p(X), _p(y), N, p, _p(XX), M, params.n0, n, params.ncand, params.search,
+    rc = lib().orc_predict_mle(_p(X), _p(y), N, p, _p(XX), M, params.n0, n, _ncand(params, N), params.search,
                                params.numrays, d0, params.g, params.brent_maxit, params.brent_tol,
                                getattr(params, "scoring", 0), mode, dmin, dmax, tol, maxit,
                                nthreads or default_threads(), _p(out["mean"]), _p(out["s2"]), _p(out["df"]),

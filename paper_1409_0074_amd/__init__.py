@@ -41,6 +41,7 @@ LAGP_STATUS_MLE_MAXIT = 64
 
 EXPORTED = [
     "lagp_version", "lagp_last_error", "lagp_design_create", "lagp_design_destroy", "lagp_design_info",
+    "lagp_design_build_grid",
     "lagp_candidates", "lagp_predict", "lagp_predict_candidates", "lagp_predict_counts", "lagp_predict_noalloc",
     "lagp_predict_mle",
     "lagp_fit_separable",
@@ -55,6 +56,7 @@ class lagp_params(ctypes.Structure):
         ("search", ctypes.c_int32), ("precision", ctypes.c_int32), ("d_len", ctypes.c_int32),
         ("rescore_k", ctypes.c_int32), ("d", ctypes.c_double * LAGP_MAX_DIM), ("g", ctypes.c_double),
         ("brent_maxit", ctypes.c_int32), ("scoring", ctypes.c_int32), ("brent_tol", ctypes.c_double),
+        ("snap", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -90,6 +92,8 @@ def lib():
         L.lagp_design_destroy.restype = None
         L.lagp_design_info.argtypes = [_vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.lagp_design_info.restype = i32
+        L.lagp_design_build_grid.argtypes = [_vp, _vp]
+        L.lagp_design_build_grid.restype = i32
         L.lagp_candidates.argtypes = [_vp, _vp, i64, i32, _vp, _vp, _vp]
         L.lagp_candidates.restype = i32
         L.lagp_predict.argtypes = [_vp, _vp, i64, pp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -165,6 +169,7 @@ def make_params(params=None, **kw) -> lagp_params:
     P.brent_maxit = src.brent_maxit
     P.brent_tol = float(src.brent_tol)
     P.scoring = src.scoring
+    P.snap = src.snap
     return P
 
 
@@ -187,6 +192,10 @@ def lagp_design_create(X, y, stream=None):
 
 def lagp_design_destroy(design) -> None:
     lib().lagp_design_destroy(design)
+
+
+def lagp_design_build_grid(design, stream=None) -> int:
+    return _check(lib().lagp_design_build_grid(design, _stream(stream)))
 
 
 def lagp_design_info(design):

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblagp.so")
-SOURCES = ["knn.hip", "local.hip", "chol.hip", "cholws.hip", "mle.hip", "sepfit.hip", "api.cpp", "server.cpp"]
+SOURCES = ["knn.hip", "local.hip", "chol.hip", "cholws.hip", "mle.hip", "sepfit.hip", "grid.hip", "api.cpp",
+           "server.cpp"]
 ARCH = os.environ.get("LAGP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -78,6 +78,10 @@ int32_t check_params(const lagp_design* d, const lagp_params* P, int* rays) {
   for (int k = 0; k < P->d_len; ++k)
     if (!(P->d[k] > 0.0) || !std::isfinite(P->d[k])) return fail(LAGP_EINVAL, "lengthscales must be finite and > 0");
   if (!(P->g >= 0.0) || !std::isfinite(P->g)) return fail(LAGP_EINVAL, "nugget g must be finite and >= 0");
+  if (P->snap != LAGP_SNAP_CANDIDATES && P->snap != LAGP_SNAP_DESIGN)
+    return fail(LAGP_EINVAL, "snap must be LAGP_SNAP_CANDIDATES or LAGP_SNAP_DESIGN");
+  if (P->snap == LAGP_SNAP_DESIGN && P->search != LAGP_SEARCH_RAY)
+    return fail(LAGP_EINVAL, "snap over the whole design applies to ray search only");
   *rays = 0;
   if (P->search == LAGP_SEARCH_RAY) {
     const int R = P->numrays > 0 ? P->numrays : p;
@@ -177,7 +181,8 @@ int32_t lagp_design_create(const double* X, const double* y, int64_t N, int32_t 
   if (e == hipSuccess) e = lagp::launch_bbox(d->X, N, p, d->lo, d->hi, s);
   if (e == hipSuccess) e = lagp::launch_row_norms(d->X, N, p, d->rn, rmax, d->X32, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&d->rn_max, rmax, sizeof(double), hipMemcpyDeviceToHost, s);
-  double lo[LAGP_MAX_DIM], hi[LAGP_MAX_DIM];
+  double* lo = d->lo_h;
+  double* hi = d->hi_h;
   if (e == hipSuccess) e = hipMemcpyAsync(lo, d->lo, sizeof(double) * p, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipMemcpyAsync(hi, d->hi, sizeof(double) * p, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -202,7 +207,40 @@ void lagp_design_destroy(lagp_design* d) {
   if (d->hi) (void)hipFree(d->hi);
   if (d->rn) (void)hipFree(d->rn);
   if (d->X32) (void)hipFree(d->X32);
+  if (d->grid_Xs) (void)hipFree(d->grid_Xs);
+  if (d->grid_rows) (void)hipFree(d->grid_rows);
+  if (d->grid_start) (void)hipFree(d->grid_start);
   delete d;
+}
+
+int32_t lagp_design_build_grid(const lagp_design* dc, void* stream) {
+  if (!dc) return fail(LAGP_EINVAL, "design is NULL");
+  lagp_design* d = const_cast<lagp_design*>(dc);  // the grid is a cache: the design itself is unchanged
+  std::lock_guard<std::mutex> lk(d->grid_mu);
+  if (d->grid_built) return LAGP_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  lagp::GridDev g = lagp::grid_plan(d->N, d->p, d->lo_h, d->hi_h);
+  const int64_t cells = lagp::grid_cells(g);
+  int32_t *cid = nullptr, *cnt = nullptr;
+  auto release = [&]() {
+    if (cid) (void)hipFree(cid);
+    if (cnt) (void)hipFree(cnt);
+  };
+  if (hipMalloc(&d->grid_Xs, sizeof(double) * (size_t)d->N * d->p) != hipSuccess ||
+      hipMalloc(&d->grid_rows, sizeof(int32_t) * (size_t)d->N) != hipSuccess ||
+      hipMalloc(&d->grid_start, sizeof(int32_t) * (size_t)(cells + 1)) != hipSuccess ||
+      hipMalloc(&cid, sizeof(int32_t) * (size_t)d->N) != hipSuccess ||
+      hipMalloc(&cnt, sizeof(int32_t) * (size_t)cells) != hipSuccess) {
+    release();
+    return fail(LAGP_ENOMEM, "device allocation of the design grid failed");
+  }
+  hipError_t e = lagp::launch_grid_build(d->X, d->N, d->p, g, cid, cnt, d->grid_start, d->grid_Xs, d->grid_rows, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release();
+  if (e != hipSuccess) return fail(LAGP_EDEVICE, std::string("design grid: ") + hipGetErrorString(e));
+  d->grid = g;
+  d->grid_built = true;
+  return LAGP_OK;
 }
 
 int32_t lagp_design_info(const lagp_design* d, int64_t* N, int32_t* p) {
@@ -274,7 +312,24 @@ lagp::LocalArgs local_args(const lagp_design* d, const lagp_params* P, int rays,
   a.brent_tol = P->brent_tol > 0.0 ? P->brent_tol : std::ldexp(1.0, -13);
   a.g = P->g;
   for (int q = 0; q < P->d_len; ++q) a.w[q] = 1.0 / P->d[q];
+  if (P->snap == LAGP_SNAP_DESIGN) {  // (the grid is built: ensure_grid)
+    a.snap_full = 1;
+    a.grid = d->grid;
+  }
   return a;
+}
+
+// A ray search that snaps over the whole design needs the design's cell
+// grid: built here on first use, unless the caller must not allocate.
+int32_t ensure_grid(const lagp_design* d, const lagp_params* P, void* stream, bool may_build) {
+  if (P->snap != LAGP_SNAP_DESIGN) return LAGP_OK;
+  {
+    std::lock_guard<std::mutex> lk(const_cast<lagp_design*>(d)->grid_mu);
+    if (d->grid_built) return LAGP_OK;
+  }
+  if (!may_build)
+    return fail(LAGP_EINVAL, "snap over the whole design needs the design grid: build it first (lagp_design_build_grid)");
+  return lagp_design_build_grid(d, stream);
 }
 
 // Cholesky scoring: the on-chip kernel where the columns fit in registers and
@@ -348,6 +403,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const int lds_max = max_lds_per_block();
   if (!cand_in && knn2_merge_lds_bytes(S) > (size_t)lds_max) return fail(LAGP_EINVAL, "ncand too large for LDS");
   const bool chol = P->scoring == LAGP_SCORING_CHOL;
+  if ((rc = ensure_grid(d, P, stream, ext_ws == nullptr)) != LAGP_OK) return rc;
   if (!chol && lagp::local_lds_bytes(n, ncs, p, rays, P->precision == LAGP_PREC_MIXED) > (size_t)lds_max)
     return fail(LAGP_EINVAL, "local design too large for LDS (n, p, numrays)");
   const int kc_rows = P->search == LAGP_SEARCH_EXHAUSTIVE ? (n + 3) / 4 * 4 : n0;  // exact tiles read whole chunks
@@ -513,6 +569,7 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
   if (mle->mode != 1 && mle->mode != 2) return fail(LAGP_EINVAL, "mle->mode must be 1 or 2");
   if (P->precision != LAGP_PREC_FP64) return fail(LAGP_EINVAL, "local MLE runs in FP64 only");
   if (P->d_len != 1) return fail(LAGP_EINVAL, "local MLE estimates one isotropic lengthscale: d_len must be 1");
+  if (M > 0 && (rc = lagp::ensure_grid(d, P, stream, true)) != LAGP_OK) return rc;
   const int p = d->p, n = P->n, nc = P->ncand;
   const bool chol = P->scoring == LAGP_SCORING_CHOL;  // else k_local's search (any mode)
   const double d0 = P->d[0];

@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/lagp.h"
+#include "grid.h"
 
 struct lagp_design {
   int64_t N;
@@ -17,6 +20,15 @@ struct lagp_design {
   double spread2;  // sum over dimensions of (max - min)^2 (chooses the kNN screen's precision)
   double rn_max;  // their maximum
   int device;
+  double lo_h[LAGP_MAX_DIM], hi_h[LAGP_MAX_DIM];  // host copies of lo, hi
+  // cell grid for snaps over the whole design (built on first use; the
+  // device arrays belong to the handle)
+  std::mutex grid_mu;
+  bool grid_built = false;
+  lagp::GridDev grid{};
+  double* grid_Xs = nullptr;
+  int32_t* grid_rows = nullptr;
+  int32_t* grid_start = nullptr;
 };
 
 namespace lagp {
@@ -58,6 +70,8 @@ struct LocalArgs {
                            // ray: Brent evaluations summed over the rays, the most of one ray;
                            // mixed: candidates whose FP32 upper bound reached the threshold,
                            // 16-candidate tiles re-scored in FP64; else: candidates scored, 0
+  int32_t snap_full;       // ray search: snap over the whole design through `grid` (else the candidates)
+  GridDev grid;
 };
 
 // Arguments of the local MLE kernel (mle.hip) for one chunk of locations.
@@ -162,6 +176,14 @@ hipError_t launch_sepfit(const SepArgs& a, hipStream_t s);
 hipError_t launch_prescale(const double* X, int64_t N, int p, const double* theta, double* out, hipStream_t s);
 
 hipError_t launch_bbox(const double* X, int64_t N, int p, double* lo, double* hi, hipStream_t s);
+
+// The cell grid of a design (grid.hip): its shape from N, p and the bounding
+// box; the build into caller-provided arrays (cid: N, cnt: cells scratch;
+// start: cells + 1, Xs: N x p, rows: N), which fills g's pointers.
+GridDev grid_plan(int64_t N, int p, const double* lo, const double* hi);
+int64_t grid_cells(const GridDev& g);
+hipError_t launch_grid_build(const double* X, int64_t N, int p, GridDev& g, int32_t* cid, int32_t* cnt,
+                             int32_t* start, double* Xs, int32_t* rows, hipStream_t s);
 
 // Shared by the C ABI and the server (api.cpp).
 int32_t check_predict_params(const lagp_design* d, const lagp_params* P);

@@ -65,9 +65,10 @@ struct Lds {
   double* redv;  // 2 NW
   double* scal;  // 8 scalars
   int* redi;     // NW
-  int* J;        // NP: ranks of the local design, selection order
+  int* J;        // NP: ranks of the local design, selection order (ncand: a row outside the candidates)
+  int* jrow;     // NP: design rows of the local design, selection order
   int* starts;   // R
-  int* ints;     // 8 scalars
+  int* ints;     // 16 scalars
   int* shortlist;  // max(64, ncs/16): mixed form, the 16-candidate tiles re-scored in FP64
   double* tps;     // 16: tile ray form, each ray's parameter this round
   int* tpe;        // 16: tile ray form, whether the ray is evaluated this round
@@ -121,8 +122,9 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool m
   take(sizeof(double) * 8);                // scal
   take(sizeof(int) * NW);                  // redi
   take(sizeof(int) * P.NP);                // J
+  take(sizeof(int) * P.NP);                // jrow
   take(sizeof(int) * P.R);                 // starts
-  take(sizeof(int) * 8);                   // ints
+  take(sizeof(int) * 16);                  // ints
   take(mixed ? sizeof(int) * (ncs / 16 > 64 ? ncs / 16 : 64) : 0);  // shortlist (tiles)
   take(tile ? sizeof(double) * 16 : 0);   // tps
   take(tile ? sizeof(int) * 16 : 0);      // tpe
@@ -144,6 +146,7 @@ __device__ inline Lds carve(unsigned char* s, const LdsPlan& P) {
   L.redv = D(); L.scal = D();
   L.redi = reinterpret_cast<int*>(s + P.off[k++]);
   L.J = reinterpret_cast<int*>(s + P.off[k++]);
+  L.jrow = reinterpret_cast<int*>(s + P.off[k++]);
   L.starts = reinterpret_cast<int*>(s + P.off[k++]);
   L.ints = reinterpret_cast<int*>(s + P.off[k++]);
   L.shortlist = reinterpret_cast<int*>(s + P.off[k++]);
@@ -754,16 +757,21 @@ __device__ __forceinline__ Best score_mixed(const LocalArgs& a, const Lds& L, in
 
 // ------------------------------------------------------------ update -----
 
-// Grow K^{-1} from j x j to (j+1) x (j+1) with candidate rank cs (the
-// partitioned inverse of Sec. 3.1), append cs to the design, and compute its
-// kernel row against every candidate.  Returns v_j of the added point.
+// Grow K^{-1} from j x j to (j+1) x (j+1) with candidate rank cs, design row
+// `row` (the partitioned inverse of Sec. 3.1), append it to the design, and
+// compute its kernel row against every candidate.  cs = ncand: a row that is
+// not among the candidates (a ray snapped over the whole design).  Returns
+// v_j of the added point.
 template <bool KROWS>  // exhaustive forms keep every candidate's kernel row
 __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, int LD, double* Kc, float* Kc32, const double* kxc,
-                            const double* Xc, int j, int cs) {
+                            const double* Xc, int j, int cs, int32_t row) {
   const int tid = threadIdx.x;
   const int ncs = a.ncs, p = a.p;
-  // the new point's coordinates (gathered in the prologue) join the design's
-  for (int k = tid; k < p; k += blockDim.x) L.xj[j * p + k] = Xc[(int64_t)cs * p + k];
+  const bool listed = cs < a.ncand;
+  // the new point's coordinates (gathered in the prologue, or the design's
+  // own) join the design's
+  for (int k = tid; k < p; k += blockDim.x)
+    L.xj[j * p + k] = listed ? Xc[(int64_t)cs * p + k] : a.X[(int64_t)row * p + k];
   __syncthreads();
   const double* xs = L.xj + j * p;
   // K(x_J, x_s): the same arguments, in the same order, as the stored rows
@@ -799,8 +807,13 @@ __device__ __forceinline__ double add_point(const LocalArgs& a, const Lds& L, in
   if (tid == 0) {
     L.Ki[j * LD + j] = 1.0 / v;
     L.J[j] = cs;
-    L.selm[cs] = 1;
-    L.kx[j] = kxc[cs];
+    L.jrow[j] = row;
+    if (listed) {
+      L.selm[cs] = 1;
+      L.kx[j] = kxc[cs];
+    } else {
+      L.kx[j] = corr(xs, L.x, p, L.w0, a.w, a.dlen);  // K(x_s, x) as kxc holds it
+    }
   }
   if (KROWS && j + 1 < a.n) {
     double* row = Kc + (int64_t)j * ncs;
@@ -1098,13 +1111,96 @@ __device__ __forceinline__ double ray_segment(const LocalArgs& a, const Lds& L, 
   return tt;
 }
 
+// Snap over the whole design (ray search not restricted to the N' nearest,
+// Sec. 5): the nearest design row to z, by (squared distance in dimension
+// order with one fma per term, row), outside the design and the step's
+// starts.  The design's cell grid is searched in boxes of cells around z's
+// cell, growing until every cell outside the box is provably farther than
+// the best row found (a row in a cell r + 1 or more cells away along a grid
+// coordinate lies at least (r - 1) narrowest cell widths away: one width of
+// slack per side for the rounding of the cell assignment).  Returns the
+// row's candidate rank when it is a candidate, else ncand with the row in
+// L.ints[8]; -1 if no row is left.
+__device__ int snap_design(const LocalArgs& a, const Lds& L, const int32_t* C, const double (&z)[LAGP_MAX_DIM], int j,
+                           int ns) {
+  const GridDev& g = a.grid;
+  const int tid = threadIdx.x, nt = blockDim.x, p = a.p;
+  int cz[GRID_Q] = {0, 0, 0};
+  for (int k = 0; k < g.q; ++k) cz[k] = grid_coord(g, k, z[k]);
+  // a row is excluded when it is in the design or a start of this step
+  const auto excluded = [&](int32_t row) {
+    for (int i = 0; i < j; ++i)
+      if (L.jrow[i] == row) return true;
+    for (int r = 0; r < ns; ++r)
+      if (C[L.starts[r]] == row) return true;
+    return false;
+  };
+  Best nb = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};  // maximise -d2, ties to the lower row
+  int rdone = -1;
+  int found = 0x7fffffff;
+  for (int r = 0;; r = r < 4 ? r + 1 : r + r / 3) {
+    int b0[GRID_Q], bn[GRID_Q];
+    bool all = true;
+    for (int k = 0; k < GRID_Q; ++k) {
+      const int lo = cz[k] - r > 0 ? cz[k] - r : 0;
+      const int hi = cz[k] + r < g.G[k] - 1 ? cz[k] + r : g.G[k] - 1;
+      b0[k] = lo;
+      bn[k] = hi - lo + 1;
+      all = all && lo == 0 && hi == g.G[k] - 1;
+    }
+    const int64_t total = (int64_t)bn[0] * bn[1] * bn[2];
+    for (int64_t t = tid; t < total; t += nt) {
+      int c[GRID_Q];
+      c[0] = b0[0] + (int)(t % bn[0]);
+      c[1] = b0[1] + (int)((t / bn[0]) % bn[1]);
+      c[2] = b0[2] + (int)(t / ((int64_t)bn[0] * bn[1]));
+      int cheb = 0;
+      for (int k = 0; k < GRID_Q; ++k) {
+        const int dk = c[k] > cz[k] ? c[k] - cz[k] : cz[k] - c[k];
+        cheb = dk > cheb ? dk : cheb;
+      }
+      if (cheb <= rdone) continue;  // examined in an earlier box
+      const int64_t cell = grid_cell(g, c);
+      const int e1 = g.start[cell + 1];
+      for (int e = g.start[cell]; e < e1; ++e) {
+        const double* xe = g.Xs + (int64_t)e * p;
+        double acc = 0.0;
+        for (int k = 0; k < p; ++k) {
+          const double dz = xe[k] - z[k];
+          acc = __builtin_fma(dz, dz, acc);
+        }
+        const int32_t row = g.rows[e];
+        if ((-acc > nb.v1 || (-acc == nb.v1 && row < nb.i1)) && !excluded(row)) best_push(nb, -acc, row);
+      }
+    }
+    block_best(L, nb);
+    const double bd = -L.scal[1];
+    found = L.ints[0];
+    const double lb = (double)(r - 1) * g.wmin;
+    if (all || (r >= 1 && bd < lb * lb * (1.0 - 0x1p-40))) break;
+    rdone = r;
+  }
+  if (found == 0x7fffffff) return -1;
+  // its rank among the candidates, if it is one
+  if (tid == 0) L.ints[9] = -1;
+  __syncthreads();
+  for (int c = tid; c < a.ncand; c += nt)
+    if (C[c] == found) L.ints[9] = c;
+  __syncthreads();
+  const int rk = L.ints[9];
+  if (rk >= 0) return rk;
+  if (tid == 0) L.ints[8] = found;
+  __syncthreads();
+  return a.ncand;
+}
+
 // The end of a ray step, once every ray's value and s* are in L.rval, L.rs:
 // the best ray (lowest on ties), its start when s* = 0, else its optimum
 // snapped to the nearest candidate outside the design and the starts.
 // Returns the chosen rank; *b1, *b2 the best and runner-up ray values.
 template <int P>
-__device__ __forceinline__ int ray_finish(const LocalArgs& a, const Lds& L, const double* Xc, int ns, double* b1,
-                                          double* b2) {
+__device__ __forceinline__ int ray_finish(const LocalArgs& a, const Lds& L, const int32_t* C, const double* Xc, int j,
+                                          int ns, double* b1, double* b2) {
   constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
   constexpr int G = PM <= 8 ? 4 : 1;  // candidates whose coordinates are loaded together
   const int tid = threadIdx.x, p = a.p;
@@ -1135,11 +1231,17 @@ __device__ __forceinline__ int ray_finish(const LocalArgs& a, const Lds& L, cons
   *b1 = L.scal[1];
   *b2 = L.scal[2];
   if (sw == 0.0) return L.starts[br];
+  const double* ar = L.ra + br * p;
+  const double* dr = L.rdir + br * p;
+  if (a.snap_full) {
+    double zf[LAGP_MAX_DIM];
+#pragma unroll
+    for (int k = 0; k < LAGP_MAX_DIM; ++k) zf[k] = k < p ? __builtin_fma(sw, dr[k], ar[k]) : 0.0;
+    return snap_design(a, L, C, zf, j, ns);
+  }
   // snap z* = a + s* dir to the nearest candidate outside J and the starts
   // (the starts are flagged unavailable for the scan, 2 = start, and
   // released after it)
-  const double* ar = L.ra + br * p;
-  const double* dr = L.rdir + br * p;
   for (int r = tid; r < ns; r += blockDim.x) L.selm[L.starts[r]] = 2;
   __syncthreads();
   double zs[PM];
@@ -1241,7 +1343,7 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
     }
     wave_sync();
   }
-  return ray_finish<P>(a, L, Xc, ns, b1, b2);
+  return ray_finish<P>(a, L, C, Xc, j, ns, b1, b2);
 }
 
 // ------------------------------------------------ ray search on one tile --
@@ -1402,7 +1504,7 @@ __device__ __forceinline__ int ray_step_tile(const LocalArgs& a, const Lds& L, i
     L.rval[lane] = val;
     L.rs[lane] = sst;
   }
-  return ray_finish<P>(a, L, Xc, ns, b1, b2);
+  return ray_finish<P>(a, L, C, Xc, j, ns, b1, b2);
 }
 
 // ------------------------------------------------------------ kernel -----
@@ -1479,6 +1581,7 @@ void k_local(LocalArgs a) {
   double* Xc = a.Xc + (int64_t)m * ncs * p;
   for (int i = tid; i < n0; i += blockDim.x) {
     L.J[i] = i;
+    L.jrow[i] = C[i];
     L.selm[i] = 1;
   }
   for (int t = tid; t < n0 * p; t += blockDim.x) L.xj[t] = a.X[(int64_t)C[t / p] * p + (t % p)];
@@ -1517,8 +1620,11 @@ void k_local(LocalArgs a) {
         b1 = L.scal[1];
         b2 = L.scal[2];
       }
-      if (cs < 0 || cs >= nc) break;  // no finite score anywhere: give up on x
-      const double v = add_point<MODE == MODE_EXACT || MODE == MODE_MIXED>(a, L, LD, Kc, Kc32, kxc, Xc, j, cs);
+      // no finite score anywhere (or nothing left to snap to): give up on x
+      if (cs < 0 || cs > nc || (cs == nc && !a.snap_full)) break;
+      const int32_t row = cs < nc ? C[cs] : L.ints[8];
+      const double v =
+          add_point<MODE == MODE_EXACT || MODE == MODE_MIXED>(a, L, LD, Kc, Kc32, kxc, Xc, j, cs, row);
       done = j + 1;
       if (!(v > 0.0)) vflag = 1;
       if (tid == 0 && a.diag) {
@@ -1538,7 +1644,7 @@ void k_local(LocalArgs a) {
   // prediction with the n local points
   const bool ok = pd && done == n;
   if (ok) {
-    for (int i = tid; i < n; i += blockDim.x) L.yJ[i] = a.y[C[L.J[i]]];
+    for (int i = tid; i < n; i += blockDim.x) L.yJ[i] = a.y[L.jrow[i]];
     __syncthreads();
     for (int i = tid; i < n; i += blockDim.x) {
       double s = 0.0, t = 0.0;
@@ -1573,7 +1679,7 @@ void k_local(LocalArgs a) {
     a.status[m] = st;
   }
   if (a.sel)
-    for (int i = tid; i < n; i += blockDim.x) a.sel[(int64_t)m * n + i] = (i < done) ? C[L.J[i]] : -1;
+    for (int i = tid; i < n; i += blockDim.x) a.sel[(int64_t)m * n + i] = (i < done) ? L.jrow[i] : -1;
 }
 
 size_t local_lds_bytes(int n, int ncs, int p, int numrays, bool mixed) {

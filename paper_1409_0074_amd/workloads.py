@@ -32,6 +32,8 @@ PREC_MIXED = 1
 
 SCORING_PARTINV = 0
 SCORING_CHOL = 1
+SNAP_CANDIDATES = 0  # ray search: snap to the nearest of the N' candidates
+SNAP_DESIGN = 1      # ray search: snap to the nearest of the whole design (Sec. 5)
 
 
 @dataclasses.dataclass
@@ -45,7 +47,8 @@ class Params:
     PREC_FP64 or PREC_MIXED; rescore_k: FP64 re-scored shortlist in the mixed
     form; brent_maxit / brent_tol: the line-search budget and tolerance;
     scoring: SCORING_PARTINV (partitioned-inverse updates) or SCORING_CHOL
-    (incremental Cholesky columns) for exhaustive search.
+    (incremental Cholesky columns) for exhaustive search; snap: SNAP_CANDIDATES
+    or SNAP_DESIGN, where ray search snaps its optimum to.
     """
 
     n0: int = 6
@@ -60,6 +63,7 @@ class Params:
     brent_maxit: int = 100
     brent_tol: float = 2.0 ** -13
     scoring: int = SCORING_PARTINV
+    snap: int = SNAP_CANDIDATES
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

@@ -50,6 +50,7 @@ def _call(lg, d, fn, XX, prm):
     ("chol_stream", 700, 60),  # n = 100: columns streamed from slots in the scratch, ~550 per chunk
     ("partinv", 260, 37),    # partitioned inverse: about 115 per chunk (kernel rows in the workspace)
     ("ray", 150, 20),
+    ("ray_design", 150, 20),  # snap over the whole design: the design's grid is built beforehand
     ("mixed", 120, 9),
 ])
 def test_noalloc_equals_predict_twice(env, case, M1, M2):
@@ -61,6 +62,9 @@ def test_noalloc_equals_predict_twice(env, case, M1, M2):
         prm = prm.replace(scoring=W.SCORING_CHOL, n=100)
     elif case == "ray":
         prm = prm.replace(search=W.SEARCH_RAY, numrays=8)
+    elif case == "ray_design":
+        prm = prm.replace(search=W.SEARCH_RAY, numrays=8, ncand=100, snap=W.SNAP_DESIGN)
+        lg.lagp_design_build_grid(d.handle)
     elif case == "mixed":
         prm = prm.replace(precision=W.PREC_MIXED)
     for M in (M1, M2):
