@@ -306,18 +306,25 @@ def sec51(steps: int):
     w = W.paper2d()
     d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
     XX = torch.from_numpy(w.XX).cuda()
-    rows = [("ray_n50_stage2", W.SEARCH_RAY, 2, 1000, W.SCORING_PARTINV),
+    # ray searches snap over the whole design (Sec. 5: no N' limit on them),
+    # so their candidate lists only hold the starts' ranks; one row keeps the
+    # N' = 1000 scope for comparison
+    nray = W.ray_candidates_needed(50, w.params.n0, 1)
+    rows = [("ray_n50_stage2", W.SEARCH_RAY, 2, nray, W.SCORING_PARTINV),
             ("ext_n50_stage2", W.SEARCH_EXHAUSTIVE, 2, 1000, W.SCORING_CHOL),
-            ("ray_n50_stage1", W.SEARCH_RAY, 1, 1000, W.SCORING_PARTINV),
+            ("ray_n50_stage1", W.SEARCH_RAY, 1, nray, W.SCORING_PARTINV),
             ("ext_n50_stage1", W.SEARCH_EXHAUSTIVE, 1, 1000, W.SCORING_CHOL),
             ("nn_n50", W.SEARCH_NN, 1, 1000, W.SCORING_PARTINV),
-            ("ext_n50_cand2000_stage1", W.SEARCH_EXHAUSTIVE, 1, 2000, W.SCORING_CHOL)]
+            ("ext_n50_cand2000_stage1", W.SEARCH_EXHAUSTIVE, 1, 2000, W.SCORING_CHOL),
+            ("ray_n50_stage1_snap_cand1000", W.SEARCH_RAY, 1, 1000, W.SCORING_PARTINV)]
     out = {"workload": w.name.replace("_exhaustive", ""), "M": int(w.XX.shape[0]), "d0": w.params.d[0],
            "g": w.params.g, "numrays": 1, "paper_secs_context": SEC51_PAPER_SECS,
            "paper_right_table_secs_context": SEC51_PAPER_RIGHT, "rows": {}}
     for name, search, mode, nc, scoring in rows:
+        full = search == W.SEARCH_RAY and "snap_cand" not in name
         prm = w.params.replace(search=search, numrays=1 if search == W.SEARCH_RAY else 0, ncand=nc,
-                               scoring=scoring if search == W.SEARCH_EXHAUSTIVE else W.SCORING_PARTINV)
+                               scoring=scoring if search == W.SEARCH_EXHAUSTIVE else W.SCORING_PARTINV,
+                               snap=W.SNAP_DESIGN if full else W.SNAP_CANDIDATES)
         d.predict_mle(XX[:256], prm, mode)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -334,7 +341,8 @@ def sec51(steps: int):
             "coverage95": float(np.mean(np.abs(w.truth - mu) <= half)),
             "dhat_median": float(np.median(o["dhat"].cpu().numpy())),
             "likelihood_evaluations_mean": float(o["iters"].float().mean().cpu()),
-            "status_nonzero": int((o["status"] != 0).sum().cpu())}
+            "status_nonzero": int((o["status"] != 0).sum().cpu()), "ncand": nc,
+            "snap": "whole design" if full else ("candidates" if search == W.SEARCH_RAY else None)}
     d.close()
     return out
 
@@ -655,6 +663,39 @@ def main() -> int:
                          "work": f"sum over steps of E_j (2 j^2 + j (3 p + 20) + 4 j) + 3 p N' with E_j the "
                                  f"kernel's own Brent evaluations: {rflops / M:.4g} FLOP/location x {M} "
                                  f"locations per launch"}}
+
+    if not args.no_ray:
+        # the same rays snapping over the whole design (Sec. 5): the candidate
+        # lists hold only the starts' ranks; the snap searches the design's grid
+        ncr = W.ray_candidates_needed(prm.n, prm.n0, R)
+        Pf = lg.make_params(prm, search=W.SEARCH_RAY, numrays=R, ncand=ncr, snap=W.SNAP_DESIGN)
+        candr = torch.empty((M, ncr), dtype=torch.int32, device=dev)
+        selr = torch.empty((M, prm.n), dtype=torch.int32, device=dev)
+        lg.lagp_design_build_grid(design)
+
+        def fstep(ev):
+            ev[0].record()
+            lg.lagp_candidates(design, XX, ncr, candr)
+            ev[1].record()
+            lg.lagp_predict_counts(design, XX, candr, Pf, mean, s2, df, selr, None, status, counts)
+            ev[2].record()
+
+        fstep(dummy)
+        torch.cuda.synchronize()
+        (fk, fl), fwall = time_steps(fstep, args.ray_steps, 2)
+        fms = fwall / args.ray_steps
+        fct = counts.cpu().numpy()[:, :, 0]
+        # chosen rows outside each location's 1000 nearest (their ranks in the
+        # N' = 1000 lists of the exhaustive run)
+        sr, cd = selr.cpu().numpy(), cand.cpu().numpy()
+        outside = int(sum(np.sum(~np.isin(sr[m], cd[m])) for m in range(0, M, 10)))
+        result["ray"]["snap_design"] = {
+            "value": round(M / (fms / 1e3), 2), "unit": "predictions/s", "ms_per_step": round(fms, 3),
+            "ncand": ncr, "phases_ms": {"knn": round(float(fk), 3), "local_design": round(float(fl), 3)},
+            "rmse_vs_truth": rmse(mean.cpu().numpy()),
+            "brent_evaluations_per_step_mean": round(float(fct.mean()), 2),
+            "rows_outside_1000_nearest": {"count": outside, "of": int(sr[::10].size), "sample": "every 10th location"},
+            "status_nonzero": int((status != 0).sum().cpu())}
 
     lg.lagp_design_destroy(design)
     del X, y, XX, cand

@@ -248,6 +248,17 @@ def serving_requests(count: int, qps: float, precision_mix: float = 0.0, p: int 
     return out
 
 
+def ray_candidates_needed(n: int, n0: int, numrays: int) -> int:
+    """Candidates a ray search's starts reach (Sec. 4): at step j the starts
+    are the remaining ranks k .. k + R - 1 with j taken, k = t mod
+    floor(sqrt t), t = j - n0 + 1; so n - 1 + R + the largest such k."""
+    off = 0
+    for t in range(1, n - n0 + 1):
+        r = math.isqrt(t)
+        off = max(off, t % r if r else 0)
+    return n - 1 + numrays + off
+
+
 def small_case(seed: int, N: int, p: int, M: int, **kw) -> Workload:
     """Small uniform workloads for parity sweeps: design and locations iid
     uniform on [0,1]^p, the 2-d bump response (p = 2) or the 8-d sines
