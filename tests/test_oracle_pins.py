@@ -431,11 +431,14 @@ def _ray_starts(cand, inJ_rows, k0, R):
     return rem[k0:k0 + R]
 
 
-def test_ray_step_snap_bruteforce(orc):
+@pytest.mark.parametrize("snap", [W.SNAP_CANDIDATES, W.SNAP_DESIGN])
+def test_ray_step_snap_bruteforce(orc, snap):
     """Recompute each ray step's start ranks, segments and snap in numpy from
-    the oracle's own reported s* and check the chosen candidate (Sec. 4)."""
+    the oracle's own reported s* and check the chosen candidate (Sec. 4);
+    with the whole-design scope (Sec. 5) the snap must reach the nearest of
+    all design rows outside the design and the starts."""
     w = W.tiny_2d(M=8)
-    prm = w.params.replace(search=W.SEARCH_RAY, numrays=3, n=30)
+    prm = w.params.replace(search=W.SEARCH_RAY, numrays=3, n=30, snap=snap)
     lo, hi = w.X.min(0), w.X.max(0)
     for m in range(8):
         x = w.XX[m]
@@ -470,6 +473,8 @@ def test_ray_step_snap_bruteforce(orc):
                 if nearest == chosen:
                     best = q
             assert best is not None, (m, step)
+        if snap == W.SNAP_DESIGN:
+            assert len(cand) == w.X.shape[0]
 
 
 def test_ray_mode_predicts_well(orc):
