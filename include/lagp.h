@@ -52,7 +52,7 @@ extern "C" {
 #define LAGP_WARN_NUMERIC 1
 
 #define LAGP_MAX_DIM 16    /* largest input dimension p */
-#define LAGP_MAX_N 128     /* largest local design size n */
+#define LAGP_MAX_N 256     /* largest local design size n */
 #define LAGP_MAX_NCAND 4096 /* largest candidate count N' */
 #define LAGP_MAX_RAYS 32   /* largest number of rays per greedy step */
 

@@ -70,6 +70,8 @@ int32_t check_params(const lagp_design* d, const lagp_params* P, int* rays) {
       (P->search != LAGP_SEARCH_EXHAUSTIVE || P->precision != LAGP_PREC_FP64))
     return fail(LAGP_EINVAL, "Cholesky scoring applies to exhaustive search in FP64 only");
   if (P->n < 1 || P->n > LAGP_MAX_N) return fail(LAGP_EINVAL, "n must be in [1, LAGP_MAX_N]");
+  if (P->n > 128 && P->search == LAGP_SEARCH_EXHAUSTIVE && P->scoring != LAGP_SCORING_CHOL)
+    return fail(LAGP_EINVAL, "designs past 128 points: exhaustive search by Cholesky columns, rays or neighbours");
   if (P->search != LAGP_SEARCH_NN && (P->n0 < 1 || P->n0 > P->n)) return fail(LAGP_EINVAL, "n0 must be in [1, n]");
   if (P->ncand < P->n) return fail(LAGP_EINVAL, "ncand must be >= n");
   if ((int64_t)P->ncand > d->N) return fail(LAGP_EINVAL, "ncand must be <= N");
@@ -349,6 +351,14 @@ size_t chol_stream_fixed(const lagp_design* d, const lagp_params* P, size_t budg
   return (sb * (size_t)k + 255) & ~size_t(255);
 }
 
+// K_J^{-1} of a design past 128 points (ray and neighbour searches), which
+// does not fit LDS: ceil8(n) rows of 257 doubles per location (the local
+// kernel's plan for n > 128).
+size_t kig_bytes(const lagp_params* P) {
+  if (P->n <= 128 || P->scoring == LAGP_SCORING_CHOL) return 0;
+  return sizeof(double) * (size_t)((P->n + 7) & ~7) * 257;
+}
+
 // Bytes run_predict allocates for M locations under a workspace cap, and the
 // per-location figure (kNN buffers when candidates are not given, the kernel
 // rows, k(x_c, x), the candidates' coordinates, the starting-inverse scratch
@@ -364,7 +374,8 @@ size_t predict_per_location_bytes(const lagp_design* d, const lagp_params* P, bo
   const size_t b_cand = have_cand ? 0 : sizeof(int32_t) * (size_t)nc;
   const size_t b_kc32 = P->precision == LAGP_PREC_MIXED ? sizeof(float) * (size_t)kc_rows * ncs : 0;
   return b_knn + b_cand + sizeof(double) * (size_t)kc_rows * ncs + b_kc32 + sizeof(double) * (size_t)ncs +
-         sizeof(double) * (size_t)ncs * d->p + sizeof(double) * 2 * (size_t)n0 * n0 + sizeof(int32_t);
+         sizeof(double) * (size_t)ncs * d->p + sizeof(double) * 2 * (size_t)n0 * n0 + kig_bytes(P) +
+         sizeof(int32_t);
 }
 
 int64_t predict_chunk(const lagp_design* d, const lagp_params* P, bool have_cand, int64_t M, size_t ws_budget) {
@@ -381,7 +392,7 @@ size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool 
   const size_t fixed = chol_stream_fixed(d, P, ws_budget, &slots);
   return predict_per_location_bytes(d, P, have_cand) *
              (size_t)predict_chunk(d, P, have_cand, M, ws_budget > fixed ? ws_budget - fixed : 0) +
-         shared + fixed + 10 * 256;  // 10 aligned sections
+         shared + fixed + 11 * 256;  // 11 aligned sections
 }
 
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
@@ -419,13 +430,14 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const size_t b_kxc = chol ? 0 : sizeof(double) * (size_t)ncs;
   const size_t b_xc = chol ? 0 : sizeof(double) * (size_t)ncs * p;
   const size_t b_chol = chol ? 0 : sizeof(double) * 2 * (size_t)n0 * n0;
+  const size_t b_kig = kig_bytes(P);
   const size_t shared = cand_in ? 0 : knn2_shared_bytes(d->N, p, nc);
   int cw_slots = 0;
   const size_t b_cw = chol_stream_fixed(d, P, ext_ws ? ext_bytes : ws_budget, &cw_slots);
   int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget > b_cw ? ws_budget - b_cw : 0);
-  if (ext_ws) {  // as many locations as the given workspace holds (10 sections, each aligned)
-    const size_t per = b_knn + b_cand + b_kc + b_kc32 + b_kxc + b_xc + b_chol + sizeof(int32_t);
-    const size_t fixed = shared + b_cw + 10 * 256;
+  if (ext_ws) {  // as many locations as the given workspace holds (11 sections, each aligned)
+    const size_t per = b_knn + b_cand + b_kc + b_kc32 + b_kxc + b_xc + b_chol + b_kig + sizeof(int32_t);
+    const size_t fixed = shared + b_cw + 11 * 256;
     if (ext_bytes < fixed + per)
       return fail(LAGP_ENOMEM, "the workspace of one location (" + std::to_string(fixed + per) +
                                    " bytes) exceeds the " + std::to_string(ext_bytes) + "-byte scratch");
@@ -436,7 +448,8 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_kc = o_cand + al(b_cand * chunk),
                o_kc32 = o_kc + al(b_kc * chunk), o_kxc = o_kc32 + al(b_kc32 * chunk),
                o_xc = o_kxc + al(b_kxc * chunk), o_chol = o_xc + al(b_xc * chunk),
-               o_st = o_chol + al(b_chol * chunk), o_sub = o_st + al(sizeof(int32_t) * chunk),
+               o_kig = o_chol + al(b_chol * chunk), o_st = o_kig + al(b_kig * chunk),
+               o_sub = o_st + al(sizeof(int32_t) * chunk),
                o_cw = o_sub + al(shared), total = o_cw + b_cw;
   char* base = nullptr;
   if (ext_ws) {
@@ -459,6 +472,7 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.kxc = reinterpret_cast<double*>(base + o_kxc);
     a.Xc = reinterpret_cast<double*>(base + o_xc);
     a.chol = reinterpret_cast<double*>(base + o_chol);
+    a.kig = b_kig ? reinterpret_cast<double*>(base + o_kig) : nullptr;
     a.cw = reinterpret_cast<double*>(base + o_cw);
     a.mean = mean + m0;
     a.s2 = s2 + m0;
@@ -579,7 +593,7 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
   const int maxit = mle->maxit > 0 ? mle->maxit : 100;
   if (!(dmin < dmax) || !std::isfinite(dmax)) return fail(LAGP_EINVAL, "need 0 < dmin < dmax (finite)");
   const int lds_max = max_lds_per_block();
-  if (!lagp::mle_supported(n, p, (size_t)lds_max)) return fail(LAGP_EINVAL, "local MLE needs n <= 50");
+  if (!lagp::mle_supported(n, p, (size_t)lds_max)) return fail(LAGP_EINVAL, "local MLE needs n <= LAGP_MAX_N");
   if (!chol && lagp::local_lds_bytes(n, (nc + 15) & ~15, p, rays, false) > (size_t)lds_max)
     return fail(LAGP_EINVAL, "local design too large for LDS (n, p, numrays)");
   if (M == 0) return LAGP_OK;
@@ -596,7 +610,9 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
   // k_local's per-location buffers (kernel rows, k(x_c, x), coordinates,
   // starting-inverse scratch, status) for the ray and nearest-neighbour searches
   const size_t b_loc = chol ? 0 : lagp::predict_per_location_bytes(d, P, true);
-  const size_t per = b_knn + b_cand + b_sel + b_st + b_th + b_loc;
+  // the likelihood's matrices of designs past the LDS sizes
+  const size_t b_mle = lagp::mle_workspace_bytes_per_location(n, p, (size_t)lds_max);
+  const size_t per = b_knn + b_cand + b_sel + b_st + b_th + b_loc + b_mle;
   int cw_slots = 0;  // Cholesky scoring past the on-chip sizes: the streaming kernel's slots
   const size_t b_cw = lagp::chol_stream_fixed(d, P, workspace_budget(), &cw_slots);
   const size_t budget = workspace_budget() > b_cw ? workspace_budget() - b_cw : 0;
@@ -605,7 +621,7 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
   ws.s = s;
   const size_t o_knn = 0, o_cand = o_knn + al(b_knn * chunk), o_sel = o_cand + al(b_cand * chunk),
                o_st = o_sel + al(b_sel * chunk), o_th = o_st + al(b_st * chunk), o_loc = o_th + al(b_th * chunk),
-               o_sub = o_loc + al(b_loc * chunk) + 4 * 256,
+               o_mle = o_loc + al(b_loc * chunk) + 5 * 256, o_sub = o_mle + al(b_mle * chunk),
                o_cw = o_sub + al(cand_in ? 0 : lagp::knn2_shared_bytes(d->N, p, nc)), total = o_cw + b_cw;
   LAGP_HIP(hipMallocAsync(&ws.ptr, total, s));
   char* base = reinterpret_cast<char*>(ws.ptr);
@@ -623,13 +639,15 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
     int32_t* it_out = iters ? iters + m0 : stw + 5 * chunk;
     double* th1 = reinterpret_cast<double*>(base + o_th);
     lagp::LocalArgs a = lagp::local_args(d, P, rays, XX + m0 * p, mc, cand);
-    if (!chol) {  // [Kc: kc_rows x ncs][kxc: ncs][Xc: ncs x p][start scratch: 2 n0^2], per location
+    if (!chol) {  // [Kc: kc_rows x ncs][kxc: ncs][Xc: ncs x p][start scratch: 2 n0^2][K^{-1} past 128 points]
       const size_t ncs = (size_t)a.ncs, o_kxc = al(sizeof(double) * a.kc_rows * ncs * chunk),
-                   o_xc = o_kxc + al(sizeof(double) * ncs * chunk), o_ch = o_xc + al(sizeof(double) * ncs * p * chunk);
+                   o_xc = o_kxc + al(sizeof(double) * ncs * chunk), o_ch = o_xc + al(sizeof(double) * ncs * p * chunk),
+                   o_ki = o_ch + al(sizeof(double) * 2 * (size_t)a.n0 * a.n0 * chunk);
       a.Kc = reinterpret_cast<double*>(base + o_loc);
       a.kxc = reinterpret_cast<double*>(base + o_loc + o_kxc);
       a.Xc = reinterpret_cast<double*>(base + o_loc + o_xc);
       a.chol = reinterpret_cast<double*>(base + o_loc + o_ch);
+      a.kig = lagp::kig_bytes(P) ? reinterpret_cast<double*>(base + o_loc + o_ki) : nullptr;
     }
     a.mean = mean + m0;  // (overwritten by the prediction under the estimate)
     a.s2 = s2 + m0;
@@ -655,6 +673,7 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
     e.n = n;
     e.p = p;
     e.M = mc;
+    e.ws = b_mle ? reinterpret_cast<double*>(base + o_mle) : nullptr;
     e.status_in = st1;
     if (mle->mode == 1) {
       e.theta_out = dhat + m0;
@@ -663,14 +682,14 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
       e.mean = mean + m0;
       e.s2 = s2 + m0;
       e.df = df + m0;
-      LAGP_HIP(lagp::launch_mle(e, s));
+      LAGP_HIP(lagp::launch_mle(e, s, (size_t)lds_max));
       continue;
     }
     e.theta_out = th1;
     e.status_out = fl1;
     e.iters_out = it1;
     e.nan_on_skip = 1;
-    LAGP_HIP(lagp::launch_mle(e, s));
+    LAGP_HIP(lagp::launch_mle(e, s, (size_t)lds_max));
     a.dloc = th1;  // second stage: search under the estimate
     a.status = st2;
     LAGP_HIP(search());
@@ -685,7 +704,7 @@ int32_t lagp_predict_mle(const lagp_design* d, const double* XX, int64_t M, cons
     e.s2 = s2 + m0;
     e.df = df + m0;
     e.nan_on_skip = 0;
-    LAGP_HIP(lagp::launch_mle(e, s));
+    LAGP_HIP(lagp::launch_mle(e, s, (size_t)lds_max));
   }
   return LAGP_OK;
 }

@@ -72,6 +72,7 @@ struct LocalArgs {
                            // 16-candidate tiles re-scored in FP64; else: candidates scored, 0
   int32_t snap_full;       // ray search: snap over the whole design through `grid` (else the candidates)
   GridDev grid;
+  double* kig;             // designs past 128 points (ray, nearest neighbours): M x NR x 257 K_J^{-1}
 };
 
 // Arguments of the local MLE kernel (mle.hip) for one chunk of locations.
@@ -94,6 +95,7 @@ struct MleArgs {
   double dmin, dmax, tol, g;
   int32_t maxit, n, p, M;
   int32_t nan_on_skip;         // a skipped location's theta_out: NaN (1) or its starting value (0)
+  double* ws;                  // designs past the LDS sizes: M x mle_workspace_bytes_per_location
 };
 
 // Arguments of the threshold-first kNN (knn.hip).
@@ -150,10 +152,13 @@ int chol_stream_max_slots(int ncand);
 bool chol_stream_forced();  // test hook: LAGP_CHOL_FORCE_STREAM=1
 hipError_t launch_chol_stream(const LocalArgs& a, int slots, hipStream_t s);
 
-// Local MLE of the lengthscale and the prediction under it (mle.hip).
+// Local MLE of the lengthscale and the prediction under it (mle.hip):
+// n <= 50 in LDS, larger designs (n <= LAGP_MAX_N) in a per-location
+// workspace slice.
 size_t mle_lds_bytes(int n, int p);
 bool mle_supported(int n, int p, size_t lds_max);
-hipError_t launch_mle(const MleArgs& a, hipStream_t s);
+size_t mle_workspace_bytes_per_location(int n, int p, size_t lds_max);
+hipError_t launch_mle(const MleArgs& a, hipStream_t s, size_t lds_max);
 
 // Global separable fit on a subset (sepfit.hip): one workgroup, n <= SEP_NMAX.
 constexpr int SEP_NMAX = 1024;

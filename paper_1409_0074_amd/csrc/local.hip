@@ -93,10 +93,15 @@ struct LdsPlan {
 // per-wave vectors); mixed: screened scores and shortlist.
 __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool mixed, bool tile = false) {
   LdsPlan P;
-  P.NP = n <= 64 ? 64 : 128;
+  // NP = 256 (n > 128): K_J^{-1} does not fit LDS and lives in a per-location
+  // workspace (LocalArgs::kig)
+  P.NP = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
   // exact scoring and rays read rows below 4 ceil(j/4); the FP32 screen
   // reads whole 16-row blocks
   P.NR = mixed ? (n + 15) & ~15 : (n + 3) & ~3;
+  // the ray sums read K^{-1} in 8-row blocks: whole blocks of (zeroed)
+  // workspace rows past 128 points, where nothing else follows in memory
+  if (P.NP == 256) P.NR = (n + 7) & ~7;
   P.KZS = P.NP + 2;
   // odd: the 16 rows of an MFMA operand fall in distinct banks (the tile ray
   // form, short of LDS, strides by the rows it uses)
@@ -106,7 +111,7 @@ __host__ __device__ inline LdsPlan plan_lds(int n, int ncs, int p, int R, bool m
   size_t o = 0;
   int k = 0;
   auto take = [&](size_t b) { P.off[k++] = o; o = align16(o + b); };
-  take(sizeof(double) * P.NR * P.LD);       // Ki
+  take(P.NP == 256 ? 0 : sizeof(double) * P.NR * P.LD);  // Ki
   for (int i = 0; i < 6; ++i) take(sizeof(double) * P.NP);  // kx h col wv gv yJ
   take(sizeof(double) * LAGP_MAX_DIM);     // x
   take(sizeof(double) * n * p);            // xj
@@ -880,9 +885,10 @@ __device__ __forceinline__ void ray_point(const Lds& L, int p, int r, double s, 
 // B[b][k][i] both in lane 16k + c.  Sums run in index order; the LDS vectors
 // are zero past j (as is K^{-1}), so padded terms add fma(0, 0, t) = t only.
 // xi: the lane's design point J_lane (registers).
-template <int P>
+template <int P, int NH>
 __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L, int LD, int j, const double* xi,
                                                 int rid, double s, bool ev, bool at_start, int* vflag) {
+  static_assert(NH == 2 || NH == 4, "design rows in two or four 64-row halves");
   constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = a.p;
@@ -902,7 +908,9 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
     ray_point<P>(L, p, rids[t], ss[t], at_start, z);
     double* kz = L.kzb + (wave * RB + t) * L.kzs;
     if (lane < j) kz[lane] = corr_regs<P>(xi, z, p, L.w0, a.w, a.dlen);
-    if (lane + 64 < j) kz[lane + 64] = corr_regs<P>(L.xj + (lane + 64) * p, z, p, L.w0, a.w, a.dlen);
+#pragma unroll
+    for (int h = 1; h < NH; ++h)
+      if (lane + 64 * h < j) kz[lane + 64 * h] = corr_regs<P>(L.xj + (lane + 64 * h) * p, z, p, L.w0, a.w, a.dlen);
   }
   // K(z_t, x) on lane t
   double kzx = 0.0;
@@ -917,7 +925,7 @@ __device__ __forceinline__ double ray_alc_lanes(const LocalArgs& a, const Lds& L
   const double* kzw = L.kzb + wave * RB * KZS;
   double* wzw = L.wvb + wave * RB * KZS;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < NH; ++h) {
     const int i = lane + 64 * h;
     if (i < j) {
       double acc[RB];
@@ -1112,15 +1120,53 @@ __device__ __forceinline__ double ray_segment(const LocalArgs& a, const Lds& L, 
 }
 
 // Snap over the whole design (ray search not restricted to the N' nearest,
-// Sec. 5): the nearest design row to z, by (squared distance in dimension
-// order with one fma per term, row), outside the design and the step's
-// starts.  The design's cell grid is searched in boxes of cells around z's
-// cell, growing until every cell outside the box is provably farther than
-// the best row found (a row in a cell r + 1 or more cells away along a grid
-// coordinate lies at least (r - 1) narrowest cell widths away: one width of
-// slack per side for the rounding of the cell assignment).  Returns the
-// row's candidate rank when it is a candidate, else ncand with the row in
-// L.ints[8]; -1 if no row is left.
+// Sec. 5): the nearest design row to z outside the design and the step's
+// starts, in the order a candidate list of the whole design would give:
+// (squared distance to z, squared distance to x, row), each squared
+// distance in dimension order with one fma per term (equal distances to z
+// go to the row of lower rank, the nearer to x).  The design's cell grid is
+// searched in boxes of cells around z's cell, growing until every cell
+// outside the box is provably farther than the best row found (a row in a
+// cell r + 1 or more cells away along a grid coordinate lies at least
+// (r - 1) narrowest cell widths away: one width of slack per side for the
+// rounding of the cell assignment).  Returns the row's candidate rank when
+// it is a candidate, else ncand with the row in L.ints[8]; -1 if no row is
+// left.
+struct Near {
+  double dz, dx;  // squared distances to z and to x
+  int row;
+};
+
+__device__ __forceinline__ bool near_before(const Near& a, const Near& b) {
+  return a.dz < b.dz || (a.dz == b.dz && (a.dx < b.dx || (a.dx == b.dx && a.row < b.row)));
+}
+
+// Block-wide first of the per-thread Nears (result in every thread).
+__device__ __forceinline__ Near block_near(const Lds& L, Near b) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int m = 32; m >= 1; m >>= 1) {
+    Near o;
+    o.dz = shfl_xor_d(b.dz, m);
+    o.dx = shfl_xor_d(b.dx, m);
+    o.row = shfl_xor_i(b.row, m);
+    if (near_before(o, b)) b = o;
+  }
+  if (lane == 0) {
+    L.redv[2 * wave] = b.dz;
+    L.redv[2 * wave + 1] = b.dx;
+    L.redi[wave] = b.row;
+  }
+  __syncthreads();
+  Near r = {L.redv[0], L.redv[1], L.redi[0]};
+  const int nw = blockDim.x >> 6;
+  for (int w = 1; w < nw; ++w) {
+    const Near o = {L.redv[2 * w], L.redv[2 * w + 1], L.redi[w]};
+    if (near_before(o, r)) r = o;
+  }
+  __syncthreads();  // (the words are rewritten by the next reduction)
+  return r;
+}
+
 __device__ int snap_design(const LocalArgs& a, const Lds& L, const int32_t* C, const double (&z)[LAGP_MAX_DIM], int j,
                            int ns) {
   const GridDev& g = a.grid;
@@ -1135,9 +1181,9 @@ __device__ int snap_design(const LocalArgs& a, const Lds& L, const int32_t* C, c
       if (C[L.starts[r]] == row) return true;
     return false;
   };
-  Best nb = {-__builtin_huge_val(), -__builtin_huge_val(), 0x7fffffff};  // maximise -d2, ties to the lower row
+  Near nb = {__builtin_huge_val(), __builtin_huge_val(), 0x7fffffff};
+  Near best = nb;
   int rdone = -1;
-  int found = 0x7fffffff;
   for (int r = 0;; r = r < 4 ? r + 1 : r + r / 3) {
     int b0[GRID_Q], bn[GRID_Q];
     bool all = true;
@@ -1169,17 +1215,22 @@ __device__ int snap_design(const LocalArgs& a, const Lds& L, const int32_t* C, c
           const double dz = xe[k] - z[k];
           acc = __builtin_fma(dz, dz, acc);
         }
-        const int32_t row = g.rows[e];
-        if ((-acc > nb.v1 || (-acc == nb.v1 && row < nb.i1)) && !excluded(row)) best_push(nb, -acc, row);
+        if (!(acc <= nb.dz)) continue;  // farther than this thread's best (or NaN)
+        double dxx = 0.0;  // the row's squared distance to x, as the candidate lists order it
+        for (int k = 0; k < p; ++k) {
+          const double dk = xe[k] - L.x[k];
+          dxx = __builtin_fma(dk, dk, dxx);
+        }
+        const Near o = {acc, dxx, g.rows[e]};
+        if (near_before(o, nb) && !excluded(o.row)) nb = o;
       }
     }
-    block_best(L, nb);
-    const double bd = -L.scal[1];
-    found = L.ints[0];
+    best = block_near(L, nb);
     const double lb = (double)(r - 1) * g.wmin;
-    if (all || (r >= 1 && bd < lb * lb * (1.0 - 0x1p-40))) break;
+    if (all || (r >= 1 && best.dz < lb * lb * (1.0 - 0x1p-40))) break;
     rdone = r;
   }
+  const int found = best.row;
   if (found == 0x7fffffff) return -1;
   // its rank among the candidates, if it is one
   if (tid == 0) L.ints[9] = -1;
@@ -1280,8 +1331,9 @@ __device__ __forceinline__ int ray_finish(const LocalArgs& a, const Lds& L, cons
 }
 
 // One ray-search step at design size j: returns the chosen candidate rank,
-// the best and runner-up ray values in *b1, *b2.
-template <int P>
+// the best and runner-up ray values in *b1, *b2.  NH: 64-row parts of the
+// design (2 up to n = 128, 4 up to 256).
+template <int P, int NH>
 __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD, const int32_t* C, const double* Xc, int j,
                                        int n0, double* b1, double* b2, int* vflag) {
   constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
@@ -1321,11 +1373,13 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
         my_tau = tau[t];
       }
     my_valid = my_valid && lane < RB;
-    const double a0 = ray_alc_lanes<P>(a, L, LD, j, xi, my_rid, 0.0, my_valid, true, vflag);
+    const double a0 = ray_alc_lanes<P, NH>(a, L, LD, j, xi, my_rid, 0.0, my_valid, true, vflag);
     my_live = my_valid && my_tau > 0.0;
     double fb = 0.0;
     int nev = 0;
-    const auto eval = [&](double s, bool e) { return ray_alc_lanes<P>(a, L, LD, j, xi, my_rid, s, e, false, vflag); };
+    const auto eval = [&](double s, bool e) {
+      return ray_alc_lanes<P, NH>(a, L, LD, j, xi, my_rid, s, e, false, vflag);
+    };
     const double xb = brent_lanes<false>(a, RB, my_live, eval, &fb, &nev);
     if (my_valid) {
       L.rev[my_rid] = nev;
@@ -1540,6 +1594,8 @@ void k_local(LocalArgs a) {
   const int LD = plan.LD;
   const int tid = threadIdx.x;
   const int m = blockIdx.x;
+  static_assert(NP != 256 || MODE == MODE_RAY || MODE == MODE_NN, "designs past 128 points: rays and neighbours");
+  if constexpr (NP == 256) L.Ki = a.kig + (int64_t)m * plan.NR * LD;  // (not in LDS)
   const int p = a.p, n = a.n, nc = a.ncand, ncs = a.ncs;
   const int n0 = (a.search == LAGP_SEARCH_NN) ? n : a.n0;
   // a per-location lengthscale (isotropic) replaces the common one; a
@@ -1603,7 +1659,7 @@ void k_local(LocalArgs a) {
       int cs;
       double b1, b2;
       if constexpr (MODE == MODE_RAY) {
-        cs = ray_step<P>(a, L, LD, C, Xc, j, n0, &b1, &b2, &vflag);
+        cs = ray_step<P, NP == 256 ? 4 : 2>(a, L, LD, C, Xc, j, n0, &b1, &b2, &vflag);
       } else if constexpr (MODE == MODE_RAY_TILE) {
         cs = ray_step_tile<NP, P>(a, L, LD, C, Xc, j, n0, &b1, &b2, &vflag);
       } else if constexpr (MODE == MODE_NN) {
@@ -1725,6 +1781,12 @@ hipError_t launch_local(const LocalArgs& a, hipStream_t s) {
       default: return launch_mode<64, MODE_RAY_TILE, 0>(a, lt, s, TILE_THREADS);
     }
   }
+  if (a.search == LAGP_SEARCH_RAY && a.n > 128) {  // K^{-1} in the workspace
+    switch (a.p) {
+      case 2: return launch_mode<256, MODE_RAY, 2>(a, lds, s);
+      default: return launch_mode<256, MODE_RAY, 0>(a, lds, s);
+    }
+  }
   if (a.search == LAGP_SEARCH_RAY) {
     switch (a.p) {
       case 1: return launch_mode<64, MODE_RAY, 1>(a, lds, s);
@@ -1735,7 +1797,7 @@ hipError_t launch_local(const LocalArgs& a, hipStream_t s) {
       default: return launch_mode<64, MODE_RAY, 0>(a, lds, s);
     }
   }
-  if (a.search == LAGP_SEARCH_NN) return launch_mode<64, MODE_NN>(a, lds, s);
+  if (a.search == LAGP_SEARCH_NN) return a.n > 128 ? launch_mode<256, MODE_NN>(a, lds, s) : launch_mode<64, MODE_NN>(a, lds, s);
   return a.n <= 64 ? launch_exhaustive<64>(a, lds, s) : launch_exhaustive<128>(a, lds, s);
 }
 

@@ -32,9 +32,9 @@ namespace lagp {
 namespace {
 
 constexpr int MLE_THREADS = 256;
-constexpr int MLE_NMAX = 50;
-static_assert(MLE_NMAX <= 64, "the factor's trailing updates take one lane per column");
+constexpr int MLE_NMAX_LDS = 50;  // designs whose matrices stay in LDS (two workgroups per CU)
 static_assert(MLE_THREADS == 256, "the per-row loops deal rows to exactly 4 waves");
+static_assert(LAGP_MAX_N <= MLE_THREADS, "a row per thread in the per-row loops");
 
 // Row handled by thread tid in the per-row loops: rows dealt to the
 // four waves in turn (i = 4 lane + wave), so all four SIMDs share them.
@@ -61,7 +61,8 @@ struct MleLds {
 __device__ __forceinline__ int sym(int i, int k) { return i >= k ? i * (i + 1) / 2 + k : k * (k + 1) / 2 + i; }
 
 // The two packed triangles and two full matrices stay under 80 KB at
-// n = 50, so two workgroups share a CU.
+// n = 50, so two workgroups share a CU; larger designs keep the same layout
+// in a per-location slice of a device workspace.
 __host__ __device__ inline size_t mle_lds_bytes_n(int n, int p) {
   const int LD = n + 1;
   return sizeof(double) * ((size_t)n * p + (size_t)n * (n + 1) + 2 * (size_t)n * LD + 9 * (size_t)n +
@@ -119,19 +120,23 @@ __device__ bool mle_cholesky(double* Lm, double* dg, double* Li, int n, int LD) 
     }
     if (tid == 0) dg[m] = piv;
     __syncthreads();
-    // trailing updates, rows dealt to the waves in turn (n <= 64: a lane per
-    // column): (i, k) with m < k <= i, and (i, c) with c <= m.  Column m of
-    // L and row m of L^{-1} are not written here, so each lane reads its
-    // L_km and (L^{-1})_mc once.
+    // trailing updates, rows dealt to the waves in turn, columns to the lanes
+    // in chunks of 64: (i, k) with m < k <= i, and (i, c) with c <= m.
+    // Column m of L and row m of L^{-1} are not written here, so each lane
+    // reads its L_km and (L^{-1})_mc once per chunk, and every element still
+    // receives one update per m.
     const int lane = tid & 63, wv = tid >> 6, nwv = T >> 6;
-    const int k = m + 1 + lane;
-    const double lkm = lane < nl ? Lm[k * LD + m] : 0.0;
-    const double lmc = lane < nr ? Li[m * LD + lane] : 0.0;
-    for (int r = wv; r < nl; r += nwv) {
-      const int i = m + 1 + r;
-      const double lim = Lm[i * LD + m];
-      if (lane <= r) Lm[i * LD + k] = __builtin_fma(-lim, lkm, Lm[i * LD + k]);
-      if (lane < nr) Li[i * LD + lane] = __builtin_fma(-lim, lmc, Li[i * LD + lane]);
+    const int ncol = nl > nr ? nl : nr;
+    for (int c0 = 0; c0 < ncol; c0 += 64) {
+      const int cl = c0 + lane, k = m + 1 + cl;
+      const double lkm = cl < nl ? Lm[k * LD + m] : 0.0;
+      const double lmc = cl < nr ? Li[m * LD + cl] : 0.0;
+      for (int r = wv; r < nl; r += nwv) {
+        const int i = m + 1 + r;
+        const double lim = Lm[i * LD + m];
+        if (cl <= r) Lm[i * LD + k] = __builtin_fma(-lim, lkm, Lm[i * LD + k]);
+        if (cl < nr) Li[i * LD + cl] = __builtin_fma(-lim, lmc, Li[i * LD + cl]);
+      }
     }
     __syncthreads();
   }
@@ -256,11 +261,16 @@ __device__ bool mle_eval(const MleLds& L, int n, double g, double theta) {
   return true;
 }
 
+// WS: the location's matrices in its slice of a.ws (designs past the LDS
+// sizes), else in LDS.
+template <bool WS>
 __global__ __launch_bounds__(MLE_THREADS) void k_mle(MleArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = a.n, p = a.p, LD = n + 1, tid = threadIdx.x, T = blockDim.x;
   const int64_t m = blockIdx.x;
-  const MleLds L = mle_carve(smem, n, p);
+  unsigned char* base = smem;
+  if constexpr (WS) base = reinterpret_cast<unsigned char*>(a.ws) + (size_t)m * ((mle_lds_bytes_n(n, p) + 255) & ~size_t(255));
+  const MleLds L = mle_carve(base, n, p);
   const int32_t* J = a.sel + m * n;
   const int st_in = a.status_in ? a.status_in[m] : 0;
   const int fl_prev = a.flags_prev ? a.flags_prev[m] : 0;
@@ -372,15 +382,25 @@ __global__ __launch_bounds__(MLE_THREADS) void k_mle(MleArgs a) {
 
 size_t mle_lds_bytes(int n, int p) { return mle_lds_bytes_n(n, p); }
 
-bool mle_supported(int n, int p, size_t lds_max) { return n <= MLE_NMAX && mle_lds_bytes_n(n, p) <= lds_max; }
+bool mle_supported(int n, int p, size_t lds_max) { return n <= LAGP_MAX_N && p <= LAGP_MAX_DIM && lds_max > 0; }
 
-hipError_t launch_mle(const MleArgs& a, hipStream_t s) {
+static bool mle_in_lds(int n, int p, size_t lds_max) { return n <= MLE_NMAX_LDS && mle_lds_bytes_n(n, p) <= lds_max; }
+
+size_t mle_workspace_bytes_per_location(int n, int p, size_t lds_max) {
+  return mle_in_lds(n, p, lds_max) ? 0 : ((mle_lds_bytes_n(n, p) + 255) & ~size_t(255));
+}
+
+hipError_t launch_mle(const MleArgs& a, hipStream_t s, size_t lds_max) {
   if (a.M <= 0) return hipSuccess;
+  if (!mle_in_lds(a.n, a.p, lds_max)) {
+    hipLaunchKernelGGL(k_mle<true>, dim3(a.M), dim3(MLE_THREADS), 0, s, a);
+    return hipGetLastError();
+  }
   const size_t lds = mle_lds_bytes_n(a.n, a.p);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mle),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mle<false>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mle, dim3(a.M), dim3(MLE_THREADS), lds, s, a);
+  hipLaunchKernelGGL(k_mle<false>, dim3(a.M), dim3(MLE_THREADS), lds, s, a);
   return hipGetLastError();
 }
 

@@ -121,7 +121,7 @@ def test_chol_rejects_unsupported(lg):
     d = lg.Design(torch.from_numpy(w.X), torch.from_numpy(w.y))
     # (past the on-chip sizes the columns stream from a workspace: n = 51 or
     # ncand = 1025 are accepted; the limits are LAGP_MAX_N and LAGP_MAX_NCAND)
-    bad = [dict(n=129), dict(ncand=4097, n=50), dict(search=W.SEARCH_RAY, numrays=2), dict(precision=W.PREC_MIXED),
+    bad = [dict(n=257), dict(ncand=4097, n=50), dict(search=W.SEARCH_RAY, numrays=2), dict(precision=W.PREC_MIXED),
            dict(search=W.SEARCH_NN)]
     XX = torch.from_numpy(w.XX).cuda()
     out = [torch.empty(2, dtype=torch.float64, device="cuda") for _ in range(3)]

@@ -163,7 +163,7 @@ def test_mle_rejects_unsupported(lg):
     bad = [(ok, lg.make_mle_params(3)), (ok.replace(d=(0.1, 0.2)), lg.make_mle_params(1)),
            (ok.replace(scoring=W.SCORING_PARTINV, precision=W.PREC_MIXED), lg.make_mle_params(1)),
            (ok, lg.make_mle_params(1, dmin=1.0, dmax=0.5)),
-           (ok.replace(n=51), lg.make_mle_params(1))]
+           (ok.replace(n=257, ncand=600), lg.make_mle_params(1))]
     for prm, q in bad:
         with pytest.raises(lg.LagpError) as e:
             lg.lagp_predict_mle(d.handle, XX, None, lg.make_params(prm), q, *out)

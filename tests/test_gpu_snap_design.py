@@ -86,6 +86,21 @@ def test_sec51_grid_one_ray(lg):
     assert out > 0  # the snaps reach rows that are not candidates
 
 
+def test_equidistant_rows_go_to_the_lower_rank(lg):
+    """On the Sec. 5.1 grid a snap target can lie exactly midway between two
+    grid rows (here at location 5, greedy step 146, d = 0.29907839...): the
+    row of lower rank in the whole design's candidate order (nearer to x,
+    then the lower row) is taken, as by a candidate list of the whole
+    design."""
+    w = W.paper2d(M=6, n=200, search=W.SEARCH_RAY, numrays=1)
+    prm = w.params.replace(ncand=W.ray_candidates_needed(200, 6, 1), snap=FULL, d=(0.2990783938635783,))
+    w = W.Workload(w.name, w.X, w.y, w.XX[5:6], prm)
+    g = _run(lg, w, prm)
+    o = oracle.predict(w.X, w.y, w.XX, prm)
+    _same(g, o, "grid tie")
+    assert o["diag"][0, 146, 4] == 0.0  # (the oracle's gap there: the two rows tie)
+
+
 @pytest.mark.parametrize("p,R,n,N", [
     (1, 1, 30, 3000),    # a one-coordinate grid
     (2, 2, 90, 6000),    # design rows past 64 (the wider local plan)
