@@ -285,16 +285,19 @@ def grid_leg(M_chol: int, M_sub: int, steps: int):
 # Table 1 of Sec. 5.1 (left: 2010 iMac, 8 threads; right: 16 Sandy Bridge
 # threads with two M2090 GPUs for the exhaustive search), seconds for the
 # 9801 predictive locations: context beside this GPU's times, not a target.
-SEC51_PAPER_SECS = {"ray_n50_stage2": 87.8, "ext_n50_stage2": 436.8, "ray_n50_stage1": 45.6,
+SEC51_PAPER_SECS = {"ray_n200_stage2": 2948.9, "ray_n200_stage1": 1695.4, "nn_n200": 710.3,
+                    "ray_n50_stage2": 87.8, "ext_n50_stage2": 436.8, "ray_n50_stage1": 45.6,
                     "ext_n50_stage1": 390.4, "nn_n50": 11.5}
 SEC51_PAPER_RIGHT = {"ext_n50_cand1000_stage1": {"cpu_gpu": 91, "imac_rays": 46},
-                     "ext_n50_cand2000_stage1": {"cpu_gpu": 120, "imac_rays": 46}}
+                     "ext_n50_cand2000_stage1": {"cpu_gpu": 120, "imac_rays": 46},
+                     "ext_n128_cand2000_stage1": {"cpu_gpu": 590, "imac_rays": 377}}
 
 
 def sec51(steps: int):
-    """The 2-d experiment of Sec. 5.1 at n = 50 (the rows of Table 1 that local
-    inference up to n = 50 covers): every design search coupled with local MLE
-    of the lengthscale, one and two stages, over the 99 x 99 predictive grid.
+    """The 2-d experiment of Sec. 5.1 (Table 1's rows at n = 200 and n = 50,
+    and the right-hand table's n = 128, N' = 2000): every design search
+    coupled with local MLE of the lengthscale, one and two stages, over the
+    99 x 99 predictive grid.
     Times cover the neighbour search, the designs, the fits and the
     predictions of all 9801 locations (inputs resident on the GPU)."""
     import torch
@@ -310,28 +313,35 @@ def sec51(steps: int):
     # so their candidate lists only hold the starts' ranks; one row keeps the
     # N' = 1000 scope for comparison
     nray = W.ray_candidates_needed(50, w.params.n0, 1)
-    rows = [("ray_n50_stage2", W.SEARCH_RAY, 2, nray, W.SCORING_PARTINV),
+    nray200 = W.ray_candidates_needed(200, w.params.n0, 1)
+    rows = [("ray_n200_stage2", W.SEARCH_RAY, 2, nray200, W.SCORING_PARTINV),
+            ("ray_n200_stage1", W.SEARCH_RAY, 1, nray200, W.SCORING_PARTINV),
+            ("nn_n200", W.SEARCH_NN, 1, 1000, W.SCORING_PARTINV),
+            ("ray_n50_stage2", W.SEARCH_RAY, 2, nray, W.SCORING_PARTINV),
             ("ext_n50_stage2", W.SEARCH_EXHAUSTIVE, 2, 1000, W.SCORING_CHOL),
             ("ray_n50_stage1", W.SEARCH_RAY, 1, nray, W.SCORING_PARTINV),
             ("ext_n50_stage1", W.SEARCH_EXHAUSTIVE, 1, 1000, W.SCORING_CHOL),
             ("nn_n50", W.SEARCH_NN, 1, 1000, W.SCORING_PARTINV),
             ("ext_n50_cand2000_stage1", W.SEARCH_EXHAUSTIVE, 1, 2000, W.SCORING_CHOL),
-            ("ray_n50_stage1_snap_cand1000", W.SEARCH_RAY, 1, 1000, W.SCORING_PARTINV)]
+            ("ray_n50_stage1_snap_cand1000", W.SEARCH_RAY, 1, 1000, W.SCORING_PARTINV),
+            ("ext_n128_cand2000_stage1", W.SEARCH_EXHAUSTIVE, 1, 2000, W.SCORING_CHOL)]
     out = {"workload": w.name.replace("_exhaustive", ""), "M": int(w.XX.shape[0]), "d0": w.params.d[0],
            "g": w.params.g, "numrays": 1, "paper_secs_context": SEC51_PAPER_SECS,
            "paper_right_table_secs_context": SEC51_PAPER_RIGHT, "rows": {}}
     for name, search, mode, nc, scoring in rows:
         full = search == W.SEARCH_RAY and "snap_cand" not in name
-        prm = w.params.replace(search=search, numrays=1 if search == W.SEARCH_RAY else 0, ncand=nc,
+        n = int(name.split("_n")[1].split("_")[0])
+        prm = w.params.replace(n=n, search=search, numrays=1 if search == W.SEARCH_RAY else 0, ncand=nc,
                                scoring=scoring if search == W.SEARCH_EXHAUSTIVE else W.SCORING_PARTINV,
                                snap=W.SNAP_DESIGN if full else W.SNAP_CANDIDATES)
         d.predict_mle(XX[:256], prm, mode)
         torch.cuda.synchronize()
+        reps = steps if n <= 50 else 1  # (the larger designs run seconds each)
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(reps):
             o = d.predict_mle(XX, prm, mode)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
+        dt = (time.perf_counter() - t0) / reps
         mu, s2 = o["mean"].cpu().numpy(), o["s2"].cpu().numpy()
         df = o["df"].cpu().numpy()
         half = student_t.ppf(0.975, df) * np.sqrt(s2)
@@ -341,7 +351,7 @@ def sec51(steps: int):
             "coverage95": float(np.mean(np.abs(w.truth - mu) <= half)),
             "dhat_median": float(np.median(o["dhat"].cpu().numpy())),
             "likelihood_evaluations_mean": float(o["iters"].float().mean().cpu()),
-            "status_nonzero": int((o["status"] != 0).sum().cpu()), "ncand": nc,
+            "status_nonzero": int((o["status"] != 0).sum().cpu()), "n": n, "ncand": nc,
             "snap": "whole design" if full else ("candidates" if search == W.SEARCH_RAY else None)}
     d.close()
     return out
