@@ -58,7 +58,8 @@ __device__ void load_and_sort(const double* bd, const int32_t* bi, int count, do
 //  1. threshold: one lane per location; the KSEL-th smallest squared
 //     distance over a subsample of the design (rows t*A mod N, t < Ns, A
 //     coprime with N, gathered once per call).  Ns = N / r with
-//     r = 2 N' / KSEL, so that about 2 N' rows of the full design fall below
+//     r = 2 n_t / KSEL (n_t = N', or a quarter of the sort size when that is
+//     larger), so that about 2 n_t >= 2 N' rows of the full design fall below
 //     that value (relative spread 1/sqrt(KSEL): fewer than N' with
 //     probability ~3e-5).
 //  2. scan: each wave takes 64 locations and one slice of the design, screens
@@ -735,8 +736,17 @@ static int64_t gcd64(int64_t x, int64_t y) {
   return x;
 }
 
+// Rows the threshold aims to let through, about 2 n_t with n_t = ncand, or a
+// quarter of the sort size for short lists (whose buffers hold at least the
+// sort size anyway): a short list then still samples one row in eight or
+// fewer instead of the whole design.
+static int knn2_target(int ncand) {
+  const int S4 = knn_sort_size(ncand) / 4;
+  return ncand > S4 ? ncand : S4;
+}
+
 int64_t knn2_sub_rows(int64_t N, int ncand) {
-  int64_t r = (2 * (int64_t)ncand) / KSEL;
+  int64_t r = (2 * (int64_t)knn2_target(ncand)) / KSEL;
   if (r < 1) r = 1;
   return (N + r - 1) / r;
 }
@@ -813,8 +823,8 @@ hipError_t launch_knn2(Knn2Args a, hipStream_t s) {
   if (a.M <= 0) return hipSuccess;
   a.S = knn_sort_size(a.ncand);
   a.CAP = knn2_capacity(a.ncand);
-  // subsample: one row in r, r = 2 ncand / KSEL, so that about 2 ncand design
-  // rows fall under the KSEL-th smallest sampled distance
+  // subsample: one row in r, r = 2 n_t / KSEL, so that about 2 n_t >= 2 ncand
+  // design rows fall under the KSEL-th smallest sampled distance
   a.sub_count = knn2_sub_rows(a.N, a.ncand);
   int64_t A = (int64_t)((double)a.N * 0.6180339887498949) | 1;
   if (A >= a.N) A = 1;

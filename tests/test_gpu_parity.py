@@ -91,6 +91,23 @@ def test_candidates_large_design_bit_exact(lg):
     assert np.array_equal(gi.astype(np.int64), oi) and np.array_equal(gd, od)
 
 
+@pytest.mark.parametrize("case", ["uniform8d_64", "sec51_55", "uniform8d_1"])
+def test_candidates_short_lists(lg, case):
+    """Short lists (the ray starts' candidates when rays snap over the whole
+    design) sample a reduced share of the design for their threshold and
+    collect more rows than they keep: still the exact lists, grid ties
+    included."""
+    if case == "sec51_55":
+        w = W.paper2d(M=40)
+        X, XX, nc = w.X, w.XX[::4], 55
+    else:
+        w = W.uniform8d(M=12)
+        X, XX, nc = w.X, w.XX, int(case.split("_")[1])
+    gi, gd = _cands(lg, X, np.zeros(len(X)), XX, nc)
+    oi, od = oracle.knn(X, XX, nc)
+    assert np.array_equal(gi.astype(np.int64), oi) and np.array_equal(gd, od)
+
+
 def test_candidates_edge_sizes(lg):
     """ncand = N returns every row, in (d2, row) order."""
     rng = np.random.default_rng(102)
