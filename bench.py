@@ -27,19 +27,22 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of one launch of each local-design kernel over the uniform 8-d
 # workload (M = 1e4), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)
-# of `bench.py --steps 1 --warmup 0 --no-ray --no-cpu --no-serving --no-mle
-# --no-ray-sweep --no-sec51 --no-prescale --copy-calibration-mb 1024`, each scaled by what the counter read for a
-# 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the
-# kernel sources it was taken on (sha256); otherwise reported as null.
+# of `bench.py --steps 1 --warmup 0 --ray-steps 1 --no-cpu --no-serving --no-mle
+# --no-ray-sweep --no-sec51 --no-prescale --no-grid --copy-calibration-mb 1024`, each scaled by what the counter
+# read for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources it was
+# taken on (sha256); otherwise reported as null.
 COMMON_SOURCES = ("paper_1409_0074_amd/csrc/dev_math.h", "paper_1409_0074_amd/csrc/lagp_internal.h",
                   "paper_1409_0074_amd/csrc/api.cpp")
 KERNEL_SOURCES = {"k_chol": ("paper_1409_0074_amd/csrc/chol.hip",) + COMMON_SOURCES,
-                  "k_local": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES}
+                  "k_local": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES,
+                  "k_local_ray": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES}
 MEASURED_TRAFFIC = {
-    "k_chol": {"sha256": "c1bcaf6daa61c64c2ad2200e7316d022d793db496cfb8d9a8171d46b468e5f01",
-               "bytes": 2.294e9, "fetch_kib": 1119451.2, "write_kib": 1257.2},
-    "k_local": {"sha256": "0e590ed338be25a38d32737b47e255bc2bc7458498a9d0cb266d0fb59c281b09",
-                "bytes": 1.405e11, "fetch_kib": 66299577.2, "write_kib": 4578716.9},
+    "k_chol": {"sha256": "90f68e64a67b830fe25bad194734f0049d86f8d6d010f28e7f6de3536294bc00",
+               "bytes": 2.2941e+09, "fetch_kib": 1119523.4, "write_kib": 1257.6},
+    "k_local": {"sha256": "e065fe3ed07a4915b189c60d7b7538fc2af04357bcc552cc9c1d85e415687cd0",
+                "bytes": 1.4055e+11, "fetch_kib": 66339872.9, "write_kib": 4578637.6},
+    "k_local_ray": {"sha256": "e065fe3ed07a4915b189c60d7b7538fc2af04357bcc552cc9c1d85e415687cd0",
+                    "bytes": 2.1848e+10, "fetch_kib": 10300592.9, "write_kib": 735077.7},
 }
 
 
@@ -669,7 +672,7 @@ def main() -> int:
             # work (kernel values, K^{-1} k_z, inner products): FP64 VALU bound
             "roofline": {"bound": "alu", "kernel": "k_local (ray search, 10 rays)", "achieved": round(r_tf, 3),
                          "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(r_tf / FP64_PEAK_TFLOPS, 4),
-                         "traffic": None,
+                         "traffic": measured_traffic("k_local_ray", M),
                          "work": f"sum over steps of E_j (2 j^2 + j (3 p + 20) + 4 j) + 3 p N' with E_j the "
                                  f"kernel's own Brent evaluations: {rflops / M:.4g} FLOP/location x {M} "
                                  f"locations per launch"}}
