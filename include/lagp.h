@@ -320,10 +320,14 @@ int32_t lagp_prescale(const double* X, int64_t N, int32_t p, const double* theta
  * Requests (host location arrays plus parameters) are admitted as long as
  * the device memory they need fits the budget; admitted requests run
  * concurrently on the device, results stay in server memory until fetched.
- * Each slot holds pinned host staging for its largest batch (4096 locations
- * at n = 128: about (540 + 8 p) x 4096 bytes), allocated at creation and
- * released by lagp_server_destroy; submits and batches allocate no pinned
- * memory. */
+ * Waiting requests with identical parameters share a batch; exhaustive FP64
+ * requests scored by Cholesky columns on chip (n <= 50, N' <= 1024, one
+ * isotropic lengthscale, no snap) share one whatever their n, lengthscale
+ * and nugget, which the batch then carries per location into a single
+ * launch.  Each slot holds pinned host staging for its largest batch (4096
+ * locations at n = 256 with their per-location parameters: (1072 + 8 p) x
+ * 4096 bytes), allocated at creation and released by lagp_server_destroy;
+ * submits and batches allocate no pinned memory. */
 
 /* Create a server on a design.  hbm_budget_bytes bounds the device memory
  * the admitted requests may hold at once; max_inflight bounds how many run

@@ -342,6 +342,10 @@ bool chol_onchip(const lagp_design* d, const lagp_params* P) {
   return chol_supported(P->n, P->ncand, d->p, (size_t)max_lds_per_block()) && !chol_stream_forced();
 }
 
+bool chol_onchip_shape(const lagp_design* d, int n, int ncand) {
+  return chol_supported(n, ncand, d->p, (size_t)max_lds_per_block()) && !chol_stream_forced();
+}
+
 size_t chol_stream_fixed(const lagp_design* d, const lagp_params* P, size_t budget, int* slots) {
   *slots = 0;
   if (P->scoring != LAGP_SCORING_CHOL || chol_onchip(d, P)) return 0;
@@ -398,7 +402,7 @@ size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool 
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in,
                     const lagp_params* P, double* mean, double* s2, double* df, int32_t* sel_idx, double* diag,
                     int32_t* status, void* stream, size_t ws_budget, void* ext_ws, size_t ext_bytes,
-                    int32_t* counts) {
+                    int32_t* counts, const PerLocation* pl) {
   if (!d) return fail(LAGP_EINVAL, "design is NULL");
   if (M < 0) return fail(LAGP_EINVAL, "M must be >= 0");
   int rays = 0;
@@ -434,6 +438,8 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
   const size_t shared = cand_in ? 0 : knn2_shared_bytes(d->N, p, nc);
   int cw_slots = 0;
   const size_t b_cw = chol_stream_fixed(d, P, ext_ws ? ext_bytes : ws_budget, &cw_slots);
+  if (pl && !(chol && cw_slots == 0 && chol_onchip(d, P)))
+    return fail(LAGP_EINVAL, "internal: per-location parameters need the on-chip Cholesky form");
   int64_t chunk = predict_chunk(d, P, cand_in != nullptr, M, ws_budget > b_cw ? ws_budget - b_cw : 0);
   if (ext_ws) {  // as many locations as the given workspace holds (11 sections, each aligned)
     const size_t per = b_knn + b_cand + b_kc + b_kc32 + b_kxc + b_xc + b_chol + b_kig + sizeof(int32_t);
@@ -474,6 +480,11 @@ int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int
     a.chol = reinterpret_cast<double*>(base + o_chol);
     a.kig = b_kig ? reinterpret_cast<double*>(base + o_kig) : nullptr;
     a.cw = reinterpret_cast<double*>(base + o_cw);
+    if (pl) {
+      a.nloc = pl->n + m0;
+      a.dloc = pl->d + m0;
+      a.gloc = pl->g + m0;
+    }
     a.mean = mean + m0;
     a.s2 = s2 + m0;
     a.df = df + m0;

@@ -173,6 +173,7 @@ struct ChRun {
   double mu, psi, qq;
   int done;
   bool pd, stop;
+  int n;  // this location's design size (<= a.n, the stride of the per-location outputs)
 };
 
 // Gaussian correlation between the winner w and candidate c in the rounding
@@ -296,7 +297,7 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nwv = blockDim.x >> 6;
   const int c0 = 2 * tid;
-  const int n = a.n, n0 = a.n0;
+  const int n = R.n, n0 = a.n0, nst = a.n - a.n0;  // (nst: stride of the per-step outputs)
   for (int jj = 0; jj < CH_CHUNK; ++jj) {
     const int j = B * CH_CHUNK + jj;
     if (j >= n || R.stop) return;
@@ -367,12 +368,12 @@ __device__ __forceinline__ void ch_block(const LocalArgs& a, const ChLds& L, ChP
       R.psi = __builtin_fma(zj, zj, R.psi);
       R.qq = __builtin_fma(wxj, wxj, R.qq);
       if (DIAG && j >= n0 && a.diag) {
-        double* dg = a.diag + (m * (n - n0) + (j - n0)) * 2;
+        double* dg = a.diag + (m * nst + (j - n0)) * 2;
         dg[0] = b1;
         dg[1] = b2 < 0.0 ? -__builtin_huge_val() : b2;
       }
       if (j >= n0 && a.counts) {  // every free candidate is scored
-        int32_t* ct = a.counts + (m * (n - n0) + (j - n0)) * 2;
+        int32_t* ct = a.counts + (m * nst + (j - n0)) * 2;
         ct[0] = a.ncand - j;
         ct[1] = 0;
       }
@@ -420,20 +421,20 @@ __device__ __forceinline__ void ch_blocks(const LocalArgs& a, const ChLds& L, Ch
                                           ChRun& R, int64_t m, double w0) {
   if constexpr (B < ChCfg<NB, PM, CS>::NCH) {
     ch_block<NB, PM, CS, DIAG, B>(a, L, S, R, m, w0);
-    if (!R.stop && (B + 1) * CH_CHUNK < a.n) ch_blocks<NB, PM, CS, DIAG, B + 1>(a, L, S, R, m, w0);
+    if (!R.stop && (B + 1) * CH_CHUNK < R.n) ch_blocks<NB, PM, CS, DIAG, B + 1>(a, L, S, R, m, w0);
   }
 }
 
-// One workgroup of 64 ceil(N'/128) threads per location; thread t holds the
-// candidates of ranks 2t and 2t+1.
-template <int NB, int PM, int CS, bool DIAG>
-__global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) void k_chol(LocalArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// One location on one workgroup of 64 ceil(N'/128) threads; thread t holds
+// the candidates of ranks 2t and 2t+1.  Its design size, lengthscale and
+// nugget are the location's own when the per-location arrays are given.
+template <int NB, int PM, int CS, bool DIAG, bool PL>
+__device__ __forceinline__ void ch_location(const LocalArgs& a, const ChLds& L, int64_t m) {
   using Cf = ChCfg<NB, PM, CS>;
-  const ChLds L = ch_carve<NB, PM, CS>(smem);
   const int tid = threadIdx.x;
-  const int64_t m = blockIdx.x;
-  const int p = a.p, n = a.n, nc = a.ncand;
+  const int p = a.p, nc = a.ncand, nmax = a.n;
+  const int n = PL ? a.nloc[m] : a.n;
+  const double g = PL ? a.gloc[m] : a.g;
   const int32_t* C = a.cand + m * nc;
   const int c0 = 2 * tid;
   // isotropic reciprocal lengthscale: per location when given (a location
@@ -497,12 +498,12 @@ __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) voi
         kx = gexp(-s);
       }
     }
-    S.v[i] = 1.0 + a.g;
+    S.v[i] = 1.0 + g;
     S.cov[i] = kx;
     S.q[i] = yc[i];
   }
 
-  ChRun R{0.0, 0.0, 0.0, 0, true, false};
+  ChRun R{0.0, 0.0, 0.0, 0, true, false, n};
   ch_blocks<NB, PM, CS, DIAG, 0>(a, L, S, R, m, w0);
 
   const int vf = __syncthreads_or(S.vflag);
@@ -511,7 +512,7 @@ __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) voi
     double mu = __builtin_nan(""), sc = __builtin_nan("");
     if (ok) {
       mu = R.mu;
-      sc = R.psi * ((1.0 + a.g) - R.qq) / (double)n;
+      sc = R.psi * ((1.0 + g) - R.qq) / (double)n;
     }
     int st = 0;
     if (!R.pd) st |= LAGP_STATUS_NOTPD;
@@ -522,10 +523,19 @@ __global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) voi
     a.df[m] = (double)n;
     a.status[m] = st;
   }
-  if (a.sel) {
+  if (a.sel) {  // rows of nmax entries, -1 past this location's design
     const int done = R.pd ? R.done : a.n0;  // not positive definite: report the n0 nearest
-    for (int i = tid; i < n; i += blockDim.x) a.sel[m * n + i] = i < done ? C[R.pd ? L.J[i] : i] : -1;
+    for (int i = tid; i < nmax; i += blockDim.x) a.sel[m * nmax + i] = i < done ? C[R.pd ? L.J[i] : i] : -1;
   }
+}
+
+// The search kernel: one workgroup per location.  PL: the call carries
+// per-location design sizes and nuggets (a merged batch of requests).
+template <int NB, int PM, int CS, bool DIAG, bool PL>
+__global__ __launch_bounds__(CS / 2) __attribute__((amdgpu_waves_per_eu(2))) void k_chol(LocalArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const ChLds L = ch_carve<NB, PM, CS>(smem);
+  ch_location<NB, PM, CS, DIAG, PL>(a, L, blockIdx.x);
 }
 
 constexpr int CH_NB_SMALL = 4;  // n <= 34
@@ -558,19 +568,20 @@ ChPick ch_pick(int n, int ncand, int p) {
   return k;
 }
 
-template <int NB, int PM, int CS, bool DIAG>
+template <int NB, int PM, int CS, bool DIAG, bool PL>
 hipError_t launch_chol_t(const LocalArgs& a, size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol<NB, PM, CS, DIAG>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol<NB, PM, CS, DIAG, PL>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int T = (a.ncand + 127) / 128 * 64;
-  hipLaunchKernelGGL((k_chol<NB, PM, CS, DIAG>), dim3(a.M), dim3(T), lds, s, a);
+  hipLaunchKernelGGL((k_chol<NB, PM, CS, DIAG, PL>), dim3((unsigned)a.M), dim3(T), lds, s, a);
   return hipGetLastError();
 }
 
 template <int NB, int PM, int CS>
 hipError_t launch_chol_d(const LocalArgs& a, size_t lds, hipStream_t s) {
-  return a.diag ? launch_chol_t<NB, PM, CS, true>(a, lds, s) : launch_chol_t<NB, PM, CS, false>(a, lds, s);
+  if (a.nloc) return a.diag ? launch_chol_t<NB, PM, CS, true, true>(a, lds, s) : launch_chol_t<NB, PM, CS, false, true>(a, lds, s);
+  return a.diag ? launch_chol_t<NB, PM, CS, true, false>(a, lds, s) : launch_chol_t<NB, PM, CS, false, false>(a, lds, s);
 }
 
 template <int NB, int PM>
@@ -591,6 +602,7 @@ bool chol_supported(int n, int ncand, int p, size_t lds_max) {
 
 hipError_t launch_chol(const LocalArgs& a, hipStream_t s) {
   if (a.M <= 0) return hipSuccess;
+  if (!a.nloc != !a.gloc) return hipErrorInvalidValue;
   const ChPick k = ch_pick(a.n, a.ncand, a.p);
   return k.nb == CH_NB_SMALL ? launch_chol_pm<CH_NB_SMALL>(a, k, s) : launch_chol_pm<CH_NB_LARGE>(a, k, s);
 }

@@ -73,6 +73,18 @@ struct LocalArgs {
   int32_t snap_full;       // ray search: snap over the whole design through `grid` (else the candidates)
   GridDev grid;
   double* kig;             // designs past 128 points (ray, nearest neighbours): M x NR x 257 K_J^{-1}
+  // Cholesky form on chip: per-location design sizes (<= n, which then is the
+  // stride of sel) and nuggets (both given or both null: n and g)
+  const int32_t* nloc;
+  const double* gloc;
+};
+
+// Per-location parameters of a merged batch (device arrays, M entries each):
+// design size, isotropic lengthscale, nugget.
+struct PerLocation {
+  const int32_t* n;
+  const double* d;
+  const double* g;
 };
 
 // Arguments of the local MLE kernel (mle.hip) for one chunk of locations.
@@ -196,10 +208,13 @@ size_t predict_workspace_bytes(const lagp_design* d, const lagp_params* P, bool 
                                size_t ws_budget);
 // ext_ws (nullable): a caller-provided device workspace of ext_bytes; the
 // locations then run in chunks that fit it and nothing is allocated.
+// pl (nullable): per-location n, d, g for exhaustive search by Cholesky
+// columns on chip (P->n is then the largest n and the stride of sel_idx).
 int32_t run_predict(const lagp_design* d, const double* XX, int64_t M, const int32_t* cand_in, const lagp_params* P,
                     double* mean, double* s2, double* df, int32_t* sel_idx, double* diag, int32_t* status,
                     void* stream, size_t ws_budget, void* ext_ws = nullptr, size_t ext_bytes = 0,
-                    int32_t* counts = nullptr);
+                    int32_t* counts = nullptr, const PerLocation* pl = nullptr);
+bool chol_onchip_shape(const lagp_design* d, int n, int ncand);
 const char* set_error(const char* msg);
 
 }  // namespace lagp

@@ -1,8 +1,13 @@
 // Continuous-batching server over a resident design.
 //
 // Requests (host location arrays + parameters) wait in a FIFO.  A worker
-// thread groups waiting requests with identical parameters into a batch (up
-// to a location cap), admits the batch when the device memory it needs (its
+// thread groups waiting requests into a batch (up to a location cap): requests
+// with identical parameters, and exhaustive FP64 requests scored by Cholesky
+// columns on chip whatever their design sizes, lengthscales and nuggets (the
+// batch then carries those per location, and one launch of the search kernel
+// serves them all, the device's workgroup dispatcher handing locations to
+// compute units as they free up); it admits the batch when the device
+// memory it needs (its
 // inputs, outputs and prediction workspace) fits under the HBM budget and a
 // stream slot is free, and launches it: upload, candidate search, local
 // designs, download, all asynchronous on the slot's stream (through pinned
@@ -60,7 +65,8 @@ struct Request {
 
 struct Batch {
   std::vector<std::shared_ptr<Request>> reqs;
-  lagp_params P{};
+  lagp_params P{};  // (a merged batch: the largest n of its requests)
+  bool merged = false;  // per-location n, d, g
   int64_t M = 0;
   size_t bytes = 0;  // device bytes held while in flight
   int slot = -1;
@@ -77,8 +83,15 @@ size_t io_bytes(int64_t M, int p, int n) {
   return (size_t)M * (sizeof(double) * p + 3 * sizeof(double) + sizeof(int32_t) * n + sizeof(int32_t));
 }
 
-// Pinned staging of one slot: the largest batch's locations and results.
-size_t stage_bytes(int p) { return io_bytes(BATCH_MAX_LOCATIONS, p, LAGP_MAX_N) + 256; }
+// A merged batch's per-location parameters as staged and uploaded after the
+// locations: d and g (FP64), then n (int32), padded to 8 bytes.
+size_t pl_stage_bytes(int64_t M) { return ((size_t)M * (2 * sizeof(double) + sizeof(int32_t)) + 7) & ~size_t(7); }
+
+// Pinned staging of one slot: the largest batch's locations, per-location
+// parameters and results.
+size_t stage_bytes(int p) {
+  return io_bytes(BATCH_MAX_LOCATIONS, p, LAGP_MAX_N) + pl_stage_bytes(BATCH_MAX_LOCATIONS) + 256;
+}
 
 }  // namespace
 
@@ -115,9 +128,30 @@ struct lagp_server {
 
 namespace {
 
-size_t batch_device_bytes(const lagp_server* s, const lagp_params& P, int64_t M) {
+// Per-location parameters of a merged batch: n (int32), d and g (FP64).
+size_t per_location_bytes(int64_t M) { return (size_t)M * (sizeof(int32_t) + 2 * sizeof(double)); }
+
+size_t batch_device_bytes(const lagp_server* s, const lagp_params& P, int64_t M, bool merged) {
   const int p = s->design->p;
-  return io_bytes(M, p, P.n) + lagp::predict_workspace_bytes(s->design, &P, false, M, s->ws_cap) + 4096;
+  return io_bytes(M, p, P.n) + (merged ? per_location_bytes(M) + 256 : 0) +
+         lagp::predict_workspace_bytes(s->design, &P, false, M, s->ws_cap) + 4096;
+}
+
+// Requests that may share a batch whatever their n, d and g: exhaustive FP64
+// search by Cholesky columns on chip with an isotropic lengthscale.
+bool mergeable(const lagp_server* s, const lagp_params& P) {
+  return P.search == LAGP_SEARCH_EXHAUSTIVE && P.precision == LAGP_PREC_FP64 && P.scoring == LAGP_SCORING_CHOL &&
+         P.d_len == 1 && P.snap == LAGP_SNAP_CANDIDATES && lagp::chol_onchip_shape(s->design, P.n, P.ncand);
+}
+
+bool same_batch(const lagp_server* s, const lagp_params& a, const lagp_params& b) {
+  if (same_params(a, b)) return true;
+  if (!mergeable(s, a) || !mergeable(s, b)) return false;
+  lagp_params x = a, y = b;  // equal but for n, d and g
+  x.n = y.n = 0;
+  x.d[0] = y.d[0] = 0.0;
+  x.g = y.g = 0.0;
+  return same_params(x, y);
 }
 
 // Called with the lock held: form the next batch from the waiting queue,
@@ -126,18 +160,22 @@ Batch form_batch(lagp_server* s, size_t start) {
   Batch b;
   auto& head = s->waiting[start];
   b.P = head->P;
+  b.merged = mergeable(s, head->P);
   for (size_t i = start; i < s->waiting.size(); ++i) {
     auto& r = s->waiting[i];
-    if (!same_params(r->P, b.P)) continue;
+    if (!same_batch(s, r->P, head->P)) continue;
+    lagp_params P = b.P;
+    P.n = std::max(P.n, r->P.n);
     // the first request alone always fits (checked at submit); growth stops
     // at the location cap or the budget, so a head batch can always run
     if (!b.reqs.empty() &&
-        (b.M + r->M > BATCH_MAX_LOCATIONS || batch_device_bytes(s, b.P, b.M + r->M) > s->budget))
+        (b.M + r->M > BATCH_MAX_LOCATIONS || batch_device_bytes(s, P, b.M + r->M, b.merged) > s->budget))
       break;
+    b.P = P;
     b.reqs.push_back(r);
     b.M += r->M;
   }
-  b.bytes = batch_device_bytes(s, b.P, b.M);
+  b.bytes = batch_device_bytes(s, b.P, b.M, b.merged);
   return b;
 }
 
@@ -154,27 +192,42 @@ int32_t launch_batch(lagp_server* s, Batch& b) {
   const int64_t M = b.M;
   hipStream_t st = s->streams[b.slot];
   const size_t xb = sizeof(double) * (size_t)M * p, db = sizeof(double) * (size_t)M,
-               sb = sizeof(int32_t) * (size_t)M * n, tb = sizeof(int32_t) * (size_t)M;
-  b.host = s->stage[b.slot];  // (xb + 3 db + sb + tb <= stage_bytes: M <= BATCH_MAX_LOCATIONS, n <= LAGP_MAX_N)
+               sb = sizeof(int32_t) * (size_t)M * n, tb = sizeof(int32_t) * (size_t)M,
+               plb = b.merged ? pl_stage_bytes(M) : 0;
+  // (xb + plb + 3 db + sb + tb <= stage_bytes: M <= BATCH_MAX_LOCATIONS, n <= LAGP_MAX_N)
+  b.host = s->stage[b.slot];
   char* h = b.host;
   double* hx = reinterpret_cast<double*>(h);
+  double* hd = reinterpret_cast<double*>(h + xb);
+  double* hg = hd + M;
+  int32_t* hn = reinterpret_cast<int32_t*>(hg + M);
   int64_t off = 0;
   for (auto& r : b.reqs) {
     std::memcpy(hx + off * p, r->xx.data(), sizeof(double) * r->M * p);
+    if (b.merged)
+      for (int64_t i = 0; i < r->M; ++i) {
+        hd[off + i] = r->P.d[0];
+        hg[off + i] = r->P.g;
+        hn[off + i] = r->P.n;
+      }
     off += r->M;
   }
-  if (hipMallocAsync(&b.dev, xb + 3 * db + sb + tb, st) != hipSuccess) return LAGP_ENOMEM;
+  if (hipMallocAsync(&b.dev, xb + plb + 3 * db + sb + tb, st) != hipSuccess) return LAGP_ENOMEM;
   char* dv = reinterpret_cast<char*>(b.dev);
   double* dx = reinterpret_cast<double*>(dv);
-  double* dmean = reinterpret_cast<double*>(dv + xb);
+  double* dd = reinterpret_cast<double*>(dv + xb);
+  double* dmean = reinterpret_cast<double*>(dv + xb + plb);
   double* ds2 = dmean + M;
   double* ddf = ds2 + M;
   int32_t* dsel = reinterpret_cast<int32_t*>(ddf + M);
   int32_t* dst = dsel + (size_t)M * n;
-  if (hipMemcpyAsync(dx, hx, xb, hipMemcpyHostToDevice, st) != hipSuccess) return LAGP_EDEVICE;
-  int32_t rc = lagp::run_predict(s->design, dx, M, nullptr, &b.P, dmean, ds2, ddf, dsel, nullptr, dst, st, s->ws_cap);
+  if (hipMemcpyAsync(dx, hx, xb + plb, hipMemcpyHostToDevice, st) != hipSuccess) return LAGP_EDEVICE;
+  const lagp::PerLocation pl{reinterpret_cast<const int32_t*>(dd + 2 * M), dd, dd + M};
+  int32_t rc = lagp::run_predict(s->design, dx, M, nullptr, &b.P, dmean, ds2, ddf, dsel, nullptr, dst, st, s->ws_cap,
+                                 nullptr, 0, nullptr, b.merged ? &pl : nullptr);
   if (rc < 0) return rc;
-  if (hipMemcpyAsync(h + xb, dmean, 3 * db + sb + tb, hipMemcpyDeviceToHost, st) != hipSuccess) return LAGP_EDEVICE;
+  if (hipMemcpyAsync(h + xb + plb, dmean, 3 * db + sb + tb, hipMemcpyDeviceToHost, st) != hipSuccess)
+    return LAGP_EDEVICE;
   if (hipFreeAsync(b.dev, st) != hipSuccess) return LAGP_EDEVICE;
   b.dev = nullptr;
   if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) return LAGP_EDEVICE;
@@ -186,8 +239,8 @@ int32_t launch_batch(lagp_server* s, Batch& b) {
 void finish_batch(lagp_server* s, Batch& b, int32_t rc) {
   const int p = s->design->p, n = b.P.n;
   const int64_t M = b.M;
-  const size_t xb = sizeof(double) * (size_t)M * p;
-  const double* hmean = b.host ? reinterpret_cast<const double*>(b.host + xb) : nullptr;
+  const size_t xb = sizeof(double) * (size_t)M * p, plb = b.merged ? pl_stage_bytes(M) : 0;
+  const double* hmean = b.host ? reinterpret_cast<const double*>(b.host + xb + plb) : nullptr;
   const double* hs2 = hmean ? hmean + M : nullptr;
   const double* hdf = hs2 ? hs2 + M : nullptr;
   const int32_t* hsel = hdf ? reinterpret_cast<const int32_t*>(hdf + M) : nullptr;
@@ -201,13 +254,15 @@ void finish_batch(lagp_server* s, Batch& b, int32_t rc) {
       r->mean = new (std::nothrow) double[m];
       r->s2 = new (std::nothrow) double[m];
       r->df = new (std::nothrow) double[m];
-      r->sel = new (std::nothrow) int32_t[(size_t)m * n];
+      const int rn = r->P.n;  // (a merged batch's rows hold n of the batch: the largest)
+      r->sel = new (std::nothrow) int32_t[(size_t)m * rn];
       r->status = new (std::nothrow) int32_t[m];
       if (r->mean && r->s2 && r->df && r->sel && r->status) {
         std::memcpy(r->mean, hmean + off, sizeof(double) * m);
         std::memcpy(r->s2, hs2 + off, sizeof(double) * m);
         std::memcpy(r->df, hdf + off, sizeof(double) * m);
-        std::memcpy(r->sel, hsel + off * n, sizeof(int32_t) * m * n);
+        for (int64_t i = 0; i < m; ++i)
+          std::memcpy(r->sel + i * rn, hsel + (off + i) * n, sizeof(int32_t) * rn);
         std::memcpy(r->status, hst + off, sizeof(int32_t) * m);
         for (int64_t i = 0; i < m; ++i)
           if (r->status[i] != 0) r->rc = LAGP_WARN_NUMERIC;
@@ -264,7 +319,7 @@ void worker_main(lagp_server* s) {
         if (start == 0 && s->head_bypassed >= HEAD_BYPASS_LIMIT) break;
         // look for a later batch with other parameters
         size_t nxt = start + 1;
-        while (nxt < s->waiting.size() && same_params(s->waiting[nxt]->P, b.P)) ++nxt;
+        while (nxt < s->waiting.size() && same_batch(s, s->waiting[nxt]->P, s->waiting[start]->P)) ++nxt;
         if (start == 0) head_blocked = true;
         start = nxt;
         continue;
@@ -357,7 +412,7 @@ int32_t lagp_server_submit(lagp_server* s, const double* XX_host, int64_t M, con
   int32_t rc = lagp::check_predict_params(s->design, P);
   if (rc != LAGP_OK) return rc;
   if (M > BATCH_MAX_LOCATIONS) return server_fail(LAGP_EINVAL, "a request may hold at most 4096 locations");
-  const size_t need = batch_device_bytes(s, *P, M);
+  const size_t need = batch_device_bytes(s, *P, M, mergeable(s, *P));
   if (need > s->budget) return server_fail(LAGP_ENOMEM, "request can never fit the server's HBM budget");
   auto r = std::make_shared<Request>();
   r->P = *P;

@@ -138,6 +138,32 @@ def test_served_requests_equal_the_oracle(lg):
         _same(r, o, f"request {k}")
 
 
+def test_merged_batch_of_varied_requests_equals_the_oracle(lg):
+    """Exhaustive FP64 requests scored by Cholesky columns with different
+    design sizes, lengthscales and nuggets share one batch (one launch with
+    per-location parameters): each request's results equal the oracle's own
+    run of it."""
+    rng = np.random.default_rng(531)
+    X = rng.random((50000, 4))
+    y = W.f_mix4(X)
+    base = W.Params(n0=6, ncand=1000, scoring=W.SCORING_CHOL)
+    prms = [base.replace(n=n, d=(d,), g=g) for n, d, g in
+            [(20, 0.1, 1e-6), (50, 0.05, 1e-4), (35, 0.2, 1e-6), (50, 0.1, 1e-6), (8, 0.1, 1e-2), (41, 0.3, 0.0)]]
+    reqs = [(rng.random((int(m), 4)), prm) for m, prm in zip([7, 13, 1, 30, 5, 9], prms)]
+    import torch
+
+    d = lg.Design(torch.from_numpy(X), torch.from_numpy(y))
+    srv = lg.lagp_server_create(d.handle, 4 << 30, 1)  # one slot: the requests wait and batch together
+    try:
+        tickets = [lg.lagp_server_submit(srv, XX, lg.make_params(prm))[1] for XX, prm in reqs]
+        res = [lg.lagp_server_fetch(srv, t, XX.shape[0], prm.n) for t, (XX, prm) in zip(tickets, reqs)]
+    finally:
+        lg.lagp_server_destroy(srv)
+        d.close()
+    for k, ((XX, prm), r) in enumerate(zip(reqs, res)):
+        _same(r, oracle.predict(X, y, XX, prm), f"request {k}")
+
+
 @pytest.mark.parametrize("p,R,n", [(8, 1, 50), (8, 7, 50), (2, 16, 64), (3, 17, 40), (8, 10, 64)])
 def test_ray_tile_and_wave_forms_bit_exact(lg, monkeypatch, p, R, n):
     """Up to 16 rays at n <= 64 run on one wave per location (every ray on a

@@ -77,18 +77,19 @@ def test_noalloc_equals_predict_twice(env, case, M1, M2):
 
 
 def test_noalloc_rejects_what_the_scratch_cannot_hold():
-    """A 2e7-row design with 64 candidates: the candidate search's per-call
-    subsample alone (N/2 rows) exceeds the 64 MiB scratch."""
+    """A 2e7-row 4-d design with 64 candidates: the candidate search's
+    per-call subsample alone (N/8 rows of 4 coordinates, 80 MB) exceeds the
+    64 MiB scratch."""
     import torch
 
     import paper_1409_0074_amd as lg
 
     rng = np.random.default_rng(602)
-    X = torch.from_numpy(rng.random((20_000_000, 1)))
+    X = torch.from_numpy(rng.random((20_000_000, 4)))
     d = lg.Design(X, X[:, 0].clone())
     try:
         prm = W.Params(n0=4, n=10, ncand=64, d=(0.1,), g=1e-6, scoring=W.SCORING_CHOL)
-        XX = torch.from_numpy(rng.random((4, 1))).cuda()
+        XX = torch.from_numpy(rng.random((4, 4))).cuda()
         out = [torch.empty(4, dtype=torch.float64, device="cuda") for _ in range(3)]
         with pytest.raises(lg.LagpError) as e:
             lg.lagp_predict_noalloc(d.handle, XX, lg.make_params(prm), *out)
