@@ -326,40 +326,49 @@ __global__ __launch_bounds__(64) void k_knn_scan(Knn2Args a) {
 }
 
 // The same scan with the screen on the FP32 matrix cores (twice the FP64
-// rate), for designs whose squared norms stay far inside FP32's range.  Two
-// more K dimensions carry the rest of the screen into the product: location
-// q contributes (-2 x_q, 1, -th_q), design row i (x_i, rn_i, 1), so the
-// accumulator is t - th_q itself and a pair passes when its sign bit is set
-// (no per-pair conversion, fma or comparison; a byte permute gathers four
-// sign bits at once).
+// rate), for designs whose squared norms stay far inside FP32's range.  The
+// accumulator starts at rn_i - th_q (one FP32 addition per entry) and the
+// product adds -2 x_q . x_i over the coordinates alone, so it ends at
+// t - th_q itself and a pair passes when its sign bit is set (no per-pair
+// conversion, fma or comparison; a byte permute gathers four sign bits at
+// once), with no K chunk spent on the two constant terms.
 // Error: operands are rounded to FP32 (u32 = 2^-24; th_q upward, which only
-// widens the screen), and the K = 4 NCH products are summed with at most
-// K + 1 roundings, so the accumulator is within
+// widens the screen); the start value is rounded once and the product's
+// 4 NCC terms are summed into it with at most 4 NCC + 1 roundings, so with
+// K = 4 NCC + 4 the accumulator is within
 // (K + 3) u32 (2 ||x_q||^2 + 3 max ||x_i||^2 + tau) (1 + 1e-3) of
 // t - th_q (the terms: the rounded coordinates, 2 u32 (||x_q||^2 + ||x_i||^2);
-// rn_i, u32 ||x_i||^2; the summation, (K + 1) u32 times the sum of the
-// products' magnitudes, which is at most 2 ||x_q||^2 + 2 ||x_i||^2 + tau).
+// rn_i, u32 ||x_i||^2; the start value, u32 (||x_i||^2 + |th_q|); the
+// summation, (4 NCC + 1) u32 times the sum of the magnitudes, which is at
+// most 2 ||x_q||^2 + 2 ||x_i||^2 + tau + |rn_i - th_q|).
 // th_q adds 4 (K + 4) u32 (2 ||x_q||^2 + 3 max ||x_i||^2 + tau) + 2^-100
 // (flushed subnormals) to the FP64 bound of the other scan, so every row
 // whose defined squared distance is <= tau gives a negative accumulator, and
 // the defined squared distance (FP64, from the FP64 coordinates) still
 // decides.  Infinite bounds stay exact: th = -inf (no row) gives +inf, th = +inf
 // (every row) -inf, and a row past the slice (rn = +inf) is masked.
-// MFMA operands as in the FP64 scan; the FP32 16x16x4 result D[i][n] sits in
-// register i % 4 of lane 16 (i / 4) + n.
-// Seven waves per SIMD (the scan is latency-bound): registers capped to fit,
-// which also keeps the MFMA results out of the accumulation registers.
+// MFMA operands as in the FP64 scan; the FP32 16x16x4 result D[i][n] (and
+// the start value C[i][n]) sits in register i % 4 of lane 16 (i / 4) + n.
+// Six waves per SIMD with three tiles in flight each (the scan waits on the
+// design stream): registers capped to fit, which also keeps the MFMA results
+// out of the accumulation registers.
+constexpr int SCAN32_WAVES = 6;  // per SIMD (registers of SD = 3 tiles in flight)
+
 template <int P>
-__global__ __launch_bounds__(64, 7) void k_knn_scan32(Knn2Args a) {
+__global__ __launch_bounds__(64, SCAN32_WAVES) void k_knn_scan32(Knn2Args a) {
+  constexpr int SD = 3;  // tiles in flight per wave
   constexpr int PD = P > 0 ? P : LAGP_MAX_DIM;
-  constexpr int NCH = (PD + 2 + 3) / 4;  // K-chunks of 4: coordinates, then (1, rn) and (-th, 1)
-  constexpr int K = 4 * NCH;
+  constexpr int NCC = (PD + 3) / 4;  // K-chunks of 4 coordinates
+  constexpr int K = 4 * NCC + 4;     // (the bound's constant)
   const int p = P > 0 ? P : a.p;
   const int lane = threadIdx.x, g = lane >> 4, n = lane & 15;
   const int q0 = blockIdx.x * 64;
   const double u = 0x1p-53, u32 = 0x1p-24;
-  // A operand: set s, row n -> location q0 + 16 s + n
-  float af[4][NCH];
+  // A operand: set s, row n -> location q0 + 16 s + n; nth_l[s][i]: -th of
+  // location q0 + 16 s + i (the start value's rows, read per tile: registers
+  // are what limits the waves per SIMD)
+  float af[4][NCC];
+  __shared__ __align__(16) float nth_l[4][16];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int q = q0 + 16 * s + n;
@@ -375,14 +384,11 @@ __global__ __launch_bounds__(64, 7) void k_knn_scan32(Knn2Args a) {
     }
     const float nth = -__double2float_ru(th);
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
+    for (int c = 0; c < NCC; ++c) {
       const int d = 4 * c + g;
-      float v = 0.0f;
-      if (d < p) v = q < a.M ? -2.0f * (float)a.XX[(int64_t)q * p + d] : 0.0f;
-      else if (d == p) v = 1.0f;
-      else if (d == p + 1) v = nth;
-      af[s][c] = v;
+      af[s][c] = (d < p && q < a.M) ? -2.0f * (float)a.XX[(int64_t)q * p + d] : 0.0f;
     }
+    if (g == 0) nth_l[s][n] = nth;
   }
   // hit-mask bits of real locations: bit 8 r + s <-> location q0 + 16 s + 4 g + r
   unsigned locmask = 0;
@@ -393,77 +399,75 @@ __global__ __launch_bounds__(64, 7) void k_knn_scan32(Knn2Args a) {
       if (q0 + 16 * s + 4 * g + r < a.M) locmask |= 1u << (8 * r + s);
   const int64_t i0 = (int64_t)blockIdx.y * a.slice;
   const int64_t i1 = i0 + a.slice < a.N ? i0 + a.slice : a.N;
-  // a tile stages at most 64 x 16 = 1024 pairs and the buffer is settled
-  // once it holds more than 128: 5.8 KB of LDS per wave, so LDS leaves room
-  // for seven waves per SIMD
-  constexpr int STG = 1152;
+  // Staging (the workgroup is one wave, so its count lives in a scalar
+  // register): a lane whose tile has hits stages one entry, its design row
+  // and its hit word with g in bits 28-29 (the locations are 16 s + 4 g + r
+  // for the set bits 8 r + s); a tile adds at most 64 entries and the buffer
+  // is settled once it holds more than STG - 64.
+  constexpr int STG = 320;
   __shared__ int32_t st_row[STG];
-  __shared__ uint8_t st_q[STG];
-  __shared__ int st_n;
-  if (lane == 0) st_n = 0;
-  __syncthreads();
+  __shared__ uint32_t st_w[STG];
+  int st_n = 0;
   auto flush = [&]() {
-    __syncthreads();
-    const int tot = st_n;
-    for (int e = lane; e < tot; e += 64) {
+    __syncthreads();  // (the entries' LDS writes are complete)
+    for (int e = lane; e < st_n; e += 64) {
       const int64_t row = st_row[e];
-      const int q = q0 + st_q[e];
-      const double* xq = a.XX + (int64_t)q * p;
+      const uint32_t w = st_w[e];
+      const int gq = (int)(w >> 28);
       const double* xr = a.X + row * p;
-      double acc = 0.0;
-      for (int k = 0; k < p; ++k) {
-        const double d = xq[k] - xr[k];
-        acc = __builtin_fma(d, d, acc);
-      }
-      if (acc <= a.tau[q]) {
-        const int pos = atomicAdd(&a.cnt[q], 1);
-        if (pos < a.CAP) {
-          a.buf_d2[(int64_t)q * a.CAP + pos] = acc;
-          a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)row;
+      for (uint32_t m = w & 0x0F0F0F0Fu; m; m &= m - 1) {
+        const int bb = __builtin_ctz(m);
+        const int q = q0 + 16 * (bb & 7) + 4 * gq + (bb >> 3);
+        const double* xq = a.XX + (int64_t)q * p;
+        double acc = 0.0;
+        for (int k = 0; k < p; ++k) {
+          const double d = xq[k] - xr[k];
+          acc = __builtin_fma(d, d, acc);
+        }
+        if (acc <= a.tau[q]) {
+          const int pos = atomicAdd(&a.cnt[q], 1);
+          if (pos < a.CAP) {
+            a.buf_d2[(int64_t)q * a.CAP + pos] = acc;
+            a.buf_idx[(int64_t)q * a.CAP + pos] = (int32_t)row;
+          }
         }
       }
     }
-    __syncthreads();
-    if (lane == 0) st_n = 0;
-    __syncthreads();
+    __syncthreads();  // (every entry read before the next tile's writes)
+    st_n = 0;
   };
-  // B operand: column n -> design row i + n.  The next tile's loads are
-  // issued one tile ahead into raw registers and converted only when used.
-  float xn[NCH];
-  double rnn = 0.0;
-  auto load_tile = [&](int64_t i) {
+  // B operand: column n -> design row i + n.  Tiles are loaded SD tiles
+  // ahead (SD register sets in a ring) into raw registers and converted only
+  // when used: the scan waits on the design stream, not on its arithmetic.
+  float xn[SD][NCC];
+  double rnn[SD];
+  auto load_tile = [&](int64_t i, float (&xr)[NCC], double& rr_n) {
     const int64_t rr = i + n;
     const int64_t rl = rr < i1 ? rr : i1 - 1;  // in bounds: every load is unconditional
-    rnn = a.rn[rl];
+    rr_n = a.rn[rl];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
+    for (int c = 0; c < NCC; ++c) {
       const int d = 4 * c + g;
-      xn[c] = (P == 0 || 4 * c < P) ? a.X32[rl * p + (d < p ? d : p - 1)] : 0.0f;
+      xr[c] = a.X32[rl * p + (d < p ? d : p - 1)];
     }
   };
-  if (i0 < i1) load_tile(i0);
-  for (int64_t i = i0; i < i1; i += 16) {
+  auto scan_tile = [&](int64_t i, const float (&xr)[NCC], double rr_n) {
     const int64_t rr = i + n;
     const bool valid = rr < i1;
-    float bf[NCH];
-    {
-      const float rn = valid ? (float)rnn : __builtin_huge_valf();
+    float bf[NCC];
+    const float rn = valid ? (float)rr_n : __builtin_huge_valf();
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const int d = 4 * c + g;
-        float v = xn[c];
-        if (!(P > 0 && 4 * c + 3 < P)) v = d < p ? v : 0.0f;  // chunks that may hold padding
-        if (P == 0 || 4 * c + 3 >= P) v = d == p ? rn : (d == p + 1 ? 1.0f : v);
-        bf[c] = v;
-      }
+    for (int c = 0; c < NCC; ++c) {
+      const int d = 4 * c + g;
+      bf[c] = (P > 0 && 4 * c + 3 < P) || d < p ? xr[c] : 0.0f;  // (chunks that may hold padding)
     }
-    if (i + 16 < i1) load_tile(i + 16);
     unsigned hit = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      const float4 t4 = *reinterpret_cast<const float4*>(&nth_l[s][4 * g]);
+      v4f acc = {rn + t4.x, rn + t4.y, rn + t4.z, rn + t4.w};
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s][c], bf[c], acc, 0, 0, 0);
+      for (int c = 0; c < NCC; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s][c], bf[c], acc, 0, 0, 0);
       // the four sign bytes into one word (bits 7, 15, 23, 31), then bits 8 r + s
       const unsigned lo = __builtin_amdgcn_perm(__float_as_uint(acc[1]), __float_as_uint(acc[0]), 0x0c0c0703u);
       const unsigned hi = __builtin_amdgcn_perm(__float_as_uint(acc[3]), __float_as_uint(acc[2]), 0x07030c0cu);
@@ -471,17 +475,33 @@ __global__ __launch_bounds__(64, 7) void k_knn_scan32(Knn2Args a) {
     }
     hit &= locmask;
     if (!valid) hit = 0;
-    if (!__builtin_expect(__any(hit), 0)) continue;
-    const int nh = __builtin_popcount(hit);
-    const int base = nh ? atomicAdd(&st_n, nh) : 0;
-    for (int k = 0; hit; ++k) {
-      const int b = __builtin_ctz(hit);  // b = 8 r + s: location 16 s + 4 g + r
-      hit &= hit - 1;
-      st_row[base + k] = (int32_t)rr;
-      st_q[base + k] = (uint8_t)(16 * (b & 7) + 4 * g + (b >> 3));
+    const uint64_t bal = __ballot(hit != 0);
+    if (!bal) return;
+    if (hit) {
+      const int pos = st_n + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      st_row[pos] = (int32_t)rr;
+      st_w[pos] = hit | ((uint32_t)g << 28);
     }
-    __syncthreads();
-    if (st_n > STG - 1024) flush();  // a tile stages at most 64 x 16
+    st_n += __builtin_popcountll(bal);
+    if (st_n > STG - 64) flush();
+  };
+#pragma unroll
+  for (int d = 0; d < SD; ++d)
+    if (i0 + 16 * d < i1) load_tile(i0 + 16 * d, xn[d], rnn[d]);
+  for (int64_t ib = i0; ib < i1; ib += 16 * SD) {
+#pragma unroll
+    for (int d = 0; d < SD; ++d) {  // (static register sets)
+      const int64_t i = ib + 16 * d;
+      if (i < i1) {
+        float xr[NCC];
+#pragma unroll
+        for (int c = 0; c < NCC; ++c) xr[c] = xn[d][c];
+        const double rr_n = rnn[d];
+        if (i + 16 * SD < i1) load_tile(i + 16 * SD, xn[d], rnn[d]);
+        scan_tile(i, xr, rr_n);
+      }
+    }
   }
   flush();
 }
@@ -787,25 +807,27 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   hipLaunchKernelGGL(k_knn_tau_reduce, dim3(a.M), dim3(64), 0, s, a, parts);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // scan: groups of 64 locations x slices of the design, about 21504 waves
-  // (three rounds of the FP32 scan's seven resident waves per SIMD; shorter
-  // slices hide the tail of the last round); the groups vary fastest, so the
-  // waves that read one slice run together and share it through L2
-  const int sgroups = (a.M + 63) / 64;
-  int64_t nsl = (21504 + sgroups - 1) / sgroups;
-  const int64_t maxsl = (a.N + 1023) / 1024;
-  if (nsl > maxsl) nsl = maxsl;
-  if (nsl < 1) nsl = 1;
-  a.slice = (a.N + nsl - 1) / nsl;
   // The FP32 screen when its slack (which grows with the squared norms) stays
   // under 5% of an estimate of the threshold (the squared radius holding
   // ncand of N points spread over the design's extent); designs far from the
   // origin relative to their extent keep the FP64 screen, whose slack is
   // 2^29 times smaller.  Either way the lists are exact.
-  constexpr int K32 = 4 * (((P > 0 ? P : LAGP_MAX_DIM) + 5) / 4);  // k_knn_scan32's product length
+  constexpr int K32 = 4 * (((P > 0 ? P : LAGP_MAX_DIM) + 3) / 4) + 4;  // k_knn_scan32's bound constant
   const double tau_est = a.spread2 * pow((double)a.ncand / (double)a.N, 2.0 / a.p);
   const double slack32 = 4.0 * (K32 + 4) * 0x1p-24 * (5.0 * a.rn_max + tau_est);
-  if (a.X32 && a.rn_max <= 1e30 && slack32 <= 0.05 * tau_est)
+  const bool fp32 = a.X32 && a.rn_max <= 1e30 && slack32 <= 0.05 * tau_est;
+  // scan: groups of 64 locations x slices of the design, three rounds of the
+  // scan's resident waves (shorter slices hide the tail of the last round);
+  // the groups vary fastest, so the waves that read one slice run together
+  // and share it through L2
+  const int sgroups = (a.M + 63) / 64;
+  const int64_t waves = fp32 ? 3 * 1024 * SCAN32_WAVES : 21504;  // (1024 SIMDs: 256 CUs of 4)
+  int64_t nsl = (waves + sgroups - 1) / sgroups;
+  const int64_t maxsl = (a.N + 1023) / 1024;
+  if (nsl > maxsl) nsl = maxsl;
+  if (nsl < 1) nsl = 1;
+  a.slice = (a.N + nsl - 1) / nsl;
+  if (fp32)
     hipLaunchKernelGGL(k_knn_scan32<P>, dim3(sgroups, (unsigned)((a.N + a.slice - 1) / a.slice)), dim3(64), 0, s, a);
   else
     hipLaunchKernelGGL(k_knn_scan<P>, dim3(sgroups, (unsigned)((a.N + a.slice - 1) / a.slice)), dim3(64), 0, s, a);
