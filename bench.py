@@ -37,12 +37,12 @@ KERNEL_SOURCES = {"k_chol": ("paper_1409_0074_amd/csrc/chol.hip",) + COMMON_SOUR
                   "k_local": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES,
                   "k_local_ray": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES}
 MEASURED_TRAFFIC = {
-    "k_chol": {"sha256": "90f68e64a67b830fe25bad194734f0049d86f8d6d010f28e7f6de3536294bc00",
-               "bytes": 2.2941e+09, "fetch_kib": 1119523.4, "write_kib": 1257.6},
-    "k_local": {"sha256": "e065fe3ed07a4915b189c60d7b7538fc2af04357bcc552cc9c1d85e415687cd0",
-                "bytes": 1.4055e+11, "fetch_kib": 66339872.9, "write_kib": 4578637.6},
-    "k_local_ray": {"sha256": "e065fe3ed07a4915b189c60d7b7538fc2af04357bcc552cc9c1d85e415687cd0",
-                    "bytes": 2.1848e+10, "fetch_kib": 10300592.9, "write_kib": 735077.7},
+    "k_chol": {"sha256": "e33583570e7db6089256086d368046d00b7833ca4c73692c84b1abc541b49eb1",
+               "bytes": 2.3424e+09, "fetch_kib": 1123171.1, "write_kib": 41193.2},
+    "k_local": {"sha256": "db2d851cdd60e3f201df2ae1a62761cf923de1d06e828dbd7a38b02df671c4de",
+                "bytes": 1.4057e+11, "fetch_kib": 66342990.1, "write_kib": 4578607.8},
+    "k_local_ray": {"sha256": "db2d851cdd60e3f201df2ae1a62761cf923de1d06e828dbd7a38b02df671c4de",
+                    "bytes": 2.1894e+10, "fetch_kib": 10319495.6, "write_kib": 735171.8},
 }
 
 
