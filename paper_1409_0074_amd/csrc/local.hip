@@ -417,8 +417,11 @@ __device__ __forceinline__ void load_tile_b(const LocalArgs& a, __amdgpu_buffer_
 
 // Exact ALC of one tile of 16 candidate columns (lane column cl holds
 // candidate `col`) at a design size j with NQ = ceil(j/4) K-chunks, from the
-// tile's candidate rows b; the value is valid in lanes 0..15.
-template <int NP, int NQ>
+// tile's candidate rows b; the value is valid in lanes 0..15.  PRE: a row
+// block's K_J^{-1} fragments are all loaded before its chain starts (one
+// tile per call: the chain then runs at the matrix cores' pace instead of
+// waiting on LDS every other step).
+template <int NP, int NQ, bool PRE = false>
 __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds& L, int LD, const double (&b)[NQ],
                                                    double kxcol, int* vflag) {
   const int lane = threadIdx.x & 63;
@@ -449,9 +452,18 @@ __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds
 #pragma unroll
   for (int I = 0; I < NFULL; ++I) {
     v4d acc = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (PRE) {
+      double af[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * I * LD + 4 * q], b[q], acc, 0, 0, 0);
+      for (int q = 0; q < NQ; ++q) af[q] = arow[16 * I * LD + 4 * q];
+      __builtin_amdgcn_sched_barrier(0);  // (the loads stay ahead of the chain)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[q], b[q], acc, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[16 * I * LD + 4 * q], b[q], acc, 0, 0, 0);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int q = 4 * I + r;
@@ -465,9 +477,18 @@ __device__ __forceinline__ double alc_tile_exact_q(const LocalArgs& a, const Lds
 #pragma unroll
   for (int qr = 4 * NFULL; qr < NQ; ++qr) {
     double w4 = 0.0;
+    if constexpr (PRE) {
+      double af[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      w4 = __builtin_amdgcn_mfma_f64_4x4x4f64(a4[4 * qr * LD + 4 * q], b[q], w4, 0, 0, 0);
+      for (int q = 0; q < NQ; ++q) af[q] = a4[4 * qr * LD + 4 * q];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) w4 = __builtin_amdgcn_mfma_f64_4x4x4f64(af[q], b[q], w4, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        w4 = __builtin_amdgcn_mfma_f64_4x4x4f64(a4[4 * qr * LD + 4 * q], b[q], w4, 0, 0, 0);
+    }
     accv = __builtin_amdgcn_mfma_f64_4x4x4f64(b[qr], w4, accv, 0, 0, 0);
     accc = __builtin_amdgcn_mfma_f64_4x4x4f64(L.kx[4 * qr + g4], w4, accc, 0, 0, 0);
   }
@@ -1002,7 +1023,11 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, int nl, bool l
   double x = lo + gold * (hi - lo);
   double w = x, v = x;
   bool run = live && lane < nl;
-  const double f0 = eval(x, run);
+  double f0;
+  if constexpr (BLOCK)
+    f0 = eval(x, run, nullptr);  // (the first evaluation runs whatever the lanes hold)
+  else
+    f0 = eval(x, run);
   double fx = -f0, fw = fx, fv = fx;
   double step = 0.0, prev = 0.0;
   int it = 0;
@@ -1041,9 +1066,18 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, int nl, bool l
         ev = true;
       }
     }
-    // (BLOCK: the evaluations span the workgroup, so every wave leaves together)
-    if (BLOCK ? !__syncthreads_or(ev) : !__any(ev)) break;
-    const double fu = -eval(u, ev);
+    // (BLOCK: the evaluations span the workgroup, so every wave leaves
+    // together: the evaluation's first barrier also carries whether any lane
+    // evaluates, and it returns at once when none does)
+    double fu;
+    if constexpr (BLOCK) {
+      bool go = true;
+      fu = -eval(u, ev, &go);
+      if (!go) break;
+    } else {
+      if (!__any(ev)) break;
+      fu = -eval(u, ev);
+    }
     if (ev) {
       ++it;
       if (fu <= fx) {
@@ -1068,20 +1102,29 @@ __device__ __forceinline__ double brent_lanes(const LocalArgs& a, int nl, bool l
 }
 
 // Round-robin starts of a ray step (Sec. 4): the R remaining candidates from
-// rank k0 = t mod floor(sqrt t) on, t = j - n0 + 1.  Leaves their number in
-// L.ints[2] (fewer than R only when the list runs out).
+// rank k0 = t mod floor(sqrt t) on, t = j - n0 + 1, i.e. the available ranks
+// numbered k0 .. k0 + R - 1 among the available ones in rank order.  Wave 0
+// numbers 64 ranks at a time by a ballot.  Leaves their number in L.ints[2]
+// (fewer than R only when the list runs out).
 __device__ __forceinline__ int ray_starts(const LocalArgs& a, const Lds& L, int j, int n0) {
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
     const int t = j - n0 + 1;
     int rt = 0;
     while ((rt + 1) * (rt + 1) <= t) ++rt;
     const int k0 = rt > 0 ? t % rt : 0;
-    int seen = 0, got = 0;
-    for (int c = 0; c < a.ncand && got < a.numrays; ++c) {
-      if (L.selm[c]) continue;
-      if (seen++ >= k0) L.starts[got++] = c;
+    int seen = 0;  // available ranks below c0 (uniform)
+    for (int c0 = 0; c0 < a.ncand && seen < k0 + a.numrays; c0 += 64) {
+      const int c = c0 + lane;
+      const bool av = c < a.ncand && !L.selm[c];
+      const uint64_t bal = __ballot(av);
+      const int num = seen + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      if (av && num >= k0 && num < k0 + a.numrays) L.starts[num - k0] = c;
+      seen += __builtin_popcountll(bal);
     }
-    L.ints[2] = got;
+    const int got = seen - k0 < 0 ? 0 : (seen - k0 < a.numrays ? seen - k0 : a.numrays);
+    if (lane == 0) L.ints[2] = got;
   }
   __syncthreads();
   return L.ints[2];
@@ -1090,11 +1133,13 @@ __device__ __forceinline__ int ray_starts(const LocalArgs& a, const Lds& L, int 
 // Segment of ray r (Sec. 4): from its start a, away from x, ten times
 // |a - x| long, cut at the design's bounding box; returns the cut fraction
 // tau, and writes a and the clipped direction to L.ra, L.rdir when `write`.
+// The start's coordinates come from the location's gathered candidate
+// coordinates Xc (the same values as its design row).
 template <int P>
-__device__ __forceinline__ double ray_segment(const LocalArgs& a, const Lds& L, const int32_t* C, int r, bool write) {
+__device__ __forceinline__ double ray_segment(const LocalArgs& a, const Lds& L, const double* Xc, int r, bool write) {
   constexpr int PM = P > 0 ? P : LAGP_MAX_DIM;
   const int p = a.p;
-  const double* src = a.X + (int64_t)C[L.starts[r]] * p;
+  const double* src = Xc + (int64_t)L.starts[r] * p;
   double ak[PM], dk[PM];
   double tt = 1.0;
 #pragma unroll
@@ -1358,7 +1403,7 @@ __device__ __forceinline__ int ray_step(const LocalArgs& a, const Lds& L, int LD
         continue;
       }
       // (every lane computes the same values; lane 0 writes them)
-      tau[t] = ray_segment<P>(a, L, C, rid[t], lane == 0);
+      tau[t] = ray_segment<P>(a, L, Xc, rid[t], lane == 0);
     }
     wave_sync();
     // slot t on lane t from here on
@@ -1498,14 +1543,16 @@ __device__ __forceinline__ double ray_tile_q(const LocalArgs& a, const Lds& L, i
   double b[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) b[q] = kcol[64 * q + lane];
-  return alc_tile_exact_q<NP, NQ>(a, L, LD, b, kxcol, vflag);
+  return alc_tile_exact_q<NP, NQ, true>(a, L, LD, b, kxcol, vflag);
 }
 
 // The objective at every evaluated ray's point, as one tile of the exact
 // scoring: lane t < R receives ray t's value (0 if it is not evaluated).
+// With `go`: *go = whether any ray is evaluated (the rays live on wave 0),
+// and nothing else is done when none is.
 template <int NP, int P>
 __device__ __forceinline__ double ray_tile(const LocalArgs& a, const Lds& L, int LD, int j, int R, double s, bool ev,
-                                           bool at_start, int* vflag) {
+                                           bool at_start, int* vflag, bool* go = nullptr) {
   const int tid = threadIdx.x;
   const int nq = (j + 3) >> 2;
   double* kcol = L.kzb;
@@ -1513,7 +1560,15 @@ __device__ __forceinline__ double ray_tile(const LocalArgs& a, const Lds& L, int
     L.tps[tid] = s;
     L.tpe[tid] = ev ? 1 : 0;
   }
+  if (go && tid < 64) {
+    const bool any = __any(ev);
+    if (tid == 0) L.ints[10] = any ? 1 : 0;
+  }
   __syncthreads();
+  if (go) {
+    *go = L.ints[10] != 0;
+    if (!*go) return 0.0;
+  }
   const double kxcol = ray_columns<P>(a, L, j, nq, R, at_start, kcol);
   __syncthreads();
   double out = 0.0;
@@ -1536,13 +1591,13 @@ __device__ __forceinline__ int ray_step_tile(const LocalArgs& a, const Lds& L, i
   const int lane = threadIdx.x;  // (rays live on the lanes of wave 0)
   const int ns = ray_starts(a, L, j, n0);
   const bool valid = lane < ns;
-  const double tau = valid ? ray_segment<P>(a, L, C, lane, true) : 0.0;
+  const double tau = valid ? ray_segment<P>(a, L, Xc, lane, true) : 0.0;
   __syncthreads();
   const double a0 = ray_tile<NP, P>(a, L, LD, j, ns, 0.0, valid, true, vflag);
   const bool live = valid && tau > 0.0;
   double fb = 0.0;
   int nev = 0;
-  const auto eval = [&](double s, bool e) { return ray_tile<NP, P>(a, L, LD, j, ns, s, e, false, vflag); };
+  const auto eval = [&](double s, bool e, bool* go) { return ray_tile<NP, P>(a, L, LD, j, ns, s, e, false, vflag, go); };
   const double xb = brent_lanes<true>(a, ns, live, eval, &fb, &nev);
   if (valid) {
     L.rev[lane] = nev;
