@@ -678,9 +678,10 @@ def main() -> int:
                                  f"locations per launch"}}
 
     if not args.no_ray:
-        # the same rays snapping over the whole design (Sec. 5): the candidate
-        # lists hold only the starts' ranks; the snap searches the design's grid
-        ncr = W.ray_candidates_needed(prm.n, prm.n0, R)
+        # the same rays snapping over the whole design (Sec. 5): the results
+        # do not depend on the list length (at least the starts' ranks); the
+        # 1000-nearest lists settle most snaps without the design's grid
+        ncr = max(W.ray_candidates_needed(prm.n, prm.n0, R), prm.ncand)
         Pf = lg.make_params(prm, search=W.SEARCH_RAY, numrays=R, ncand=ncr, snap=W.SNAP_DESIGN)
         candr = torch.empty((M, ncr), dtype=torch.int32, device=dev)
         selr = torch.empty((M, prm.n), dtype=torch.int32, device=dev)

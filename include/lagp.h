@@ -210,7 +210,9 @@ int32_t lagp_predict(const lagp_design* design, const double* XX, int64_t M, con
 
 /* Local GP prediction from candidate lists already on the device, as
  * lagp_candidates writes them: cand_idx (M x params->ncand int32, nearest
- * first).  Everything else as lagp_predict.  Lets a caller keep candidate
+ * first; with LAGP_SNAP_DESIGN the lists must be exactly the ncand nearest
+ * rows, as the whole-design snap relies on every other row lying at least
+ * as far from x as the list's last).  Everything else as lagp_predict.  Lets a caller keep candidate
  * lists resident and re-run the design search (another n, search mode or
  * precision) without repeating the neighbour search. */
 int32_t lagp_predict_candidates(const lagp_design* design, const double* XX, int64_t M, const int32_t* cand_idx,

@@ -1329,15 +1329,9 @@ __device__ __forceinline__ int ray_finish(const LocalArgs& a, const Lds& L, cons
   if (sw == 0.0) return L.starts[br];
   const double* ar = L.ra + br * p;
   const double* dr = L.rdir + br * p;
-  if (a.snap_full) {
-    double zf[LAGP_MAX_DIM];
-#pragma unroll
-    for (int k = 0; k < LAGP_MAX_DIM; ++k) zf[k] = k < p ? __builtin_fma(sw, dr[k], ar[k]) : 0.0;
-    return snap_design(a, L, C, zf, j, ns);
-  }
   // snap z* = a + s* dir to the nearest candidate outside J and the starts
   // (the starts are flagged unavailable for the scan, 2 = start, and
-  // released after it)
+  // released after it); over the whole design, the same scan first
   for (int r = tid; r < ns; r += blockDim.x) L.selm[L.starts[r]] = 2;
   __syncthreads();
   double zs[PM];
@@ -1372,7 +1366,34 @@ __device__ __forceinline__ int ray_finish(const LocalArgs& a, const Lds& L, cons
   block_best(L, nb);  // (its barriers order the scan before the release)
   for (int r = tid; r < ns; r += blockDim.x) L.selm[L.starts[r]] = 0;
   __syncthreads();
-  return L.ints[0];
+  if (!a.snap_full) return L.ints[0];
+  // Whole design.  The list holds the ncand nearest rows to x (as the
+  // candidate search writes them), so a row outside it lies at least
+  // R = |x_last - x| from x and at least R - |z* - x| from z*: when that
+  // exceeds the best candidate's distance delta (with a 2^-40 relative
+  // margin for the roundings of the three distances), no other row can be
+  // nearer or tie, and the candidate is the design's nearest allowed row
+  // (equal distances among candidates already go to the lower rank, nearer
+  // to x).  Otherwise the design's cell grid is searched.
+  {
+    const double* xl = Xc + (int64_t)(a.ncand - 1) * p;
+    double r2 = 0.0, q2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < PM; ++k)
+      if (P > 0 || k < p) {
+        const double t = xl[k] - L.x[k], u = zs[k] - L.x[k];
+        r2 = __builtin_fma(t, t, r2);
+        q2 = __builtin_fma(u, u, q2);
+      }
+    const double d2 = -L.scal[1];  // (+inf when no candidate is available)
+    const double e = 0x1p-40;
+    if (__builtin_sqrt(r2) * (1.0 - e) - __builtin_sqrt(q2) * (1.0 + e) > __builtin_sqrt(d2) * (1.0 + e))
+      return L.ints[0];
+  }
+  double zf[LAGP_MAX_DIM];
+#pragma unroll
+  for (int k = 0; k < LAGP_MAX_DIM; ++k) zf[k] = k < p ? __builtin_fma(sw, dr[k], ar[k]) : 0.0;
+  return snap_design(a, L, C, zf, j, ns);
 }
 
 // One ray-search step at design size j: returns the chosen candidate rank,

@@ -117,6 +117,22 @@ def test_shapes(lg, p, R, n, N):
     _same(g, oracle.predict(w.X, w.y, w.XX, prm), f"p={p} R={R} n={n}")
 
 
+@pytest.mark.parametrize("p,R,n,N,ncand", [
+    (8, 10, 50, 20000, 1000),  # the benchmark's shape: most snaps settled by the candidate list
+    (2, 2, 40, 6000, 600),     # a dense 2-d design
+    (4, 4, 60, 10000, 300),    # a shorter list: more snaps fall through to the grid
+])
+def test_long_lists_settle_snaps_exactly(lg, p, R, n, N, ncand):
+    """With a long candidate list most snap targets lie so close to x that no
+    row outside the list can be nearer than the best candidate; those snaps
+    are settled by the list, the others by the grid: the same designs and
+    predictions as the oracle's search over the whole design."""
+    w = _uniform(940 + p, N, p, 6, n0=6, n=n, search=W.SEARCH_RAY, numrays=R, d=(0.1 * p,), g=1e-6)
+    prm = w.params.replace(ncand=ncand, snap=FULL)
+    g = _run(lg, w, prm)
+    _same(g, oracle.predict(w.X, w.y, w.XX, prm), f"p={p} ncand={ncand}")
+
+
 def test_four_wave_form(lg, monkeypatch):
     """LAGP_RAY_FORCE_WAVES=1 keeps the four-wave ray form: the same results."""
     monkeypatch.setenv("LAGP_RAY_FORCE_WAVES", "1")
