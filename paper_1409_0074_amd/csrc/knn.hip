@@ -821,7 +821,11 @@ static hipError_t launch_knn2_p(Knn2Args a, hipStream_t s) {
   // the groups vary fastest, so the waves that read one slice run together
   // and share it through L2
   const int sgroups = (a.M + 63) / 64;
-  const int64_t waves = fp32 ? 3 * 1024 * SCAN32_WAVES : 21504;  // (1024 SIMDs: 256 CUs of 4)
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cus < 1)
+    cus = 256;
+  const int64_t waves = (int64_t)3 * 4 * cus * (fp32 ? SCAN32_WAVES : 7);  // (4 SIMDs per CU)
   int64_t nsl = (waves + sgroups - 1) / sgroups;
   const int64_t maxsl = (a.N + 1023) / 1024;
   if (nsl > maxsl) nsl = maxsl;
