@@ -1506,10 +1506,12 @@ __device__ __forceinline__ double corr_regs_bf(const double* u, const double* v,
 
 // Kernel columns of the round's ray points into the B layout in LDS: lane
 // 16k + t writes K(x_{4q+k}, z_t) to kcol[64 q + lane] for q < nq (zero past
-// j, or when ray t is not evaluated), and returns K(z_t, x) (zero likewise).
-// Four chunks at a time, every lane alike (rows past j read a valid row and
-// are masked after), their exps in lockstep: the arithmetic of corr() per
-// value (ISO: the isotropic form).
+// j, or when ray t is not evaluated), and returns K(z_t, x) in wave 0 (zero
+// likewise).  Groups of four chunks go to the waves round robin, every lane
+// alike (rows past j read a valid row and are masked after), their exps in
+// lockstep; K(z, x) rides along as a fifth exp of wave 0's first group.  The
+// arithmetic of corr() per value (ISO: the isotropic form; x - z squares to
+// the same value as z - x).
 template <int P, bool ISO>
 __device__ __forceinline__ double ray_columns_t(const LocalArgs& a, const Lds& L, int j, int nq, bool et,
                                                 const double* z, double* kcol) {
@@ -1517,29 +1519,49 @@ __device__ __forceinline__ double ray_columns_t(const LocalArgs& a, const Lds& L
   const int lane = threadIdx.x & 63;
   const int g4 = lane >> 4;
   const int p = a.p;
-  const int wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-  const double kx = wv == 0 ? corr_regs_bf<P>(z, L.x, p, L.w0, a.w, a.dlen) : 0.0;  // (wave 0 scores)
-  for (int q0 = 4 * wv; q0 < nq; q0 += 4 * nwv) {  // groups of four chunks, round robin over the waves
-    double e[4];
+  // (the wave index as a scalar: the branches below are whole-wave)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nwv = blockDim.x >> 6;
+  auto d2 = [&](const double* xi) {
+    double acc = 0.0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = 4 * (q0 + u) + g4;
-      const double* xi = L.xj + (i < j ? i : 0) * p;
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < PM; ++k)
-        if (P > 0 || k < p) {
-          const double t = xi[k] - z[k];
-          acc = ISO ? __builtin_fma(t, t, acc) : __builtin_fma(t * t, a.w[k], acc);
-        }
-      e[u] = ISO ? -(acc * L.w0) : -acc;
-    }
-    gexp4(e);
+    for (int k = 0; k < PM; ++k)
+      if (P > 0 || k < p) {
+        const double t = xi[k] - z[k];
+        acc = ISO ? __builtin_fma(t, t, acc) : __builtin_fma(t * t, a.w[k], acc);
+      }
+    return ISO ? -(acc * L.w0) : -acc;
+  };
+  auto store = [&](int q0, const double* e) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {  // (kcol holds whole groups of four chunks)
       const int i = 4 * (q0 + u) + g4;
       kcol[64 * (q0 + u) + lane] = (et && i < j) ? e[u] : 0.0;
     }
+  };
+  double kx = 0.0;
+  int q0 = 4 * wv;
+  if (wv == 0) {  // (wave 0 always has a group: nq >= 1)
+    double e[5];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = 4 * u + g4;
+      e[u] = d2(L.xj + (i < j ? i : 0) * p);
+    }
+    e[4] = d2(L.x);
+    gexp_lockstep<5>(e);
+    store(0, e);
+    kx = e[4];
+    q0 += 4 * nwv;
+  }
+  for (; q0 < nq; q0 += 4 * nwv) {
+    double e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = 4 * (q0 + u) + g4;
+      e[u] = d2(L.xj + (i < j ? i : 0) * p);
+    }
+    gexp4(e);
+    store(q0, e);
   }
   return et ? kx : 0.0;
 }
