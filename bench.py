@@ -38,11 +38,11 @@ KERNEL_SOURCES = {"k_chol": ("paper_1409_0074_amd/csrc/chol.hip",) + COMMON_SOUR
                   "k_local_ray": ("paper_1409_0074_amd/csrc/local.hip",) + COMMON_SOURCES}
 MEASURED_TRAFFIC = {
     "k_chol": {"sha256": "e33583570e7db6089256086d368046d00b7833ca4c73692c84b1abc541b49eb1",
-               "bytes": 2.3424e+09, "fetch_kib": 1123171.1, "write_kib": 41193.2},
-    "k_local": {"sha256": "db2d851cdd60e3f201df2ae1a62761cf923de1d06e828dbd7a38b02df671c4de",
-                "bytes": 1.4057e+11, "fetch_kib": 66342990.1, "write_kib": 4578607.8},
-    "k_local_ray": {"sha256": "db2d851cdd60e3f201df2ae1a62761cf923de1d06e828dbd7a38b02df671c4de",
-                    "bytes": 2.1894e+10, "fetch_kib": 10319495.6, "write_kib": 735171.8},
+               "bytes": 2.3422e+09, "fetch_kib": 1123071.4, "write_kib": 41193.2},
+    "k_local": {"sha256": "d0b3810627f7f6e1fbfd78f97dedb74acc1a5a6c53d83bc9925e45781f9b34f4",
+                "bytes": 1.4054e+11, "fetch_kib": 66332140.9, "write_kib": 4578604.7},
+    "k_local_ray": {"sha256": "d0b3810627f7f6e1fbfd78f97dedb74acc1a5a6c53d83bc9925e45781f9b34f4",
+                    "bytes": 2.1522e+10, "fetch_kib": 10141631.9, "write_kib": 734717.2},
 }
 
 
