@@ -67,6 +67,20 @@ def test_candidates_bit_exact(lg, case):
     assert np.array_equal(gd, od)
 
 
+@pytest.mark.parametrize("p", [1, 6, 7, 12, 16])
+def test_candidates_every_chunk_count(lg, p):
+    """The FP32 screen's product runs over ceil(p/4) K-chunks of coordinates
+    (the row norm and the threshold enter as its start value): dimensions
+    with one to four chunks, padded (p = 1, 6, 7) and whole (12, 16)."""
+    rng = np.random.default_rng(150 + p)
+    X, XX = rng.random((6000, p)), rng.random((70, p))  # 70 locations: two groups of 64, one ragged
+    nc = 300
+    idx, d2 = _cands(lg, X, X[:, 0].copy(), XX, nc)
+    oi, od = oracle.knn(X, XX, nc)
+    assert np.array_equal(idx.astype(np.int64), oi)
+    assert np.array_equal(d2, od)
+
+
 @pytest.mark.parametrize("case", ["uniform8d", "grid_ties"])
 def test_candidates_forced_fallback_bit_exact(lg, case, monkeypatch):
     """The exact fallback scan (taken when the sampled threshold catches too
